@@ -1,0 +1,382 @@
+"""The discrete lattice-Boltzmann map of the paper, written plainly (test infrastructure only).
+
+One time step, Section 3 of the paper, in this order:
+
+  pass 1, every node (Eqs. Moment0_c_alpha, Moment0_Phi, PotChem, SourceTerm_Phi)
+      c^alpha = sum_k h_k^alpha
+      phi*    = sum_k g_k
+      phi     = phi* + S(phi*, mu(c, phi*)) / 2          (one predictor step, see below)
+      mu      = mu(c, phi),   S = S(phi, mu)
+  pass 2, every node, flow only (Eqs. DerivDirec_Grad ... Laplacian, SurfaceTension_Force,
+      HydroPressure, Velocity)
+      grad phi, lap phi on the fluid lattice from the pass-1 phi field
+      F   = (phi - phi_ref) drho g + (3/2) sigma W [omega_dw'(phi)/W^2 - lap phi] grad phi
+      p_h = sum_k f_k,   rho0 u = (1/c_s^2) sum_k f_k e_k + F/2
+  collision (Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq, LBE_Phi, Geq,
+      Source_LBE_Phi, LBE_c_alpha, Heq), BGK with rate 1/(tau + 1/2) and D = tau c_s^2
+  streaming: X_k(x + e_k) <- X*_k(x); across a wall the population returns to its own
+      node in the opposite direction (half-way bounce-back, Section 4.2.4).
+
+Readings of points the paper leaves open (each is also a field of ``Params``):
+  * phi = sum g + S/2 is implicit in phi (S depends on phi).  It is resolved by one
+    predictor step: S is first evaluated at phi* = sum g, then at the corrected phi.
+  * All moments of step n come from the populations of step n; nothing is lagged.
+  * The grad/Laplacian stencil always uses the fluid lattice (D2Q9 in 2D, D3Q19 in 3D)
+    with the factor 3 = 1/c_s^2 of that lattice; walls use mirror ghosts
+    phi(-1) = phi(0), phi(N) = phi(N-1) (zero normal gradient at a half-way wall).
+  * nu(phi) is interpolated linearly (see ``model.viscosity``).
+  * The gravity force uses (phi - phi_ref) drho g.  phi_ref = 0 (the paper's form)
+    unless ``gravity_mean_subtract`` is set, for fully periodic boxes, where
+    phi_ref is the domain mean of phi of the previous step (of phi_0 at step 0).
+  * The scalar lattices D2Q5 / D3Q7 use their own c_s^2 (1/3, 1/4) in the rates and
+    in the c_k.u / c_s^2 terms of g^eq and h^eq.
+
+Arrays are indexed [k][z][y][x] (2D grids have nz = 1).
+"""
+
+from dataclasses import dataclass, field, replace
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import model
+from .lattices import BY_NAME, D2Q9, D3Q19
+
+
+@dataclass
+class Params:
+    nx: int
+    ny: int
+    nz: int = 1
+    fluid: Optional[str] = None          # None, "D2Q9" or "D3Q19"
+    scalar: str = "D2Q5"                 # "D2Q5" or "D3Q7"
+    bc: Tuple[str, str, str] = ("periodic", "periodic", "periodic")   # per axis x, y, z
+    W: float = 4.0
+    lam: float = 1.0
+    M_phi: float = 0.1
+    M_A: Tuple[float, float] = (0.1, 0.1)      # (phase 0, phase 1)
+    M_B: Tuple[float, float] = (0.1, 0.1)
+    c_eq: Tuple[Tuple[float, float], Tuple[float, float]] = ((0.2, 0.1), (0.6, 0.3))  # [phase][A, B]
+    rho0: float = 1.0
+    drho: float = 0.0
+    g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    sigma: float = 0.0
+    nu: Tuple[float, float] = (0.1, 0.1)       # (phase 0, phase 1)
+    gravity_mean_subtract: bool = False
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def dim(self):
+        return BY_NAME[self.scalar].dim
+
+    @property
+    def slat(self):
+        return BY_NAME[self.scalar]
+
+    @property
+    def flat(self):
+        return BY_NAME[self.fluid] if self.fluid else None
+
+    @property
+    def stencil_lattice(self):
+        return D2Q9 if self.dim == 2 else D3Q19
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+@dataclass
+class State:
+    g: np.ndarray                 # [Qs][z][y][x]
+    hA: np.ndarray
+    hB: np.ndarray
+    f: Optional[np.ndarray] = None  # [Qf][z][y][x] or None without flow
+    phi_ref: complex = 0.0
+    step: int = 0
+
+    def copy(self):
+        return State(self.g.copy(), self.hA.copy(), self.hB.copy(),
+                     None if self.f is None else self.f.copy(), self.phi_ref, self.step)
+
+
+# ----------------------------------------------------------------------------------------
+# neighbour access and streaming
+
+def _padded(field, bc):
+    """Pad a [z][y][x] field by one node per side: periodic axes wrap, wall axes repeat
+    the edge value (mirror ghost of a half-way wall)."""
+    out = field
+    for ax, b in ((0, bc[2]), (1, bc[1]), (2, bc[0])):
+        pw = [(0, 0)] * 3
+        pw[ax] = (1, 1)
+        out = np.pad(out, pw, mode="wrap" if b == "periodic" else "edge")
+    return out
+
+
+def neighbour(field, e, bc):
+    """Value of ``field`` at x + e for every node x (|e_i| <= 1)."""
+    P = _padded(field, bc)
+    nz, ny, nx = field.shape
+    ex, ey, ez = (int(v) for v in e)
+    return P[1 + ez:1 + ez + nz, 1 + ey:1 + ey + ny, 1 + ex:1 + ex + nx]
+
+
+def _outside_mask(shape, e, bc):
+    """True where x - e lies outside the domain across a wall axis."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros(shape, dtype=bool)
+    for coord, n, comp, b in ((x, nx, e[0], bc[0]), (y, ny, e[1], bc[1]), (z, nz, e[2], bc[2])):
+        if b == "walls" and comp != 0:
+            src = coord - comp
+            out |= (src < 0) | (src >= n)
+    return out
+
+
+def stream(post, lat, bc):
+    """Streaming of post-collision populations ``post[k]`` (LBE left-hand sides):
+    X_k(x) = X*_k(x - e_k) when x - e_k is inside the domain (periodic axes wrap),
+    otherwise X*_opp(k)(x): the population that left x towards the wall comes back
+    reversed (half-way bounce-back with a wall at rest)."""
+    new = np.empty_like(post)
+    for k in range(lat.Q):
+        e = lat.e[k]
+        rolled = np.roll(post[k], shift=(int(e[2]), int(e[1]), int(e[0])), axis=(0, 1, 2))
+        mask = _outside_mask(post.shape[1:], e, bc)
+        new[k] = np.where(mask, post[lat.opp[k]], rolled)
+    return new
+
+
+# ----------------------------------------------------------------------------------------
+# finite-difference stencils of Section 3.1
+
+def gradient(phi, bc, lat):
+    """Isotropic gradient, Eqs. DerivDirec_Grad and Grad:
+    e_k . grad phi = [phi(x + e_k) - phi(x - e_k)] / 2,
+    grad phi = 3 sum_k w_k e_k (e_k . grad phi)."""
+    grad = [np.zeros_like(phi) for _ in range(3)]
+    for k in range(lat.Q):
+        e = lat.e[k]
+        d = 0.5 * (neighbour(phi, e, bc) - neighbour(phi, -e, bc))
+        for a in range(3):
+            if e[a] != 0:
+                grad[a] = grad[a] + 3.0 * lat.w[k] * e[a] * d
+    return grad
+
+
+def laplacian(phi, bc, lat):
+    """Isotropic Laplacian, Eqs. DerivDirect_Laplacian and Laplacian:
+    lap phi = 3 sum_{k != 0} w_k [phi(x + e_k) - 2 phi(x) + phi(x - e_k)]."""
+    lap = np.zeros_like(phi)
+    for k in range(1, lat.Q):
+        e = lat.e[k]
+        lap = lap + 3.0 * lat.w[k] * (neighbour(phi, e, bc) - 2.0 * phi + neighbour(phi, -e, bc))
+    return lap
+
+
+# ----------------------------------------------------------------------------------------
+# equilibria and forcing of Section 3
+
+def _edot(e, vec):
+    return e[0] * vec[0] + e[1] * vec[1] + e[2] * vec[2]
+
+
+def gamma_k(lat, k, u):
+    """Eq. GammaFunction."""
+    eu = _edot(lat.e[k], u)
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    cs2 = lat.cs2
+    return lat.w[k] * (1.0 + eu / cs2 + eu * eu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2))
+
+
+def forcing_k(lat, k, u, F):
+    """He-Shan-Doolen forcing population, Eq. ForcingTerm: F_k = Gamma_k (c_k - u) . F."""
+    e = lat.e[k]
+    return gamma_k(lat, k, u) * ((e[0] - u[0]) * F[0] + (e[1] - u[1]) * F[1] + (e[2] - u[2]) * F[2])
+
+
+def f_equilibrium_k(lat, k, p_h, u, rho0, Fk):
+    """He-Luo incompressible equilibrium with the forcing shift, Eq. Feq."""
+    eu = _edot(lat.e[k], u)
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    cs2 = lat.cs2
+    return lat.w[k] * (p_h + rho0 * cs2 * (eu / cs2 + eu * eu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2))) - 0.5 * Fk
+
+
+def g_equilibrium_k(lat, k, phi, u, Gk):
+    """Phase-field equilibrium, Eq. Geq: w_k phi (1 + c_k.u / c_s^2) - G_k / 2."""
+    return lat.w[k] * phi * (1.0 + _edot(lat.e[k], u) / lat.cs2) - 0.5 * Gk
+
+
+def h_equilibrium_k(lat, k, c, mu, u):
+    """Composition equilibrium, Eq. Heq: c - (1 - w_0) mu for k = 0,
+    w_k mu + w_k c (c_k.u) / c_s^2 otherwise."""
+    if k == 0:
+        return c - (1.0 - lat.w[0]) * mu
+    return lat.w[k] * mu + lat.w[k] * c * _edot(lat.e[k], u) / lat.cs2
+
+
+def rate(D, cs2):
+    """BGK rate 1/(tau + 1/2) with the transport coefficient D = tau c_s^2 (delta t = 1)."""
+    return 1.0 / (D / cs2 + 0.5)
+
+
+# ----------------------------------------------------------------------------------------
+# moments
+
+def scalar_moments(st, prm):
+    """Pass 1: compositions, phase field (with the predictor), potentials and source."""
+    cA = st.hA.sum(axis=0)                               # Eq. Moment0_c_alpha
+    cB = st.hB.sum(axis=0)
+    phi_star = st.g.sum(axis=0)                          # sum_k g_k
+    mu_star = model.closure_mu((cA, cB), phi_star, prm.c_eq)
+    S_star = model.source_phi(phi_star, mu_star, prm)
+    phi = phi_star + 0.5 * S_star                        # Eq. Moment0_Phi (predictor)
+    mu = model.closure_mu((cA, cB), phi, prm.c_eq)       # Eq. PotChem
+    S = model.source_phi(phi, mu, prm)                   # Eq. SourceTerm_Phi
+    return dict(phi=phi, phi_star=phi_star, cA=cA, cB=cB, muA=mu[0], muB=mu[1], S=S)
+
+
+def force(phi, prm, phi_ref):
+    """Total force of Eq. QDM: buoyancy plus capillary force Eq. SurfaceTension_Force."""
+    lat = prm.stencil_lattice
+    grad = gradient(phi, prm.bc, lat)
+    lap = laplacian(phi, prm.bc, lat)
+    bracket = model.domega_dw(phi) / prm.W ** 2 - lap
+    cap = 1.5 * prm.sigma * prm.W
+    return [(phi - phi_ref) * prm.drho * prm.g[a] + cap * bracket * grad[a] for a in range(3)]
+
+
+def flow_moments(f, F, prm):
+    """Eqs. HydroPressure and Velocity."""
+    lat = prm.flat
+    p_h = f.sum(axis=0)
+    u = []
+    for a in range(3):
+        m = np.zeros_like(p_h)
+        for k in range(lat.Q):
+            if lat.e[k][a] != 0:
+                m = m + f[k] * lat.e[k][a]
+        u.append((m / lat.cs2 + 0.5 * F[a]) / prm.rho0)
+    return p_h, u
+
+
+def moments(st, prm):
+    """All macroscopic fields of the current state: phi, c, mu, S, p_h, u, F."""
+    m = scalar_moments(st, prm)
+    zero = np.zeros_like(m["phi"])
+    if prm.fluid:
+        F = force(m["phi"], prm, st.phi_ref)
+        p_h, u = flow_moments(st.f, F, prm)
+    else:
+        F = [zero, zero, zero]
+        p_h, u = zero, [zero, zero, zero]
+    m.update(p=p_h, ux=u[0], uy=u[1], uz=u[2], F=F)
+    return m
+
+
+# ----------------------------------------------------------------------------------------
+# init and step
+
+def init(phi0, muA0, muB0, prm):
+    """Populations at rest from (phi_0, mu_0), with u = 0 and p_h = 0 (Section 4.2.1):
+    c from the closure Eq. species_closure, every population set to its equilibrium
+    including the -G_k/2 and -F_k/2 shifts, so that the moments of Eqs. Moment0_Phi
+    and Velocity give back phi_0 + O(S) and u = 0."""
+    phi0 = np.asarray(phi0)
+    shape = prm.shape
+    phi0 = phi0.reshape(shape)
+    mu0 = (np.asarray(muA0).reshape(shape), np.asarray(muB0).reshape(shape))
+    c = model.closure_c(mu0, phi0, prm.c_eq)
+    S0 = model.source_phi(phi0, mu0, prm)
+    zero = np.zeros_like(phi0 * S0)
+    u0 = [zero, zero, zero]
+    slat = prm.slat
+    g = np.stack([g_equilibrium_k(slat, k, phi0, u0, slat.w[k] * S0) for k in range(slat.Q)])
+    hA = np.stack([h_equilibrium_k(slat, k, c[0], mu0[0], u0) + zero for k in range(slat.Q)])
+    hB = np.stack([h_equilibrium_k(slat, k, c[1], mu0[1], u0) + zero for k in range(slat.Q)])
+    phi_ref = phi0.mean() if prm.gravity_mean_subtract else 0.0
+    f = None
+    if prm.fluid:
+        flat = prm.flat
+        F0 = force(phi0, prm, phi_ref)
+        f = np.stack([f_equilibrium_k(flat, k, zero, u0, prm.rho0, forcing_k(flat, k, u0, F0))
+                      for k in range(flat.Q)])
+    return State(g=g, hA=hA, hB=hB, f=f, phi_ref=phi_ref, step=0)
+
+
+def step(st, prm):
+    """One time step P^n -> P^(n+1) (see the module docstring for the order)."""
+    slat = prm.slat
+    m = scalar_moments(st, prm)
+    phi, S = m["phi"], m["S"]
+    zero = np.zeros_like(phi)
+    if prm.fluid:
+        flat = prm.flat
+        F = force(phi, prm, st.phi_ref)
+        p_h, u = flow_moments(st.f, F, prm)
+    else:
+        u = [zero, zero, zero]
+
+    # g: Eqs. LBE_Phi, Geq, Source_LBE_Phi
+    wg = rate(prm.M_phi, slat.cs2)
+    g_post = np.stack([st.g[k] - wg * (st.g[k] - g_equilibrium_k(slat, k, phi, u, slat.w[k] * S))
+                       + slat.w[k] * S for k in range(slat.Q)])
+
+    # h^alpha: Eqs. LBE_c_alpha, Heq with the phase-dependent mobility
+    h_post = []
+    for h, c, mu, Mpair in ((st.hA, m["cA"], m["muA"], prm.M_A), (st.hB, m["cB"], m["muB"], prm.M_B)):
+        wh = rate(model.mobility(phi, Mpair), slat.cs2)
+        h_post.append(np.stack([h[k] - wh * (h[k] - h_equilibrium_k(slat, k, c, mu, u))
+                                for k in range(slat.Q)]))
+
+    f_new = None
+    if prm.fluid:
+        # f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq
+        wf = rate(model.viscosity(phi, prm.nu), flat.cs2)
+        Fk = [forcing_k(flat, k, u, F) for k in range(flat.Q)]
+        f_post = np.stack([st.f[k] - wf * (st.f[k] - f_equilibrium_k(flat, k, p_h, u, prm.rho0, Fk[k]))
+                           + Fk[k] for k in range(flat.Q)])
+        f_new = stream(f_post, flat, prm.bc)
+
+    phi_ref = phi.mean() if prm.gravity_mean_subtract else st.phi_ref
+    return State(g=stream(g_post, slat, prm.bc), hA=stream(h_post[0], slat, prm.bc),
+                 hB=stream(h_post[1], slat, prm.bc), f=f_new, phi_ref=phi_ref, step=st.step + 1)
+
+
+def run(st, prm, nsteps):
+    for _ in range(nsteps):
+        st = step(st, prm)
+    return st
+
+
+# ----------------------------------------------------------------------------------------
+# diagnostics
+
+DIAG_NAMES = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u",
+              "interface_measure", "free_energy", "nan_count")
+
+
+def diagnostics(st, prm):
+    """Global reductions of the current state:
+    sums of c^A, c^B and phi; kinetic energy sum rho0 |u|^2 / 2; max |u|;
+    interface measure sum (4/W) phi (1 - phi) (the integrand of Eq. Rmoy_2D);
+    free energy sum [W^2/2 |grad phi|^2 + omega_dw(phi) + lambda/2 (mu_A^2 + mu_B^2)],
+    which is the functional of Eq. functional in units of H after the Legendre
+    transform with the parabolic wells (bulk free energy density = |mu|^2 / 2 in
+    units of K, lambda = K/H); gradient on the dimension's fluid lattice;
+    count of nodes whose phi, c^A or c^B is not finite."""
+    m = moments(st, prm)
+    phi = m["phi"]
+    u2 = m["ux"] ** 2 + m["uy"] ** 2 + m["uz"] ** 2
+    grad = gradient(phi, prm.bc, prm.stencil_lattice)
+    g2 = grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2
+    fe = 0.5 * prm.W ** 2 * g2 + model.omega_dw(phi) + 0.5 * prm.lam * (m["muA"] ** 2 + m["muB"] ** 2)
+    bad = ~(np.isfinite(phi) & np.isfinite(m["cA"]) & np.isfinite(m["cB"]))
+    return dict(sum_cA=m["cA"].sum(), sum_cB=m["cB"].sum(), sum_phi=phi.sum(),
+                kinetic_energy=(0.5 * prm.rho0 * u2).sum(), max_u=np.sqrt(u2.real).max(),
+                interface_measure=((4.0 / prm.W) * phi * (1.0 - phi)).sum(),
+                free_energy=fe.sum(), nan_count=int(bad.sum()))

@@ -1,0 +1,497 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values printed in
+the paper (tests/golden/paper_printed_values.json), moment identities the paper states
+for its equilibria, exact conservation laws of the discrete map, closed-form solutions
+(diffusion, tanh interface, curvature-driven shrinkage, diffusion couple, Poiseuille,
+Laplace), and exact rational arithmetic for the lattice tables.
+"""
+
+import json
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+from oracle import analytic, lattices, lbm, model
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "paper_printed_values.json")))
+
+ALL_LATTICES = [lattices.D2Q5, lattices.D2Q9, lattices.D3Q7, lattices.D3Q19]
+
+
+# ----------------------------------------------------------------------------------------
+# lattice tables (exact rational arithmetic)
+
+@pytest.mark.parametrize("lat", ALL_LATTICES, ids=lambda l: l.name)
+def test_lattice_moments_exact(lat):
+    w, e = lat.w_exact, lat.e
+    assert sum(w) == 1
+    for a in range(3):
+        assert sum(wk * int(ek[a]) for wk, ek in zip(w, e)) == 0
+    cs2 = {"D2Q5": Fr(1, 3), "D2Q9": Fr(1, 3), "D3Q7": Fr(1, 4), "D3Q19": Fr(1, 3)}[lat.name]
+    assert lat.cs2_exact == cs2
+    for a in range(lat.dim):
+        for b in range(lat.dim):
+            m2 = sum(wk * int(ek[a]) * int(ek[b]) for wk, ek in zip(w, e))
+            assert m2 == (cs2 if a == b else 0)
+            for c in range(lat.dim):
+                assert sum(wk * int(ek[a]) * int(ek[b]) * int(ek[c]) for wk, ek in zip(w, e)) == 0
+    for k in range(lat.Q):
+        assert (lat.e[lat.opp[k]] == -lat.e[k]).all()
+        assert lat.w_exact[lat.opp[k]] == lat.w_exact[k]
+
+
+@pytest.mark.parametrize("lat", [lattices.D2Q9, lattices.D3Q19], ids=lambda l: l.name)
+def test_fluid_lattice_fourth_moment_isotropic(lat):
+    """D2Q9 / D3Q19 carry the isotropic fourth moment c_s^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc)
+    that the He-Luo equilibrium (Eq. Feq) relies on."""
+    w, e = lat.w_exact, lat.e
+    cs4 = Fr(1, 9)
+    D = range(lat.dim)
+    for a in D:
+        for b in D:
+            for c in D:
+                for d in D:
+                    m4 = sum(wk * int(ek[a]) * int(ek[b]) * int(ek[c]) * int(ek[d]) for wk, ek in zip(w, e))
+                    iso = cs4 * ((a == b) * (c == d) + (a == c) * (b == d) + (a == d) * (b == c))
+                    assert m4 == iso
+
+
+def test_paper_table_orderings():
+    """Tables tab:D2Q9 and tab:D3Q19: first vectors and weights in the printed order."""
+    assert [tuple(v[:2]) for v in lattices.D2Q9.e[:5]] == [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1)]
+    assert tuple(lattices.D2Q9.e[6][:2]) == (-1, 1)
+    assert lattices.D2Q9.w_exact[0] == Fr(4, 9) and lattices.D2Q9.w_exact[5] == Fr(1, 36)
+    assert tuple(lattices.D3Q19.e[9]) == (1, 0, 1) and tuple(lattices.D3Q19.e[18]) == (0, -1, 1)
+    assert lattices.D3Q19.w_exact[6] == Fr(1, 18) and lattices.D3Q19.w_exact[7] == Fr(1, 36)
+
+
+# ----------------------------------------------------------------------------------------
+# thermodynamics
+
+def test_interpolation_and_double_well_properties():
+    """p(0)=0, p(1)=1, p'(0)=p'(1)=0 (Section 2.2); p(1 - phi) = 1 - p(phi)."""
+    phi = np.linspace(-0.3, 1.3, 33)
+    assert model.p(0.0) == 0.0 and model.p(1.0) == 1.0
+    assert model.dp(0.0) == 0.0 and model.dp(1.0) == 0.0
+    np.testing.assert_allclose(model.p(1.0 - phi), 1.0 - model.p(phi), atol=1e-14)
+    h = 1e-6
+    np.testing.assert_allclose((model.p(phi + h) - model.p(phi - h)) / (2 * h), model.dp(phi), atol=1e-8)
+    np.testing.assert_allclose((model.omega_dw(phi + h) - model.omega_dw(phi - h)) / (2 * h),
+                               model.domega_dw(phi), atol=1e-7)
+
+
+def test_tanh_profile_is_equilibrium_and_surface_tension():
+    """Eq. tanh solves W^2 phi'' = omega_dw'(phi); the excess grand potential of the
+    profile, int [W^2/2 phi'^2 + omega_dw] dx in units of H, is sigma/H = 2W/3."""
+    W = 3.7
+    x = np.linspace(-12 * W, 12 * W, 200001)
+    dx = x[1] - x[0]
+    phi = analytic.tanh_profile(x, W)
+    d1 = np.gradient(phi, dx)
+    d2 = np.gradient(d1, dx)
+    inner = slice(100, -100)
+    np.testing.assert_allclose(W ** 2 * d2[inner], model.domega_dw(phi)[inner], atol=1e-6)
+    excess = np.trapezoid(0.5 * W ** 2 * d1 ** 2 + model.omega_dw(phi), x)
+    assert abs(excess - 2.0 * W / 3.0) < 1e-6
+
+
+def test_lambda_star_printed():
+    dcp = GOLD["diffusion_couple"]
+    c_eq = (tuple(dcp["c_eq_phase0"]), tuple(dcp["c_eq_phase1"]))
+    lam = model.lambda_star(1.0, dcp["M_phi"], dcp["M_alpha"], c_eq)
+    assert abs(lam - dcp["lambda_star"]) < 5e-9
+    # the value does not depend on W (beta and delta both scale with W)
+    assert abs(model.lambda_star(7.0, dcp["M_phi"], dcp["M_alpha"], c_eq) - lam) < 1e-12
+
+
+def test_far_field_potentials_printed():
+    """Caption of tab:Parameters_Diffusion-Couple: the far-field compositions are
+    equivalent to the printed potentials (phase 0 on the left, phase 1 on the right)."""
+    dcp = GOLD["diffusion_couple"]
+    c_eq = (tuple(dcp["c_eq_phase0"]), tuple(dcp["c_eq_phase1"]))
+    mu_l = model.closure_mu(tuple(dcp["c_minus_inf"]), 0.0, c_eq)
+    mu_r = model.closure_mu(tuple(dcp["c_plus_inf"]), 1.0, c_eq)
+    np.testing.assert_allclose(mu_l, dcp["mu_minus_inf"], atol=1e-15)
+    np.testing.assert_allclose(mu_r, dcp["mu_plus_inf"], atol=1e-15)
+    # the forward closure inverts the backward one at any phi
+    for phi in (0.0, 0.3, 0.5, 1.0):
+        mu = model.closure_mu((0.31, 0.27), phi, c_eq)
+        np.testing.assert_allclose(model.closure_c(mu, phi, c_eq), (0.31, 0.27), atol=1e-15)
+
+
+def test_delta_omega_closed_form_and_coexistence():
+    """Delta omega = -sum mu (c_0 - c_1) (Section 2.2); it vanishes on the coexistence
+    line, and c = -d omega / d mu gives back the closure compositions (Eq. species_closure)."""
+    c_eq = ((0.3, 0.3), (0.4, 0.4))
+    rng = np.random.default_rng(1)
+    mu = rng.normal(size=(2, 10))
+    d = model.delta_omega(mu, c_eq)
+    np.testing.assert_allclose(d, -(mu[0] * (0.3 - 0.4) + mu[1] * (0.3 - 0.4)), atol=1e-15)
+    assert abs(model.delta_omega((0.05, -0.05), c_eq)) < 1e-16
+    h = 1e-6
+    for pi in range(2):
+        for a in range(2):
+            mp = [mu[0].copy(), mu[1].copy()]
+            mm = [mu[0].copy(), mu[1].copy()]
+            mp[a] += h
+            mm[a] -= h
+            dw = (model.grand_potential(mp, c_eq[pi]) - model.grand_potential(mm, c_eq[pi])) / (2 * h)
+            np.testing.assert_allclose(-dw, mu[a] + c_eq[pi][a], atol=1e-8)
+
+
+def test_ostwald_collision_rates_printed():
+    """Caption of tab:Parameters_Ostwald-Ripening: the listed rates are tau + 1/2 of a
+    D2Q9 lattice with D = tau c_s^2 dt/dx^2 - this pins the oracle's rate convention.
+    The printed figures are the values cut after four decimals (0.81468 -> 0.8146)."""
+    o = GOLD["ostwald_2d"]
+    s = o["dt"] / o["dx"] ** 2
+    cs2 = lattices.D2Q9.cs2
+    for D, printed in ((o["M_phi"], o["tau_g"]), (o["M_alpha"][0], o["tau_hA"]), (o["M_alpha"][1], o["tau_hB"])):
+        assert 0.0 <= 1.0 / lbm.rate(D * s, cs2) - printed < 1e-4
+
+
+# ----------------------------------------------------------------------------------------
+# equilibrium moments stated in Section 3
+
+@pytest.mark.parametrize("slat,flat", [(lattices.D2Q5, lattices.D2Q9), (lattices.D3Q7, lattices.D3Q19)],
+                         ids=["2D", "3D"])
+def test_equilibrium_moments(slat, flat):
+    rng = np.random.default_rng(7)
+    n = 17
+    phi, c, mu, p_h, S = (rng.uniform(-1, 1, n) for _ in range(5))
+    u = [rng.uniform(-0.1, 0.1, n) for _ in range(3)]
+    F = [rng.uniform(-0.01, 0.01, n) for _ in range(3)]
+    if slat.dim == 2:
+        u[2] = np.zeros(n)
+        F[2] = np.zeros(n)
+    rho0 = 1.3
+    heq = [lbm.h_equilibrium_k(slat, k, c, mu, u) for k in range(slat.Q)]
+    Gk = [slat.w[k] * S for k in range(slat.Q)]
+    geq = [lbm.g_equilibrium_k(slat, k, phi, u, Gk[k]) for k in range(slat.Q)]
+    Fk = [lbm.forcing_k(flat, k, u, F) for k in range(flat.Q)]
+    feq = [lbm.f_equilibrium_k(flat, k, p_h, u, rho0, Fk[k]) for k in range(flat.Q)]
+    tol = dict(atol=1e-14, rtol=0)
+    # Eq. Heq: zeroth moment c, first moment c u, second moment c_s^2 mu I
+    np.testing.assert_allclose(sum(heq), c, **tol)
+    for a in range(slat.dim):
+        np.testing.assert_allclose(sum(heq[k] * slat.e[k][a] for k in range(slat.Q)), c * u[a], **tol)
+        for b in range(slat.dim):
+            m2 = sum(heq[k] * slat.e[k][a] * slat.e[k][b] for k in range(slat.Q))
+            np.testing.assert_allclose(m2, slat.cs2 * mu * (a == b), **tol)
+    # Eqs. Geq, Source_LBE_Phi: sum G = S, sum g^eq = phi - S/2, first moment phi u
+    np.testing.assert_allclose(sum(Gk), S, **tol)
+    np.testing.assert_allclose(sum(geq), phi - 0.5 * S, **tol)
+    for a in range(slat.dim):
+        np.testing.assert_allclose(sum(geq[k] * slat.e[k][a] for k in range(slat.Q)), phi * u[a], **tol)
+    # Eq. ForcingTerm: sum F_k = 0, sum F_k c_k = c_s^2 F (the form Eq. Velocity needs)
+    np.testing.assert_allclose(sum(Fk), 0.0, **tol)
+    for a in range(flat.dim):
+        np.testing.assert_allclose(sum(Fk[k] * flat.e[k][a] for k in range(flat.Q)), flat.cs2 * F[a], **tol)
+    # Eq. Feq: sum f^eq = p_h; (1/c_s^2) sum f^eq c_k + F/2 = rho0 u (Eq. Velocity)
+    np.testing.assert_allclose(sum(feq), p_h, **tol)
+    for a in range(flat.dim):
+        m1 = sum(feq[k] * flat.e[k][a] for k in range(flat.Q))
+        np.testing.assert_allclose(m1 / flat.cs2 + 0.5 * F[a], rho0 * u[a], **tol)
+
+
+# ----------------------------------------------------------------------------------------
+# exact conservation of the discrete map
+
+def _droplet_fields(shape, centres, radii, W, rng, noise=1e-3):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = np.zeros(shape)
+    for c, R in zip(centres, radii):
+        r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+        phi = np.maximum(phi, analytic.tanh_profile(R - r, W))
+    mu = rng.normal(0.0, noise, (2,) + shape)
+    return phi, mu[0], mu[1]
+
+
+@pytest.mark.parametrize("case", ["2d_noflow_walls", "2d_flow_walls", "3d_flow_walls", "3d_flow_periodic_g"])
+def test_mass_conservation_exact(case):
+    rng = np.random.default_rng(3)
+    if case == "2d_noflow_walls":
+        prm = lbm.Params(nx=40, ny=24, bc=("walls", "periodic", "periodic"), W=3.0, lam=21.05)
+        fields = _droplet_fields(prm.shape, [(10, 12, 0), (28, 8, 0)], [6, 5], 3.0, rng)
+        nsteps = 150
+    elif case == "2d_flow_walls":
+        prm = lbm.Params(nx=32, ny=28, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05,
+                         drho=0.5, g=(0, -1e-4, 0), sigma=1e-3, nu=(0.1, 0.05))
+        fields = _droplet_fields(prm.shape, [(16, 14, 0)], [7], 4.0, rng)
+        nsteps = 100
+    elif case == "3d_flow_walls":
+        prm = lbm.Params(nx=14, ny=12, nz=16, fluid="D3Q19", scalar="D3Q7", bc=("periodic", "periodic", "walls"),
+                         W=4.0, lam=21.05, drho=0.5, g=(0, 0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
+        fields = _droplet_fields(prm.shape, [(7, 6, 8)], [4.5], 4.0, rng)
+        nsteps = 30
+    else:
+        prm = lbm.Params(nx=12, ny=12, nz=12, fluid="D3Q19", scalar="D3Q7", W=4.0, lam=21.05,
+                         drho=0.5, g=(0, 0, -1e-4), sigma=1e-3, nu=(0.1, 0.05), gravity_mean_subtract=True)
+        fields = _droplet_fields(prm.shape, [(6, 6, 6)], [4.0], 4.0, rng)
+        nsteps = 30
+    st = lbm.init(*fields, prm)
+    d0 = lbm.diagnostics(st, prm)
+    p0 = st.f.sum() if st.f is not None else 0.0
+    st = lbm.run(st, prm, nsteps)
+    d1 = lbm.diagnostics(st, prm)
+    for key in ("sum_cA", "sum_cB"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * abs(d0[key]), key
+    if st.f is not None:
+        # sum_k F_k = 0 and sum_k f^eq_k = p_h make sum_x p_h invariant as well
+        assert abs(st.f.sum() - p0) <= 1e-12 * max(1.0, abs(d0["sum_phi"]))
+    assert d1["nan_count"] == 0
+
+
+def test_momentum_balance_periodic():
+    """Fully periodic flow: total momentum changes by exactly the total force each step
+    (sum_k F_k c_k = c_s^2 F and the half-force shift of Eq. Velocity)."""
+    rng = np.random.default_rng(5)
+    prm = lbm.Params(nx=20, ny=18, fluid="D2Q9", W=4.0, lam=21.05, drho=0.5, g=(2e-4, -1e-4, 0),
+                     sigma=1e-3, nu=(0.1, 0.05))
+    st = lbm.init(*_droplet_fields(prm.shape, [(10, 9, 0)], [5], 4.0, rng), prm)
+    for _ in range(5):
+        m = lbm.moments(st, prm)
+        mom_a = [(prm.rho0 * m[u]).sum() - 0.5 * m["F"][a].sum() for a, u in enumerate(("ux", "uy"))]
+        st2 = lbm.step(st, prm)
+        m2 = lbm.moments(st2, prm)
+        mom_b = [(prm.rho0 * m2[u]).sum() - 0.5 * m2["F"][a].sum() for a, u in enumerate(("ux", "uy"))]
+        for a in range(2):
+            assert abs(mom_b[a] - mom_a[a] - m["F"][a].sum()) < 1e-15 * prm.nx * prm.ny + 1e-14
+        st = st2
+
+
+# ----------------------------------------------------------------------------------------
+# diffusion of the composition lattice: Fourier-mode decay against exp(-M k^2 t)
+
+@pytest.mark.parametrize("scalar,axis", [("D2Q5", 0), ("D2Q5", 1), ("D3Q7", 2)])
+def test_fourier_mode_diffusivity(scalar, axis):
+    """phi = 0 everywhere stays 0 (omega_dw'(0) = p'(0) = 0), so c^A obeys
+    dc/dt = M lap mu with mu = c - c_0 (Eq. Compos, bulk phase 0).  A sine mode decays
+    as exp(-M k^2 t) up to O(k^4); the measured rate must approach M k^2 with an error
+    that falls like k^2."""
+    errs = []
+    for N in (16, 32):
+        shape = [1, 1, 1] if scalar == "D3Q7" else [1, 1, 1]
+        shape[2 - axis] = N
+        nz, ny, nx = shape
+        M = 0.15
+        prm = lbm.Params(nx=nx, ny=ny, nz=nz, scalar=scalar, W=4.0, lam=10.0, M_phi=0.1,
+                         M_A=(M, M), M_B=(M, M), c_eq=((0.2, 0.1), (0.6, 0.3)))
+        coord = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")[2 - axis]
+        kw = 2 * math.pi / N
+        eps = 1e-3
+        mu0 = eps * np.sin(kw * coord)
+        st = lbm.init(np.zeros(prm.shape), mu0, 0 * mu0, prm)
+        t0, t1 = 40, 40 + int(2.0 / (M * kw * kw))
+        st = lbm.run(st, prm, t0)
+        a0 = (lbm.moments(st, prm)["muA"] * np.sin(kw * coord)).sum()
+        st = lbm.run(st, prm, t1 - t0)
+        m = lbm.moments(st, prm)
+        assert np.abs(m["phi"]).max() == 0.0
+        a1 = (m["muA"] * np.sin(kw * coord)).sum()
+        rate_meas = -math.log(a1 / a0) / (t1 - t0)
+        errs.append(abs(rate_meas / (M * kw * kw) - 1.0))
+    assert errs[1] < 0.02
+    assert errs[0] / errs[1] > 3.0   # O(k^2) relative error
+
+
+# ----------------------------------------------------------------------------------------
+# Allen-Cahn dynamics of the g lattice (Delta omega = 0 by equal phase compositions)
+
+@pytest.mark.slow
+def test_flat_tanh_interface_is_stationary():
+    errs = []
+    for W in (4.0, 8.0):
+        N = int(16 * W)
+        prm = lbm.Params(nx=N, ny=1, bc=("walls", "periodic", "periodic"), W=W, lam=21.05, M_phi=0.1,
+                         c_eq=((0.3, 0.3), (0.3, 0.3)))
+        x = np.arange(N) - (N - 1) / 2.0
+        phi0 = analytic.tanh_profile(x, W).reshape(prm.shape)
+        st = lbm.run(lbm.init(phi0, 0 * phi0, 0 * phi0, prm), prm, int(4 * W * W / prm.M_phi))
+        phi = lbm.moments(st, prm)["phi"].ravel()
+        errs.append(np.abs(phi - analytic.tanh_profile(x, W)).max())
+    assert errs[0] < 2e-2
+    assert errs[0] / errs[1] > 3.0   # O(W^-2)
+
+
+@pytest.mark.slow
+def test_disk_shrinks_by_curvature():
+    """Delta omega = 0: V = -M_phi kappa, so R^2 = R0^2 - 2 M_phi t in 2D."""
+    N, W, R0, Mphi = 96, 4.0, 30.0, 0.1
+    prm = lbm.Params(nx=N, ny=N, W=W, lam=21.05, M_phi=Mphi, c_eq=((0.3, 0.3), (0.3, 0.3)))
+    z, y, x = np.meshgrid(np.arange(1), np.arange(N), np.arange(N), indexing="ij")
+    r = np.sqrt((x - N / 2 + 0.5) ** 2 + (y - N / 2 + 0.5) ** 2)
+    phi0 = analytic.tanh_profile(R0 - r, W)
+    st = lbm.init(phi0, 0 * phi0, 0 * phi0, prm)
+    st = lbm.run(st, prm, 200)
+    r2a = lbm.moments(st, prm)["phi"].sum() / math.pi
+    T = 1500
+    st = lbm.run(st, prm, T)
+    r2b = lbm.moments(st, prm)["phi"].sum() / math.pi
+    slope = (r2b - r2a) / T
+    assert abs(slope / (-2.0 * Mphi) - 1.0) < 0.05
+
+
+# ----------------------------------------------------------------------------------------
+# ternary diffusion couple (Section 4.1)
+
+def test_diffusion_couple_printed_parameters_root():
+    """With the printed table the similarity equation has the single root xi = 0 in
+    [-4, 4] and mu_int = (mu_-inf + mu_+inf)/2 (the printed xi = -0.269824 does not
+    follow from the printed parameters)."""
+    dcp = GOLD["diffusion_couple"]
+    dc = [a - b for a, b in zip(dcp["c_eq_phase0"], dcp["c_eq_phase1"])]
+    roots = analytic.dc_roots(dcp["mu_minus_inf"], dcp["mu_plus_inf"], dc, dcp["M_alpha"])
+    assert len(roots) == 1 and abs(roots[0]) < 1e-12
+    for a in range(2):
+        mi = analytic.dc_interface_mu(roots[0], dcp["mu_minus_inf"][a], dcp["mu_plus_inf"][a], dc[a], dcp["M_alpha"][a])
+        assert abs(mi - 0.5 * (dcp["mu_minus_inf"][a] + dcp["mu_plus_inf"][a])) < 1e-14
+
+
+def _interface_position(phi, x):
+    i = np.nonzero((phi[:-1] - 0.5) * (phi[1:] - 0.5) <= 0)[0][0]
+    return x[i] + (0.5 - phi[i]) / (phi[i + 1] - phi[i]) * (x[i + 1] - x[i])
+
+
+def _run_couple(mu_l, mu_r, c_eq, M, Mphi, W, N, T, snaps):
+    dc = [c_eq[0][a] - c_eq[1][a] for a in range(2)]
+    lam = model.lambda_star(W, Mphi, M, c_eq)
+    prm = lbm.Params(nx=N, ny=1, bc=("walls", "periodic", "periodic"), W=W, lam=lam, M_phi=Mphi,
+                     M_A=(M[0], M[0]), M_B=(M[1], M[1]), c_eq=c_eq)
+    x = np.arange(N) - (N - 1) / 2.0
+    phi0 = analytic.tanh_profile(x, W)
+    muA0 = np.where(x < 0, mu_l[0], mu_r[0])
+    muB0 = np.where(x < 0, mu_l[1], mu_r[1])
+    st = lbm.init(phi0.reshape(prm.shape), muA0.reshape(prm.shape), muB0.reshape(prm.shape), prm)
+    out = {}
+    t = 0
+    for s in snaps:
+        st = lbm.run(st, prm, s - t)
+        t = s
+        m = lbm.moments(st, prm)
+        out[s] = dict(xI=_interface_position(m["phi"].ravel(), x), muA=m["muA"].ravel(), muB=m["muB"].ravel())
+    return x, dc, out
+
+
+@pytest.mark.slow
+def test_diffusion_couple_printed_parameters_profiles():
+    """Paper's couple in lattice units (mobilities x 0.1, W = 4): the interface stays at
+    x = 0 and the potentials follow the erfc solution with mu_int = (-0.0375, 0.0375)."""
+    dcp = GOLD["diffusion_couple"]
+    c_eq = (tuple(dcp["c_eq_phase0"]), tuple(dcp["c_eq_phase1"]))
+    M = [0.1 * m for m in dcp["M_alpha"]]
+    T = 2000
+    x, dc, out = _run_couple(dcp["mu_minus_inf"], dcp["mu_plus_inf"], c_eq, M, 0.12, 4.0, 512, T, [T])
+    assert abs(out[T]["xI"]) < 0.05
+    for a, key in enumerate(("muA", "muB")):
+        ref = analytic.dc_mu_profile(x, T, 0.0, dcp["mu_minus_inf"][a], dcp["mu_plus_inf"][a], dc[a], M[a])
+        assert np.abs(out[T][key] - ref).max() < 0.01 * abs(dcp["mu_plus_inf"][a] - dcp["mu_minus_inf"][a])
+
+
+@pytest.mark.slow
+def test_diffusion_couple_moving_interface():
+    """A couple whose far fields are not symmetric about the coexistence line moves as
+    x_I = xi sqrt(t) with xi from the similarity equation; the phase-field interface must
+    follow it (pins the sign and size of the coupling lambda p' Delta omega, the closure
+    and the interface mass balance together)."""
+    c_eq = ((0.3, 0.3), (0.4, 0.4))
+    M = [0.1, 0.08]
+    mu_l, mu_r = (0.1, 0.05), (-0.02, 0.0)
+    dc = [c_eq[0][a] - c_eq[1][a] for a in range(2)]
+    roots = analytic.dc_roots(mu_l, mu_r, dc, M)
+    assert len(roots) == 1
+    xi = roots[0]
+    assert xi < -0.4     # phase 1 grows to the left
+    snaps = [1000, 4000]
+    x, _, out = _run_couple(mu_l, mu_r, c_eq, M, 0.12, 4.0, 512, snaps[-1], snaps)
+    # the velocity is checked through the displacement between two times, which cancels the
+    # initial transient offset of the diffuse interface
+    xi_meas = (out[snaps[1]]["xI"] - out[snaps[0]]["xI"]) / (math.sqrt(snaps[1]) - math.sqrt(snaps[0]))
+    assert abs(xi_meas / xi - 1.0) < 0.05
+    for a, key in enumerate(("muA", "muB")):
+        ref = analytic.dc_mu_profile(x, snaps[1], xi, mu_l[a], mu_r[a], dc[a], M[a])
+        far = np.abs(x - out[snaps[1]]["xI"]) > 3 * 4.0
+        assert np.abs(out[snaps[1]][key] - ref)[far].max() < 0.05 * abs(mu_l[a] - mu_r[a])
+
+
+# ----------------------------------------------------------------------------------------
+# flow
+
+@pytest.mark.slow
+def test_poiseuille_between_walls():
+    """phi = 1 everywhere: no capillary force, buoyancy is a uniform body force drho g;
+    the steady profile between half-way bounce-back walls is the parabola."""
+    N, nu = 16, 0.1
+    prm = lbm.Params(nx=2, ny=N, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05,
+                     drho=1.0, g=(1e-6, 0, 0), sigma=1e-3, nu=(nu, nu))
+    phi0 = np.ones(prm.shape)
+    st = lbm.run(lbm.init(phi0, 0 * phi0, 0 * phi0, prm), prm, 6000)
+    ux = lbm.moments(st, prm)["ux"][0, :, 0]
+    ref = analytic.poiseuille(np.arange(N), N, 1e-6, prm.rho0, nu)
+    assert np.abs(ux - ref).max() < 0.01 * ref.max()
+
+
+@pytest.mark.slow
+def test_laplace_pressure_jump():
+    """Static 2D drop with no driving force: p_in - p_out = sigma / R (within the spurious
+    current error of the diffuse-interface force Eq. SurfaceTension_Force)."""
+    N, W, R, sigma = 64, 4.0, 16.0, 1e-3
+    prm = lbm.Params(nx=N, ny=N, fluid="D2Q9", W=W, lam=21.05, M_phi=0.002, c_eq=((0.3, 0.3), (0.3, 0.3)),
+                     drho=0.0, sigma=sigma, nu=(0.2, 0.2))
+    z, y, x = np.meshgrid(np.arange(1), np.arange(N), np.arange(N), indexing="ij")
+    r = np.sqrt((x - N / 2 + 0.5) ** 2 + (y - N / 2 + 0.5) ** 2)
+    phi0 = analytic.tanh_profile(R - r, W)
+    st = lbm.run(lbm.init(phi0, 0 * phi0, 0 * phi0, prm), prm, 1500)
+    m = lbm.moments(st, prm)
+    R_now = math.sqrt(m["phi"].sum() / math.pi)
+    dp = m["p"][r < R - 2 * W].mean() - m["p"][r > R + 2 * W].mean()
+    assert abs(dp / analytic.laplace_jump(sigma, R_now) - 1.0) < 0.05
+
+
+# ----------------------------------------------------------------------------------------
+# free-energy decrease without flow
+
+def test_free_energy_decreases_without_flow():
+    rng = np.random.default_rng(11)
+    prm = lbm.Params(nx=48, ny=40, W=3.0, lam=21.05, M_phi=0.1, M_A=(0.1, 0.1), M_B=(0.1, 0.1))
+    st = lbm.init(*_droplet_fields(prm.shape, [(12, 12, 0), (32, 26, 0), (36, 8, 0)], [7, 5, 4], 3.0, rng,
+                                   noise=2e-3), prm)
+    F = [lbm.diagnostics(st, prm)["free_energy"]]
+    for _ in range(8):
+        st = lbm.run(st, prm, 25)
+        F.append(lbm.diagnostics(st, prm)["free_energy"])
+    assert all(b < a for a, b in zip(F, F[1:]))
+
+
+# ----------------------------------------------------------------------------------------
+# complex-step derivatives of the oracle against central differences
+
+def test_complex_step_matches_central_difference():
+    rng = np.random.default_rng(2)
+    base = lbm.Params(nx=16, ny=14, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05,
+                      M_phi=0.1, M_A=(0.1, 0.1), M_B=(0.1, 0.1), drho=0.5, g=(0, -1e-4, 0), sigma=1e-3,
+                      nu=(0.1, 0.05))
+    phi0, muA, muB = _droplet_fields(base.shape, [(8, 7, 0)], [4.5], 4.0, rng)
+
+    def loss(M, W, dphi=0.0):
+        prm = base.with_(M_phi=M, M_A=(M, M), M_B=(M, M), W=W)
+        st = lbm.run(lbm.init(phi0 + dphi, muA, muB, prm), prm, 12)
+        return (lbm.moments(st, prm)["phi"] ** 2).sum()
+
+    h = 1e-30
+    dM_cs = loss(0.1 + 1j * h, 4.0).imag / h
+    dW_cs = loss(0.1, 4.0 + 1j * h).imag / h
+    v = rng.normal(size=phi0.shape)
+    dv_cs = loss(0.1, 4.0, 1j * h * v).imag / h
+    e = 1e-5
+    dM_fd = (loss(0.1 + e, 4.0) - loss(0.1 - e, 4.0)) / (2 * e)
+    dW_fd = (loss(0.1, 4.0 + e) - loss(0.1, 4.0 - e)) / (2 * e)
+    dv_fd = (loss(0.1, 4.0, e * v) - loss(0.1, 4.0, -e * v)) / (2 * e)
+    for a, b in ((dM_cs, dM_fd), (dW_cs, dW_fd), (dv_cs, dv_fd)):
+        assert abs(a - b) <= 1e-6 * max(abs(a), 1e-3)
