@@ -1,0 +1,157 @@
+/*
+ * lbm.h - C ABI of the MI355X lattice-Boltzmann step of the grand-potential
+ * phase-field model of a two-phase ternary fluid (Verdier, Cartalade & Plapp,
+ * arXiv 2409.03401).
+ *
+ * One simulation domain on one GPU.  Every device buffer is owned by the
+ * caller; the library never allocates device memory.  All calls are
+ * asynchronous on the HIP stream passed as `stream` (a hipStream_t; NULL is the
+ * default stream) unless stated otherwise.  Errors: a call returns LBM_OK (0)
+ * or a negative LBM_E* code and leaves a message for lbm_last_error() (per
+ * host thread).  No C++ exception crosses this interface.
+ *
+ * Grids are indexed node = (z * ny + y) * nx + x, x fastest.  In 2D nz = 1.
+ * Same inputs give bitwise-identical outputs (no floating-point atomics).
+ */
+#ifndef LBM_GP_TERNARY_H
+#define LBM_GP_TERNARY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)       /* bad argument or inconsistent configuration        */
+#define LBM_ESIZE (-2)        /* a caller buffer is smaller than required          */
+#define LBM_EUNSTABLE (-3)    /* a BGK rate lies outside (0, 2) (tau <= 0)         */
+#define LBM_EUNSUPPORTED (-4) /* lattice / precision / boundary combination        */
+#define LBM_EHIP (-5)         /* a HIP runtime call failed                         */
+
+/* ---- configuration values --------------------------------------------------- */
+#define LBM_NONE 0            /* no flow: u = 0, no f populations                  */
+#define LBM_D2Q9 9            /* fluid lattices, Tables tab:D2Q9 / tab:D3Q19       */
+#define LBM_D3Q19 19
+#define LBM_D2Q5 5            /* scalar lattices for phi, c^A, c^B                 */
+#define LBM_D3Q7 7
+
+#define LBM_PERIODIC 0
+#define LBM_WALLS 1           /* half-way bounce-back walls at both ends of an axis */
+
+#define LBM_FP64 0            /* FP64 storage and arithmetic                        */
+#define LBM_FP32 1            /* FP32 storage and arithmetic                        */
+#define LBM_FP32_FP16STORE 2  /* FP32 arithmetic, moving populations stored in FP16 */
+#define LBM_FP32_BF16STORE 3  /* FP32 arithmetic, moving populations stored in BF16 */
+
+#define LBM_OUT_F64 0
+#define LBM_OUT_F32 1
+
+/* moment masks for lbm_moments; out[i] belongs to the i-th bit */
+#define LBM_M_PHI (1u << 0)   /* phase field, Eq. Moment0_Phi                       */
+#define LBM_M_CA (1u << 1)    /* compositions, Eq. Moment0_c_alpha                  */
+#define LBM_M_CB (1u << 2)
+#define LBM_M_MUA (1u << 3)   /* diffusion potentials, Eq. PotChem                  */
+#define LBM_M_MUB (1u << 4)
+#define LBM_M_P (1u << 5)     /* hydrodynamic pressure, Eq. HydroPressure           */
+#define LBM_M_UX (1u << 6)    /* velocity, Eq. Velocity                             */
+#define LBM_M_UY (1u << 7)
+#define LBM_M_UZ (1u << 8)
+#define LBM_NMOM 9
+
+/* diagnostics written by lbm_diagnostics, in this order */
+#define LBM_D_SUM_CA 0        /* sum_x c^A                                          */
+#define LBM_D_SUM_CB 1        /* sum_x c^B                                          */
+#define LBM_D_SUM_PHI 2       /* sum_x phi                                          */
+#define LBM_D_KINETIC 3       /* sum_x rho0 |u|^2 / 2                               */
+#define LBM_D_MAX_U 4         /* max_x |u|                                          */
+#define LBM_D_INTERFACE 5     /* sum_x (4/W) phi (1 - phi), integrand of Eq. Rmoy_2D */
+#define LBM_D_FREE_ENERGY 6   /* sum_x [W^2/2 |grad phi|^2 + omega_dw + lambda/2 |mu|^2] */
+#define LBM_D_NAN_COUNT 7     /* nodes whose phi, c^A or c^B is not finite          */
+#define LBM_NDIAG 8
+
+/*
+ * Physical parameters in lattice units (dx = dt = 1).  Section 2 of the paper
+ * for the model, Section 3 for the lattices; [2] arrays are (phase 0, phase 1),
+ * c_eq[phase][component].
+ */
+typedef struct lbm_config {
+    int32_t nx, ny, nz;        /* nz = 1 for 2D                                     */
+    int32_t fluid;             /* LBM_NONE, LBM_D2Q9 (2D) or LBM_D3Q19 (3D)         */
+    int32_t scalar;            /* LBM_D2Q5 (2D) or LBM_D3Q7 (3D)                    */
+    int32_t bc[3];             /* per axis x, y, z: LBM_PERIODIC or LBM_WALLS       */
+    int32_t precision;         /* LBM_FP64 ... LBM_FP32_BF16STORE                   */
+    int32_t gravity_mean_subtract; /* 1: buoyancy uses phi - <phi> of the previous
+                                      step (for fully periodic boxes); 0: phi       */
+    double W;                  /* interface width                                   */
+    double lambda;             /* coupling constant K/H                             */
+    double M_phi;              /* scaled phase-field mobility W^2 / tau_phi         */
+    double M_A[2], M_B[2];     /* scaled species mobilities per phase               */
+    double c_eq[2][2];         /* equilibrium compositions [phase][A|B]             */
+    double rho0;               /* reference density                                 */
+    double drho;               /* density difference (phase 1 denser)               */
+    double g[3];               /* gravity                                           */
+    double sigma;              /* surface tension                                   */
+    double nu[2];              /* kinematic viscosity per phase                     */
+    double store_ref[4];       /* 16-bit storage: reference per field f, g, hA, hB  */
+    int32_t store_shift[4];    /* 16-bit storage: power-of-two scale per field      */
+} lbm_config;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Size of the state buffer lbm_init needs (two population copies plus a small
+ * reduction area), and of one checkpoint written by lbm_save. */
+int lbm_state_bytes(const lbm_config* cfg, size_t* bytes);
+int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes);
+
+/*
+ * Initialise the populations at rest (Section 4.2.1): from the FP64 device
+ * fields phi0, muA0, muB0 ([node]), compositions follow Eq. species_closure,
+ * u = 0, p_h = 0, and every population is set to its equilibrium (Eqs. Feq,
+ * Geq, Heq) including the -F_k/2 and -G_k/2 shifts.  `state` is a device
+ * buffer of at least lbm_state_bytes; it must stay allocated until
+ * lbm_destroy.  On success *out receives a host handle (owns no device memory).
+ */
+int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes,
+             const double* phi0, const double* muA0, const double* muB0,
+             void* stream, lbm_handle** out);
+
+/* Advance nsteps >= 0 time steps (Section 3: moments, forces, BGK collision of
+ * f, g, h^A, h^B, streaming with periodic or bounce-back boundaries). */
+int lbm_step(lbm_handle* h, int64_t nsteps, void* stream);
+
+/* Write the macroscopic fields of the current state into out[i] for each bit
+ * i set in mask (device arrays of nx*ny*nz elements, LBM_OUT_F64 or
+ * LBM_OUT_F32).  Entries of out for unset bits are ignored.  In 2D, uz is 0. */
+int lbm_moments(lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtype,
+                void* stream);
+
+/* FP64 reductions of the current state into host_out[LBM_NDIAG].  Synchronises
+ * `stream`. */
+int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream);
+
+/* Current populations decoded to FP64, canonical order: f_0..f_{Qf-1},
+ * g_0..g_{Qs-1}, hA_0.., hB_0.. (paper's direction order), each [node].
+ * dst holds (Qf + 3 Qs) * nodes doubles.  set_populations encodes such an
+ * array into the current state (rounding to the storage type). */
+int lbm_get_populations(lbm_handle* h, double* dst, void* stream);
+int lbm_set_populations(lbm_handle* h, const double* src, void* stream);
+
+/* Checkpoint / resume: byte copy of the current population copy plus the
+ * buffered <phi> of the gravity reference.  restore(save(s)) continues
+ * bitwise identically. */
+int lbm_save(lbm_handle* h, void* dst, void* stream);
+int lbm_restore(lbm_handle* h, const void* src, void* stream);
+
+/* Number of steps taken since lbm_init (host counter). */
+int64_t lbm_step_count(const lbm_handle* h);
+
+void lbm_destroy(lbm_handle* h);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_GP_TERNARY_H */

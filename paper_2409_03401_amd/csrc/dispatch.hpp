@@ -1,0 +1,27 @@
+// Launchers of one lattice family at one storage precision, used by the host API.
+#pragma once
+
+#include "params.hpp"
+
+namespace lbm {
+
+struct KernelSet {
+    // fused kernel in MODE_STEP / MODE_MOMENTS / MODE_DIAG
+    void (*fused)(int mode, dim3 grid, const KParams& kp, hipStream_t s);
+    // equilibrium initialisation, one thread per node
+    void (*init)(const KParams& kp, const double* phi0, const double* muA0, const double* muB0,
+                 hipStream_t s);
+    void (*get_pops)(const KParams& kp, int nslots, long long nodes, double* out, hipStream_t s);
+    void (*set_pops)(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s);
+    int tx, ty;  // work-group tile of the fused kernel
+};
+
+// fluid: 0 (none) or 9 / 19; prec: Prec.  nullptr for unsupported combinations.
+const KernelSet* kernels_2d(int fluid, int prec);
+const KernelSet* kernels_3d(int fluid, int prec);
+
+void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
+void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,
+                     double* out, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,53 @@
+// Instantiation helper: the launchers of one (scalar lattice, fluid lattice)
+// family for the four storage precisions.
+#pragma once
+
+#include "dispatch.hpp"
+#include "kernels.hpp"
+
+namespace lbm {
+
+template <class SL, class FL, int PREC, int TX, int TY>
+struct Family {
+    static void fused(int mode, dim3 grid, const KParams& kp, hipStream_t s) {
+        const dim3 block(TX, TY);
+        switch (mode) {
+            case MODE_STEP:
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP, PREC, TX, TY>), grid, block, 0, s, kp);
+                break;
+            case MODE_MOMENTS:
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_MOMENTS, PREC, TX, TY>), grid, block, 0, s, kp);
+                break;
+            default:
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_DIAG, PREC, TX, TY>), grid, block, 0, s, kp);
+                break;
+        }
+    }
+    static void init(const KParams& kp, const double* phi0, const double* muA0, const double* muB0,
+                     hipStream_t s) {
+        const dim3 grid((kp.nx + 255) / 256, kp.ny, kp.nz);
+        hipLaunchKernelGGL((k_init<SL, FL, PREC>), grid, dim3(256), 0, s, kp, phi0, muA0, muB0);
+    }
+    static void get_pops(const KParams& kp, int nslots, long long nodes, double* out, hipStream_t s) {
+        const dim3 grid(unsigned((nodes + 255) / 256), nslots);
+        hipLaunchKernelGGL((k_get_pops<PREC>), grid, dim3(256), 0, s, kp, nslots, nodes, out);
+    }
+    static void set_pops(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s) {
+        const dim3 grid(unsigned((nodes + 255) / 256), nslots);
+        hipLaunchKernelGGL((k_set_pops<PREC>), grid, dim3(256), 0, s, kp, nslots, nodes, in);
+    }
+    static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, TX, TY};
+};
+
+template <class SL, class FL, int TX, int TY>
+const KernelSet* family_for_prec(int prec) {
+    switch (prec) {
+        case P64: return &Family<SL, FL, P64, TX, TY>::set;
+        case P32: return &Family<SL, FL, P32, TX, TY>::set;
+        case P16: return &Family<SL, FL, P16, TX, TY>::set;
+        case PB16: return &Family<SL, FL, PB16, TX, TY>::set;
+        default: return nullptr;
+    }
+}
+
+}  // namespace lbm

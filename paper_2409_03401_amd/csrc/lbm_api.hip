@@ -1,0 +1,393 @@
+// C ABI of the library (declared in include/lbm.h): configuration checks, state
+// layout, launch geometry and the host side of every entry point.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "dispatch.hpp"
+#include "lattice.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define LBM_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) return fail(LBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// weights of the paper's lattices in canonical order (for the 16-bit references)
+double lattice_w(int q, int k) {
+    switch (q) {
+        case 5: return D2Q5K::w(k);
+        case 7: return D3Q7K::w(k);
+        case 9: return D2Q9K::w(k);
+        case 19: return D3Q19K::w(k);
+    }
+    return 0.0;
+}
+
+struct Layout {
+    int dim, qf, qs, nslots, prec;
+    int NX, NY, NZ;  // kernel frame
+    long long nodes;
+    size_t slot_off[kMaxSlots];
+    size_t copy_bytes;
+    int tx, ty, zc;
+    dim3 grid;
+    long long nparts;     // work-groups of the fused kernel
+    size_t aux_bytes;
+    size_t state_bytes;
+};
+
+int check_config(const lbm_config* c, Layout* L) {
+    if (!c) return fail(LBM_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(LBM_EINVAL, "grid sizes must be >= 1");
+    if (c->scalar == LBM_D2Q5) {
+        if (c->nz != 1) return fail(LBM_EINVAL, "D2Q5 needs nz = 1");
+        if (c->fluid != LBM_NONE && c->fluid != LBM_D2Q9)
+            return fail(LBM_EUNSUPPORTED, "2D runs take LBM_NONE or LBM_D2Q9 for the fluid");
+        L->dim = 2;
+    } else if (c->scalar == LBM_D3Q7) {
+        if (c->fluid != LBM_NONE && c->fluid != LBM_D3Q19)
+            return fail(LBM_EUNSUPPORTED, "3D runs take LBM_NONE or LBM_D3Q19 for the fluid");
+        L->dim = 3;
+    } else {
+        return fail(LBM_EUNSUPPORTED, "scalar lattice must be LBM_D2Q5 or LBM_D3Q7");
+    }
+    if (c->precision < LBM_FP64 || c->precision > LBM_FP32_BF16STORE)
+        return fail(LBM_EUNSUPPORTED, "unknown precision");
+    for (int a = 0; a < 3; ++a)
+        if (c->bc[a] != LBM_PERIODIC && c->bc[a] != LBM_WALLS)
+            return fail(LBM_EINVAL, "bc must be LBM_PERIODIC or LBM_WALLS");
+    const long long nodes = (long long)c->nx * c->ny * c->nz;
+    if (nodes >= (1LL << 31)) return fail(LBM_EUNSUPPORTED, "more than 2^31 - 1 nodes");
+    const bool flow = c->fluid != LBM_NONE;
+    if (c->gravity_mean_subtract && !flow)
+        return fail(LBM_EINVAL, "gravity_mean_subtract needs a fluid lattice");
+    auto finite = [](double v) { return std::isfinite(v); };
+    if (!(finite(c->W) && c->W > 0)) return fail(LBM_EINVAL, "W must be > 0");
+    if (!finite(c->lambda)) return fail(LBM_EINVAL, "lambda must be finite");
+    for (int pi = 0; pi < 2; ++pi)
+        for (int a = 0; a < 2; ++a)
+            if (!finite(c->c_eq[pi][a])) return fail(LBM_EINVAL, "c_eq must be finite");
+    // every BGK rate 1 / (D / c_s^2 + 1/2) must lie in (0, 2): D > 0
+    if (!(c->M_phi > 0)) return fail(LBM_EUNSTABLE, "M_phi must be > 0 (rate outside (0, 2))");
+    for (int pi = 0; pi < 2; ++pi)
+        if (!(c->M_A[pi] > 0) || !(c->M_B[pi] > 0))
+            return fail(LBM_EUNSTABLE, "species mobilities must be > 0 (rate outside (0, 2))");
+    if (flow) {
+        if (!(c->rho0 > 0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+        for (int pi = 0; pi < 2; ++pi)
+            if (!(c->nu[pi] > 0)) return fail(LBM_EUNSTABLE, "viscosities must be > 0 (rate outside (0, 2))");
+        for (double v : {c->drho, c->g[0], c->g[1], c->g[2], c->sigma})
+            if (!finite(v)) return fail(LBM_EINVAL, "flow parameters must be finite");
+    }
+    if (c->precision >= LBM_FP32_FP16STORE)
+        for (int i = 0; i < 4; ++i) {
+            if (!finite(c->store_ref[i])) return fail(LBM_EINVAL, "store_ref must be finite");
+            if (c->store_shift[i] < -30 || c->store_shift[i] > 30)
+                return fail(LBM_EINVAL, "store_shift out of [-30, 30]");
+        }
+
+    L->prec = c->precision;
+    L->qf = c->fluid;
+    L->qs = c->scalar;
+    L->nslots = L->qf + 3 * L->qs;
+    L->nodes = nodes;
+    if (L->dim == 2) {  // user (x, y) -> kernel (x, z)
+        L->NX = c->nx; L->NY = 1; L->NZ = c->ny;
+    } else {
+        L->NX = c->nx; L->NY = c->ny; L->NZ = c->nz;
+    }
+    size_t off = 0;
+    for (int s = 0; s < L->nslots; ++s) {
+        const int k = s < L->qf ? s : (s - L->qf) % L->qs;
+        L->slot_off[s] = off;
+        off += round_up((size_t)nodes * slot_bytes(L->prec, k));
+    }
+    L->copy_bytes = off;
+
+    // launch geometry: TX x TY node columns marching along z in chunks of zc planes,
+    // aiming at about 2048 work-groups (8 per compute unit)
+    L->tx = L->dim == 2 ? 64 : 32;
+    L->ty = L->dim == 2 ? 1 : 8;
+    const long long gx = (L->NX + L->tx - 1) / L->tx, gy = (L->NY + L->ty - 1) / L->ty;
+    long long nchunks = std::max(1LL, std::min<long long>(L->NZ, 2048 / std::max(1LL, gx * gy)));
+    int zc = int((L->NZ + nchunks - 1) / nchunks);
+    if (const char* e = std::getenv("LBM_ZC")) {
+        const int v = std::atoi(e);
+        if (v > 0) zc = std::min(v, L->NZ);
+    }
+    L->zc = zc;
+    const long long gz = (L->NZ + zc - 1) / zc;
+    L->grid = dim3(unsigned(gx), unsigned(gy), unsigned(gz));
+    L->nparts = gx * gy * gz;
+    // aux: 16 doubles of scalars, then per-work-group partials (8 per group)
+    const long long npart_doubles = std::max<long long>(8 * L->nparts, 1024);
+    L->aux_bytes = round_up(sizeof(double) * (16 + npart_doubles));
+    L->state_bytes = 2 * L->copy_bytes + L->aux_bytes;
+    return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_handle {
+    lbm_config cfg;
+    Layout L;
+    const KernelSet* ks;
+    char* copy[2];
+    double* aux;
+    int cur;
+    int64_t steps;
+    KParams base;  // every field except src/dst/mout
+};
+
+namespace {
+
+void set_slots(const lbm_handle* h, KParams& kp, const char* src, char* dst) {
+    for (int s = 0; s < kMaxSlots; ++s) {
+        kp.src[s] = (src && s < h->L.nslots) ? src + h->L.slot_off[s] : nullptr;
+        kp.dst[s] = (dst && s < h->L.nslots) ? dst + h->L.slot_off[s] : nullptr;
+    }
+}
+
+void fill_params(lbm_handle* h) {
+    const lbm_config& c = h->cfg;
+    const Layout& L = h->L;
+    KParams& kp = h->base;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.nx = L.NX; kp.ny = L.NY; kp.nz = L.NZ;
+    if (L.dim == 2) {
+        kp.wall_x = c.bc[0] == LBM_WALLS; kp.wall_y = 0; kp.wall_z = c.bc[1] == LBM_WALLS;
+        kp.gx = c.g[0]; kp.gy = 0.0; kp.gz = c.g[1];
+    } else {
+        kp.wall_x = c.bc[0] == LBM_WALLS; kp.wall_y = c.bc[1] == LBM_WALLS; kp.wall_z = c.bc[2] == LBM_WALLS;
+        kp.gx = c.g[0]; kp.gy = c.g[1]; kp.gz = c.g[2];
+    }
+    kp.zc = L.zc;
+    kp.mean_subtract = c.gravity_mean_subtract ? 1 : 0;
+    kp.W = c.W;
+    kp.lam = c.lambda;
+    kp.mphi_w2 = c.M_phi / (c.W * c.W);
+    kp.c0A = c.c_eq[0][0]; kp.c0B = c.c_eq[0][1];
+    kp.c1A = c.c_eq[1][0]; kp.c1B = c.c_eq[1][1];
+    const double cs2s = L.qs == 5 ? D2Q5K::cs2 : D3Q7K::cs2;
+    kp.omega_g = 1.0 / (c.M_phi / cs2s + 0.5);
+    kp.MA0 = c.M_A[0]; kp.MA1 = c.M_A[1]; kp.MB0 = c.M_B[0]; kp.MB1 = c.M_B[1];
+    kp.nu0 = c.nu[0]; kp.nu1 = c.nu[1];
+    kp.rho0 = L.qf ? c.rho0 : 1.0;
+    kp.drho = c.drho;
+    kp.cap = 1.5 * c.sigma * c.W;
+    kp.inv_W2 = 1.0 / (c.W * c.W);
+    for (int s = 0; s < L.nslots; ++s) {
+        const int field = s < L.qf ? 0 : 1 + (s - L.qf) / L.qs;
+        const int k = s < L.qf ? s : (s - L.qf) % L.qs;
+        const int q = s < L.qf ? L.qf : L.qs;
+        const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
+        kp.srest[s] = k == 0;
+        kp.swref[s] = (sixteen && k != 0) ? float(lattice_w(q, k) * c.store_ref[field]) : 0.0f;
+        const int sh = sixteen ? c.store_shift[field] : 0;
+        kp.sscale[s] = std::ldexp(1.0f, sh);
+        kp.sinv[s] = std::ldexp(1.0f, -sh);
+    }
+    kp.phi_ref = h->aux;
+    kp.partials = h->aux + 16;
+}
+
+int check_handle(const lbm_handle* h) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    return LBM_OK;
+}
+
+int launched(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_state_bytes(const lbm_config* cfg, size_t* bytes) {
+    Layout L;
+    if (int r = check_config(cfg, &L)) return r;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = L.state_bytes;
+    return LBM_OK;
+}
+
+int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes) {
+    Layout L;
+    if (int r = check_config(cfg, &L)) return r;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = L.copy_bytes + kAlign;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
+             const double* muA0, const double* muB0, void* stream, lbm_handle** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    if (int r = check_config(cfg, &L)) return r;
+    if (!state || !phi0 || !muA0 || !muB0) return fail(LBM_EINVAL, "NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(state) % kAlign) != 0)
+        return fail(LBM_EINVAL, "state must be 256-byte aligned");
+    if (state_bytes < L.state_bytes)
+        return fail(LBM_ESIZE, "state buffer smaller than lbm_state_bytes");
+    const KernelSet* ks = L.dim == 2 ? kernels_2d(L.qf, L.prec) : kernels_3d(L.qf, L.prec);
+    if (!ks) return fail(LBM_EUNSUPPORTED, "no kernel for this lattice / precision");
+
+    lbm_handle* h = new lbm_handle();
+    h->cfg = *cfg;
+    h->L = L;
+    h->ks = ks;
+    h->copy[0] = static_cast<char*>(state);
+    h->copy[1] = static_cast<char*>(state) + L.copy_bytes;
+    h->aux = reinterpret_cast<double*>(static_cast<char*>(state) + 2 * L.copy_bytes);
+    h->cur = 0;
+    h->steps = 0;
+    fill_params(h);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    auto bail = [&](int r) { delete h; return r; };
+    if (hipMemsetAsync(h->aux, 0, 16 * sizeof(double), s) != hipSuccess)
+        return bail(fail(LBM_EHIP, "hipMemsetAsync of the aux area failed"));
+    if (cfg->gravity_mean_subtract) {
+        // <phi_0> for the buoyancy reference of the first step
+        const int nb = int(std::min<long long>(1024, (L.nodes + 255) / 256));
+        launch_sum_partials(phi0, L.nodes, h->aux + 16, nb, s);
+        launch_finalize(h->aux + 16, nb, 1, -1, 1.0 / double(L.nodes), h->aux, s);
+        if (int r = launched("phi_0 mean")) return bail(r);
+    }
+    KParams kp = h->base;
+    set_slots(h, kp, nullptr, h->copy[0]);
+    ks->init(kp, phi0, muA0, muB0, s);
+    if (int r = launched("init kernel")) return bail(r);
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int64_t nsteps, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp[2] = {h->base, h->base};
+    set_slots(h, kp[0], h->copy[0], h->copy[1]);
+    set_slots(h, kp[1], h->copy[1], h->copy[0]);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        h->ks->fused(MODE_STEP, h->L.grid, kp[h->cur], s);
+        if (h->cfg.gravity_mean_subtract)
+            launch_finalize(h->aux + 16, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), h->aux, s);
+        if (int r = launched("step kernel")) return r;
+        h->cur ^= 1;
+        h->steps += 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtype, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (out_dtype != LBM_OUT_F64 && out_dtype != LBM_OUT_F32) return fail(LBM_EINVAL, "bad out_dtype");
+    if (mask >> LBM_NMOM) return fail(LBM_EINVAL, "unknown bits in mask");
+    if (mask && !out) return fail(LBM_EINVAL, "out is NULL");
+    for (int i = 0; i < LBM_NMOM; ++i)
+        if ((mask >> i & 1u) && !out[i]) return fail(LBM_EINVAL, "NULL output for a requested moment");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp = h->base;
+    set_slots(h, kp, h->copy[h->cur], nullptr);
+    for (int i = 0; i < kNumMom; ++i) kp.mout[i] = nullptr;
+    for (int i = 0; i < 6; ++i)
+        if (mask >> i & 1u) kp.mout[i] = out[i];
+    const size_t esize = out_dtype == LBM_OUT_F32 ? 4 : 8;
+    if (h->L.dim == 3) {
+        for (int i = 6; i < 9; ++i)
+            if (mask >> i & 1u) kp.mout[i] = out[i];
+    } else {
+        if (mask & LBM_M_UX) kp.mout[6] = out[6];
+        if (mask & LBM_M_UY) kp.mout[8] = out[7];  // user y is the kernel z axis
+        if (mask & LBM_M_UZ) LBM_HIP(hipMemsetAsync(out[8], 0, esize * h->L.nodes, s));
+    }
+    kp.mout_f32 = out_dtype == LBM_OUT_F32;
+    if (mask) {
+        h->ks->fused(MODE_MOMENTS, h->L.grid, kp, s);
+        if (int r = launched("moments kernel")) return r;
+    }
+    return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!host_out) return fail(LBM_EINVAL, "host_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp = h->base;
+    set_slots(h, kp, h->copy[h->cur], nullptr);
+    h->ks->fused(MODE_DIAG, h->L.grid, kp, s);
+    launch_finalize(h->aux + 16, int(h->L.nparts), 8, 4, 1.0, h->aux + 8, s);
+    if (int r = launched("diagnostics kernels")) return r;
+    LBM_HIP(hipMemcpyAsync(host_out, h->aux + 8, LBM_NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
+    LBM_HIP(hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle* h, double* dst, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+    KParams kp = h->base;
+    set_slots(h, kp, h->copy[h->cur], nullptr);
+    h->ks->get_pops(kp, h->L.nslots, h->L.nodes, dst, static_cast<hipStream_t>(stream));
+    return launched("get_populations kernel");
+}
+
+int lbm_set_populations(lbm_handle* h, const double* src, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!src) return fail(LBM_EINVAL, "src is NULL");
+    KParams kp = h->base;
+    set_slots(h, kp, nullptr, h->copy[h->cur]);
+    h->ks->set_pops(kp, h->L.nslots, h->L.nodes, src, static_cast<hipStream_t>(stream));
+    return launched("set_populations kernel");
+}
+
+int lbm_save(lbm_handle* h, void* dst, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LBM_HIP(hipMemcpyAsync(dst, h->copy[h->cur], h->L.copy_bytes, hipMemcpyDeviceToDevice, s));
+    LBM_HIP(hipMemcpyAsync(static_cast<char*>(dst) + h->L.copy_bytes, h->aux, sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    return LBM_OK;
+}
+
+int lbm_restore(lbm_handle* h, const void* src, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!src) return fail(LBM_EINVAL, "src is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LBM_HIP(hipMemcpyAsync(h->copy[h->cur], src, h->L.copy_bytes, hipMemcpyDeviceToDevice, s));
+    LBM_HIP(hipMemcpyAsync(h->aux, static_cast<const char*>(src) + h->L.copy_bytes, sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
+
+void lbm_destroy(lbm_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Kernel parameter block and storage formats shared by the kernels and the host API.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+constexpr int kMaxSlots = 19 + 3 * 7;  // D3Q19 + 3 x D3Q7
+constexpr int kNumMom = 9;
+constexpr int kNumDiag = 8;
+
+enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
+enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2 };
+
+// Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
+// formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
+// FP16 / BF16 (round to nearest even) and keep the rest population (k = 0) in
+// FP32: the rest populations carry most of the conserved composition, so their
+// rounding would otherwise break mass conservation at the 16-bit level.
+template <int PREC> struct Stor;
+template <> struct Stor<P64> { using T = double; using R = double; using C = double; };
+template <> struct Stor<P32> { using T = float; using R = float; using C = float; };
+template <> struct Stor<P16> { using T = __half; using R = float; using C = float; };
+template <> struct Stor<PB16> { using T = __hip_bfloat16; using R = float; using C = float; };
+
+__host__ __device__ inline constexpr int slot_bytes(int prec, int k) {
+    return prec == P64 ? 8 : (prec == P32 ? 4 : (k == 0 ? 4 : 2));
+}
+
+struct KParams {
+    // grid (kernel frame: 2D problems live in the x-z plane with ny = 1)
+    int nx, ny, nz;
+    int wall_x, wall_y, wall_z;  // 1: half-way bounce-back walls on that axis
+    int zc;                      // planes marched per work-group
+    int mean_subtract;           // buoyancy uses phi - phi_ref
+    // model (Section 2), lattice units
+    double W, lam, mphi_w2;      // mphi_w2 = M_phi / W^2 = 1 / tau_phi
+    double c0A, c0B, c1A, c1B;   // equilibrium compositions of phases 0 and 1
+    double omega_g;              // g-lattice rate 1 / (M_phi / c_s^2 + 1/2)
+    double MA0, MA1, MB0, MB1;   // species mobilities per phase
+    double nu0, nu1, rho0, drho;
+    double gx, gy, gz;           // gravity in the kernel frame
+    double cap;                  // 3/2 sigma W of Eq. SurfaceTension_Force
+    double inv_W2;
+    // per-slot storage constants (canonical slot order): value = swref + d * sinv
+    // for 16-bit moving populations, d = (value - swref) * sscale on store;
+    // srest = 1 for rest populations (k = 0), stored in FP32 by the 16-bit formats
+    float swref[kMaxSlots], sscale[kMaxSlots], sinv[kMaxSlots];
+    int srest[kMaxSlots];
+    // device scalars
+    const double* phi_ref;       // buoyancy reference <phi> (aux area)
+    double* partials;            // per-work-group partial sums
+    // populations: canonical slot order f_0.., g_0.., hA_0.., hB_0..
+    const void* src[kMaxSlots];
+    void* dst[kMaxSlots];
+    // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame)
+    void* mout[kNumMom];
+    int mout_f32;
+};
+
+}  // namespace lbm

@@ -1,0 +1,270 @@
+"""Python binding of liblbm.so (include/lbm.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of the library; this module
+allocates device memory with torch, passes pointers and the current HIP stream,
+and turns return codes into exceptions.  It fails loudly when the library has
+not been built or no GPU is present: there is no CPU fallback.
+"""
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+# ---- constants of include/lbm.h ------------------------------------------------------
+LBM_OK, LBM_EINVAL, LBM_ESIZE, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_EHIP = 0, -1, -2, -3, -4, -5
+LBM_NONE, LBM_D2Q9, LBM_D3Q19, LBM_D2Q5, LBM_D3Q7 = 0, 9, 19, 5, 7
+LBM_PERIODIC, LBM_WALLS = 0, 1
+LBM_FP64, LBM_FP32, LBM_FP32_FP16STORE, LBM_FP32_BF16STORE = 0, 1, 2, 3
+LBM_OUT_F64, LBM_OUT_F32 = 0, 1
+MOMENTS = ("phi", "cA", "cB", "muA", "muB", "p", "ux", "uy", "uz")
+DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interface_measure",
+               "free_energy", "nan_count")
+PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP32_FP16STORE, "bf16": LBM_FP32_BF16STORE}
+_FLUID = {None: LBM_NONE, "none": LBM_NONE, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
+_SCALAR = {"D2Q5": LBM_D2Q5, "D3Q7": LBM_D3Q7}
+_BC = {"periodic": LBM_PERIODIC, "walls": LBM_WALLS}
+_ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ESIZE: "LBM_ESIZE", LBM_EUNSTABLE: "LBM_EUNSTABLE",
+             LBM_EUNSUPPORTED: "LBM_EUNSUPPORTED", LBM_EHIP: "LBM_EHIP"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("fluid", ctypes.c_int32), ("scalar", ctypes.c_int32), ("bc", ctypes.c_int32 * 3),
+        ("precision", ctypes.c_int32), ("gravity_mean_subtract", ctypes.c_int32),
+        ("W", ctypes.c_double), ("lambda_", ctypes.c_double), ("M_phi", ctypes.c_double),
+        ("M_A", ctypes.c_double * 2), ("M_B", ctypes.c_double * 2),
+        ("c_eq", (ctypes.c_double * 2) * 2),
+        ("rho0", ctypes.c_double), ("drho", ctypes.c_double), ("g", ctypes.c_double * 3),
+        ("sigma", ctypes.c_double), ("nu", ctypes.c_double * 2),
+        ("store_ref", ctypes.c_double * 4), ("store_shift", ctypes.c_int32 * 4),
+    ]
+
+
+_LIB = None
+
+# exported entry points and their ctypes signatures
+_SIGS = {
+    "lbm_state_bytes": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_checkpoint_bytes": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_init": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_void_p)]),
+    "lbm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    "lbm_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
+                                   ctypes.c_int32, ctypes.c_void_p]),
+    "lbm_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "lbm_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_restore": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_step_count": (ctypes.c_int64, [ctypes.c_void_p]),
+    "lbm_destroy": (None, [ctypes.c_void_p]),
+    "lbm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load liblbm.so once; raise if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_03401_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(code):
+    if code != LBM_OK:
+        raise LBMError(code, lib().lbm_last_error().decode())
+
+
+@dataclass
+class LBMConfig:
+    """Parameters in lattice units; mirrors ``lbm_config`` of include/lbm.h."""
+    nx: int
+    ny: int
+    nz: int = 1
+    fluid: Optional[str] = None
+    scalar: str = "D2Q5"
+    bc: Tuple[str, str, str] = ("periodic", "periodic", "periodic")
+    W: float = 4.0
+    lam: float = 1.0
+    M_phi: float = 0.1
+    M_A: Tuple[float, float] = (0.1, 0.1)
+    M_B: Tuple[float, float] = (0.1, 0.1)
+    c_eq: Tuple[Tuple[float, float], Tuple[float, float]] = ((0.2, 0.1), (0.6, 0.3))
+    rho0: float = 1.0
+    drho: float = 0.0
+    g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    sigma: float = 0.0
+    nu: Tuple[float, float] = (0.1, 0.1)
+    gravity_mean_subtract: bool = False
+    precision: str = "fp32"
+    # 16-bit storage: moving population k of field F (f, g, hA, hB) is stored as
+    # (x - w_k store_ref[F]) * 2^store_shift[F]
+    store_ref: Tuple[float, float, float, float] = (0.0, 0.5, 0.0, 0.0)
+    store_shift: Tuple[int, int, int, int] = (8, 0, 6, 6)
+
+    @property
+    def nodes(self):
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def qf(self):
+        return _FLUID[self.fluid]
+
+    @property
+    def qs(self):
+        return _SCALAR[self.scalar]
+
+    def to_c(self) -> _Config:
+        c = _Config()
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.fluid = _FLUID[self.fluid]
+        c.scalar = _SCALAR[self.scalar]
+        for a in range(3):
+            c.bc[a] = _BC[self.bc[a]]
+        c.precision = PRECISIONS[self.precision]
+        c.gravity_mean_subtract = int(bool(self.gravity_mean_subtract))
+        c.W, c.lambda_, c.M_phi = self.W, self.lam, self.M_phi
+        for i in range(2):
+            c.M_A[i], c.M_B[i], c.nu[i] = self.M_A[i], self.M_B[i], self.nu[i]
+            for a in range(2):
+                c.c_eq[i][a] = self.c_eq[i][a]
+        c.rho0, c.drho, c.sigma = self.rho0, self.drho, self.sigma
+        for a in range(3):
+            c.g[a] = self.g[a]
+        for i in range(4):
+            c.store_ref[i] = self.store_ref[i]
+            c.store_shift[i] = int(self.store_shift[i])
+        return c
+
+
+def state_bytes(cfg: LBMConfig) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_state_bytes(ctypes.byref(cfg.to_c()), ctypes.byref(n)))
+    return n.value
+
+
+def checkpoint_bytes(cfg: LBMConfig) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_checkpoint_bytes(ctypes.byref(cfg.to_c()), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(a, n, device):
+    t = torch.as_tensor(a, dtype=torch.float64, device=device).reshape(-1).contiguous()
+    if t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return t
+
+
+class Simulation:
+    """One domain on one GPU: state buffer (torch uint8 tensor) plus the library handle."""
+
+    def __init__(self, cfg: LBMConfig, phi0, muA0, muB0, device="cuda", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a GPU; none is visible")
+        L = lib()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self._c = cfg.to_c()
+        nbytes = state_bytes(cfg)
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        n = cfg.nodes
+        self._inputs = [_dev_f64(a, n, self.device) for a in (phi0, muA0, muB0)]
+        h = ctypes.c_void_p()
+        _check(L.lbm_init(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
+                          *[ctypes.c_void_p(t.data_ptr()) for t in self._inputs], _stream_ptr(stream),
+                          ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nslots(self):
+        return self.cfg.qf + 3 * self.cfg.qs
+
+    def step(self, n=1, stream=None):
+        _check(lib().lbm_step(self._h, int(n), _stream_ptr(stream)))
+
+    @property
+    def step_count(self):
+        return lib().lbm_step_count(self._h)
+
+    def moments(self, names: Sequence[str] = MOMENTS, dtype=torch.float64, stream=None) -> Dict[str, torch.Tensor]:
+        out_dtype = LBM_OUT_F64 if dtype == torch.float64 else LBM_OUT_F32
+        outs = {}
+        ptrs = (ctypes.c_void_p * len(MOMENTS))()
+        mask = 0
+        for i, name in enumerate(MOMENTS):
+            if name in names:
+                t = torch.empty(self.cfg.shape, dtype=dtype, device=self.device)
+                outs[name] = t
+                ptrs[i] = t.data_ptr()
+                mask |= 1 << i
+        _check(lib().lbm_moments(self._h, mask, ptrs, out_dtype, _stream_ptr(stream)))
+        return outs
+
+    def diagnostics(self, stream=None) -> Dict[str, float]:
+        out = (ctypes.c_double * len(DIAGNOSTICS))()
+        _check(lib().lbm_diagnostics(self._h, out, _stream_ptr(stream)))
+        return dict(zip(DIAGNOSTICS, list(out)))
+
+    def populations(self, stream=None) -> torch.Tensor:
+        """[slot][z][y][x] FP64 decoded populations: f_0.., g_0.., hA_0.., hB_0.."""
+        t = torch.empty((self.nslots,) + self.cfg.shape, dtype=torch.float64, device=self.device)
+        _check(lib().lbm_get_populations(self._h, ctypes.c_void_p(t.data_ptr()), _stream_ptr(stream)))
+        return t
+
+    def set_populations(self, pops, stream=None):
+        t = torch.as_tensor(pops, dtype=torch.float64, device=self.device).contiguous()
+        if t.numel() != self.nslots * self.cfg.nodes:
+            raise ValueError("wrong population count")
+        _check(lib().lbm_set_populations(self._h, ctypes.c_void_p(t.data_ptr()), _stream_ptr(stream)))
+        torch.cuda.current_stream().synchronize()
+
+    def save(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(checkpoint_bytes(self.cfg), dtype=torch.uint8, device=self.device)
+        _check(lib().lbm_save(self._h, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def restore(self, ckpt: torch.Tensor, stream=None):
+        _check(lib().lbm_restore(self._h, ctypes.c_void_p(ckpt.data_ptr()), _stream_ptr(stream)))

@@ -1,0 +1,70 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/lbm.h declares, and validates configurations without touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_03401_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.lib()
+    names = _declared()
+    assert "lbm_step" in names and "lbm_init" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_covers_header():
+    assert set(_declared()) <= set(lbm._SIGS)
+
+
+def test_struct_layout_matches_header():
+    # 10 int32 fields, then doubles; store_shift closes the struct
+    assert lbm._Config.W.offset == 40
+    assert ctypes.sizeof(lbm._Config) == lbm._Config.store_shift.offset + 16
+
+
+def _cfg(**kw):
+    base = dict(nx=32, ny=16, nz=1, W=4.0, lam=21.05, M_phi=0.1)
+    base.update(kw)
+    return lbm.LBMConfig(**base)
+
+
+def test_state_bytes_layout():
+    c = _cfg()
+    n = lbm.state_bytes(c)
+    # two copies of 15 FP32 slots, each rounded to 256 bytes, plus the reduction area
+    per_slot = (32 * 16 * 4 + 255) // 256 * 256
+    assert n >= 2 * 15 * per_slot
+    c16 = _cfg(nz=1, fluid="D2Q9", precision="bf16")
+    assert lbm.checkpoint_bytes(c16) < lbm.checkpoint_bytes(_cfg(fluid="D2Q9"))
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=0), lbm.LBM_EINVAL),
+    (dict(nz=4), lbm.LBM_EINVAL),                         # D2Q5 needs nz = 1
+    (dict(fluid="D3Q19"), lbm.LBM_EUNSUPPORTED),          # 3D fluid on a 2D scalar lattice
+    (dict(M_phi=0.0), lbm.LBM_EUNSTABLE),                 # rate 1/(tau + 1/2) = 2
+    (dict(M_A=(0.1, -0.01)), lbm.LBM_EUNSTABLE),
+    (dict(fluid="D2Q9", nu=(0.0, 0.1)), lbm.LBM_EUNSTABLE),
+    (dict(W=-1.0), lbm.LBM_EINVAL),
+    (dict(W=float("nan")), lbm.LBM_EINVAL),
+    (dict(gravity_mean_subtract=True), lbm.LBM_EINVAL),   # needs a fluid
+])
+def test_config_errors(kw, code):
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.state_bytes(_cfg(**kw))
+    assert e.value.code == code
+    assert lbm.lib().lbm_last_error().decode()
