@@ -31,22 +31,25 @@ CFLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, out: str = OUT, extra_flags=()) -> str:
+    """Compile and link.  `extra_flags` are appended to every hipcc line (for
+    tuning builds, e.g. -DLBM_WAVES_PER_EU=3); `out` is the library path."""
+    build_dir = BUILD_DIR if out == OUT else out + ".build"
+    os.makedirs(build_dir, exist_ok=True)
     t0 = time.time()
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *CFLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:
-        out, _ = p.communicate()
-        text = out.decode(errors="replace")
+        raw, _ = p.communicate()
+        text = raw.decode(errors="replace")
         if p.returncode != 0:
             failed.append((src, text))
         elif verbose and text.strip():
@@ -54,16 +57,22 @@ def build(verbose: bool = False) -> str:
     if failed:
         msg = "\n".join(f"--- {s} ---\n{t}" for s, t in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     link = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(link, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {OUT} in {time.time() - t0:.1f} s", flush=True)
-    return OUT
+        print(f"built {out} in {time.time() - t0:.1f} s", flush=True)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-q" not in sys.argv)
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-q", action="store_true")
+    ap.add_argument("--out", default=OUT)
+    ap.add_argument("flags", nargs="*", help="extra hipcc flags, e.g. -DLBM_WAVES_PER_EU=3")
+    a = ap.parse_args()
+    build(verbose=not a.q, out=os.path.abspath(a.out), extra_flags=a.flags)

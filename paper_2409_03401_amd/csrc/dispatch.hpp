@@ -13,12 +13,15 @@ struct KernelSet {
                  hipStream_t s);
     void (*get_pops)(const KParams& kp, int nslots, long long nodes, double* out, hipStream_t s);
     void (*set_pops)(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s);
+    // bounce-back fix-up on the two faces of one wall axis (0 x, 1 y, 2 z), after a step
+    void (*walls)(const KParams& kp, int axis, hipStream_t s);
     int tx, ty;  // work-group tile of the fused kernel
 };
 
-// fluid: 0 (none) or 9 / 19; prec: Prec.  nullptr for unsupported combinations.
-const KernelSet* kernels_2d(int fluid, int prec);
-const KernelSet* kernels_3d(int fluid, int prec);
+// fluid: 0 (none) or 9 / 19; prec: Prec; (tx, ty): work-group tile, 0 for the
+// default.  nullptr for unsupported combinations.
+const KernelSet* kernels_2d(int fluid, int prec, int tx);
+const KernelSet* kernels_3d(int fluid, int prec, int tx, int ty);
 
 void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
 void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,

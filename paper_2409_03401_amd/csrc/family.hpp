@@ -28,15 +28,22 @@ struct Family {
         const dim3 grid((kp.nx + 255) / 256, kp.ny, kp.nz);
         hipLaunchKernelGGL((k_init<SL, FL, PREC>), grid, dim3(256), 0, s, kp, phi0, muA0, muB0);
     }
-    static void get_pops(const KParams& kp, int nslots, long long nodes, double* out, hipStream_t s) {
-        const dim3 grid(unsigned((nodes + 255) / 256), nslots);
-        hipLaunchKernelGGL((k_get_pops<PREC>), grid, dim3(256), 0, s, kp, nslots, nodes, out);
+    static void get_pops(const KParams& kp, int, long long nodes, double* out, hipStream_t s) {
+        const dim3 grid(unsigned((nodes + 255) / 256));
+        hipLaunchKernelGGL((k_pops<SL, FL, PREC, false>), grid, dim3(256), 0, s, kp, nodes, out);
     }
-    static void set_pops(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s) {
-        const dim3 grid(unsigned((nodes + 255) / 256), nslots);
-        hipLaunchKernelGGL((k_set_pops<PREC>), grid, dim3(256), 0, s, kp, nslots, nodes, in);
+    static void set_pops(const KParams& kp, int, long long nodes, const double* in, hipStream_t s) {
+        const dim3 grid(unsigned((nodes + 255) / 256));
+        hipLaunchKernelGGL((k_pops<SL, FL, PREC, true>), grid, dim3(256), 0, s, kp, nodes,
+                           const_cast<double*>(in));
     }
-    static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, TX, TY};
+    static void walls(const KParams& kp, int axis, hipStream_t s) {
+        const long long n[3] = {kp.nx, kp.ny, kp.nz};
+        const long long face = n[axis == 0 ? 1 : 0] * n[axis == 2 ? 1 : 2];
+        const dim3 grid(unsigned((2 * face + 255) / 256));
+        hipLaunchKernelGGL((k_walls<SL, FL, PREC>), grid, dim3(256), 0, s, kp, axis);
+    }
+    static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, &walls, TX, TY};
 };
 
 template <class SL, class FL, int TX, int TY>

@@ -1,15 +1,22 @@
 // HIP kernels of the coupled lattice-Boltzmann step for gfx950.
 //
-// One fused kernel per (lattice family, mode, storage precision).  A work-group
-// owns a TX x TY column of nodes and marches along z over `zc` planes.  When the
-// capillary force (or the free-energy diagnostic) needs grad phi and lap phi,
-// phi of three consecutive planes, each with a one-node ring, is staged in LDS:
-// the work-group computes phi of plane z+1 (its own nodes from registers kept for
-// the next iteration, ring nodes from L2-resident neighbour populations), then
-// updates plane z.  Populations live in two copies (read one, write the other),
-// so ring reads never race with writes.  Streaming is a push: each node writes
-// its post-collision populations into the neighbour slots of the other copy,
-// or back into its own node in the opposite direction across a wall.
+// One fused kernel per (lattice family, mode, storage precision, tile).  A
+// work-group owns a TX x TY column of nodes and marches along z over `zc` planes.
+// When the capillary force (or the free-energy diagnostic) needs grad phi and
+// lap phi, phi of three consecutive planes, each with a one-node ring, is staged
+// in LDS: the work-group computes phi of plane z+1 (its own nodes from registers
+// kept for the next iteration, ring nodes from L2-resident neighbour
+// populations), then updates plane z.  Populations live in two copies (read one,
+// write the other), so ring reads never race with writes.  Streaming is a pull:
+// a copy holds post-collision populations; each node gathers X_k from x - e_k
+// (periodic wrap), collides, and writes its post-collision populations to its
+// own slots, so every store is aligned.  Half-way bounce-back at walls is a
+// small fix-up kernel after the step (k_walls).
+//
+// Memory layout of one copy: a sequence of slots, one [node] array per
+// (field, direction) in the canonical order f_0.., g_0.., hA_0.., hB_0...  Every
+// slot base is wave-uniform (SGPR) and every access uses a 32-bit per-lane
+// offset, so each load / store is one `global_* voffset, saddr` instruction.
 #pragma once
 
 #include <type_traits>
@@ -56,46 +63,7 @@ __device__ __forceinline__ Scalars node_scalars(double phis, double cA, double c
 }
 
 // ---------------------------------------------------------------------------
-// population storage
-
-template <int PREC>
-__device__ __forceinline__ typename Stor<PREC>::C ld_pop(const void* base, int idx, bool rest,
-                                                         float wref, float inv_scale) {
-    if constexpr (PREC == P64) {
-        return static_cast<const double*>(base)[idx];
-    } else if constexpr (PREC == P32) {
-        return static_cast<const float*>(base)[idx];
-    } else {
-        if (rest) return static_cast<const float*>(base)[idx];
-        using T = typename Stor<PREC>::T;
-        const T d = static_cast<const T*>(base)[idx];
-        float v;
-        if constexpr (PREC == P16) v = __half2float(d);
-        else v = __bfloat162float(d);
-        return fmaf(v, inv_scale, wref);
-    }
-}
-
-template <int PREC>
-__device__ __forceinline__ void st_pop(void* base, int idx, bool rest, float wref, float scale,
-                                       typename Stor<PREC>::C v) {
-    if constexpr (PREC == P64) {
-        static_cast<double*>(base)[idx] = v;
-    } else if constexpr (PREC == P32) {
-        static_cast<float*>(base)[idx] = v;
-    } else {
-        if (rest) {
-            static_cast<float*>(base)[idx] = v;
-            return;
-        }
-        using T = typename Stor<PREC>::T;
-        const float d = (v - wref) * scale;
-        T q;
-        if constexpr (PREC == P16) q = __float2half_rn(d);
-        else q = __float2bfloat16(d);
-        static_cast<T*>(base)[idx] = q;
-    }
-}
+// helpers
 
 // compile-time loop: f(std::integral_constant<int, k>) for k in [B, E)
 template <int B, int E, class F>
@@ -106,11 +74,155 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// e . v for a lattice vector with components in {-1, 0, 1}, without the zero terms
+template <int EX, int EY, int EZ, class C>
+__device__ __forceinline__ C edot(C a, C b, C c) {
+    C r = C(0);
+    if constexpr (EX != 0) r = EX > 0 ? a : -a;
+    if constexpr (EY != 0) {
+        if constexpr (EX != 0) r += EY > 0 ? b : -b;
+        else r = EY > 0 ? b : -b;
+    }
+    if constexpr (EZ != 0) {
+        if constexpr (EX != 0 || EY != 0) r += EZ > 0 ? c : -c;
+        else r = EZ > 0 ? c : -c;
+    }
+    return r;
+}
+
+// 1/x: exact in FP64, the hardware reciprocal (1 ulp) in FP32
+template <class C>
+__device__ __forceinline__ C rcp(C x) {
+    if constexpr (std::is_same<C, double>::value) return 1.0 / x;
+    else return __builtin_amdgcn_rcpf(x);
+}
+
+// Work-groups are handed to the 8 XCDs of the chip round-robin by linear id.
+// Remap so that XCD j owns the contiguous range of tiles [j N / 8, (j + 1) N / 8):
+// tiles that share phi-halo cache lines then run on the same XCD and meet in
+// its L2 instead of each fetching the lines from memory.
+__device__ __forceinline__ int xcd_tile(int w, int n) {
+    constexpr int kXcd = 8;
+    const int base = n / kXcd, rem = n % kXcd;
+    const int j = w % kXcd, local = w / kXcd;
+    return j < rem ? j * (base + 1) + local : rem * (base + 1) + (j - rem) * base + local;
+}
+
 // periodic wrap / mirror ghost of a coordinate in [-1, n]
 __device__ __forceinline__ int map_coord(int c, int n, int wall) {
     if (c < 0) return wall ? 0 : n - 1;
     if (c >= n) return wall ? n - 1 : 0;
     return c;
+}
+
+// index offsets of the six axis neighbours of node (x, y, z), periodic wrap folded in
+struct Nbr {
+    int xp, xm, yp, ym, zp, zm;
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, int z, const KParams& P) {
+    const int nxny = P.nx * P.ny;
+    Nbr n;
+    n.xp = (x + 1 < P.nx) ? 1 : 1 - P.nx;
+    n.xm = (x > 0) ? -1 : P.nx - 1;
+    n.yp = (y + 1 < P.ny) ? P.nx : (1 - P.ny) * P.nx;
+    n.ym = (y > 0) ? -P.nx : (P.ny - 1) * P.nx;
+    n.zp = (z + 1 < P.nz) ? nxny : (1 - P.nz) * nxny;
+    n.zm = (z > 0) ? -nxny : (P.nz - 1) * nxny;
+    return n;
+}
+
+// offset of the node x - e that a population moving along e arrives from (pull)
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ int pull_offset(const Nbr& n) {
+    int d = 0;
+    if constexpr (EX > 0) d += n.xm;
+    if constexpr (EX < 0) d += n.xp;
+    if constexpr (EY > 0) d += n.ym;
+    if constexpr (EY < 0) d += n.yp;
+    if constexpr (EZ > 0) d += n.zm;
+    if constexpr (EZ < 0) d += n.zp;
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// population storage
+
+// slot bookkeeping of one lattice family: rest slots (k = 0) are f_0, g_0, hA_0, hB_0
+template <int QF, int QS>
+struct Slots {
+    static constexpr int G0 = QF, A0 = QF + QS, B0 = QF + 2 * QS, N = QF + 3 * QS;
+    __host__ __device__ static constexpr bool rest(int s) {
+        return (QF > 0 && s == 0) || s == G0 || s == A0 || s == B0;
+    }
+    __host__ __device__ static constexpr int rest_before(int s) {
+        return (QF > 0 && s > 0 ? 1 : 0) + (s > G0 ? 1 : 0) + (s > A0 ? 1 : 0) + (s > B0 ? 1 : 0);
+    }
+    __host__ __device__ static constexpr int field(int s) {
+        return s < G0 ? 0 : (s < A0 ? 1 : (s < B0 ? 2 : 3));
+    }
+};
+
+// byte offset of slot S in a copy (moving slots take stride_m bytes, rest slots stride_r)
+template <class SLOTS, int S>
+__device__ __forceinline__ unsigned long long slot_offset(const KParams& P) {
+    constexpr int rb = SLOTS::rest_before(S);
+    return (unsigned long long)(S - rb) * P.stride_m + (unsigned long long)rb * P.stride_r;
+}
+
+// load one population at node idx and decode it to the compute type
+template <int PREC, bool REST>
+__device__ __forceinline__ typename Stor<PREC>::C ld_at(const char* slot, unsigned idx, float wref,
+                                                        float inv_scale) {
+    if constexpr (PREC == P64) {
+        return *reinterpret_cast<const double*>(slot + idx * 8u);
+    } else if constexpr (PREC == P32 || REST) {
+        return *reinterpret_cast<const float*>(slot + idx * 4u);
+    } else {
+        const unsigned short bits = *reinterpret_cast<const unsigned short*>(slot + idx * 2u);
+        float v;
+        if constexpr (PREC == P16) v = __half2float(__ushort_as_half(bits));
+        else v = float(__builtin_bit_cast(__bf16, bits));
+        return fmaf(v, inv_scale, wref);
+    }
+}
+
+// encode and store one population; populations written by a step are read again
+// only in the next step, so they stream past the caches (non-temporal stores)
+template <int PREC, bool REST>
+__device__ __forceinline__ void st_at(char* slot, unsigned idx, float wref, float scale,
+                                      typename Stor<PREC>::C v) {
+    if constexpr (PREC == P64) {
+        __builtin_nontemporal_store(v, reinterpret_cast<double*>(slot + idx * 8u));
+    } else if constexpr (PREC == P32 || REST) {
+        __builtin_nontemporal_store(float(v), reinterpret_cast<float*>(slot + idx * 4u));
+    } else {
+        const float d = (v - wref) * scale;
+        unsigned short bits;
+        if constexpr (PREC == P16) bits = __half_as_ushort(__float2half_rn(d));
+        else bits = __builtin_bit_cast(unsigned short, __bf16(d));  // round to nearest even
+        __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short*>(slot + idx * 2u));
+    }
+}
+
+// runtime-slot variants (generic copy kernels)
+template <int PREC>
+__device__ __forceinline__ typename Stor<PREC>::C ld_pop(const void* base, int idx, bool rest,
+                                                         float wref, float inv_scale) {
+    const char* p = static_cast<const char*>(base);
+    if (rest) return ld_at<PREC, true>(p, unsigned(idx), wref, inv_scale);
+    return ld_at<PREC, false>(p, unsigned(idx), wref, inv_scale);
+}
+
+template <int PREC>
+__device__ __forceinline__ void st_pop(void* base, int idx, bool rest, float wref, float scale,
+                                       typename Stor<PREC>::C v) {
+    char* p = static_cast<char*>(base);
+    if (rest) st_at<PREC, true>(p, unsigned(idx), wref, scale, v);
+    else st_at<PREC, false>(p, unsigned(idx), wref, scale, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -148,9 +260,32 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 // ---------------------------------------------------------------------------
 // the fused step / moments / diagnostics kernel
 
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 1
+#endif
+#ifndef LBM_EARLY_F
+#define LBM_EARLY_F 1
+#endif
+#ifndef LBM_LDS_POPS
+#define LBM_LDS_POPS 1
+#endif
+#ifndef LBM_PTR_ARRAY
+#define LBM_PTR_ARRAY 0
+#endif
+#ifndef LBM_PHASES
+#define LBM_PHASES 0
+#endif
+// scheduling fence between phases of the collision (bounds register live ranges)
+#define LBM_FENCE()                                          \
+    do {                                                     \
+        if constexpr (LBM_PHASES) __builtin_amdgcn_sched_barrier(0); \
+    } while (0)
+
 template <class SL, class FL, int MODE, int PREC, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+k_lbm(const KParams P) {
     using C = typename Stor<PREC>::C;
+    using SLOTS = Slots<FL::Q, SL::Q>;
     constexpr int QS = SL::Q;
     constexpr int QF = FL::Q;
     constexpr bool FLOW = QF > 0;
@@ -162,27 +297,64 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
     constexpr int OY = HAS_Y ? 1 : 0;
     constexpr int NSLOT = STENCIL ? 3 : 1;
     constexpr int NT = TX * TY;
-    constexpr int G0 = QF, A0 = QF + QS, B0 = QF + 2 * QS;  // slot offsets
+    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
     constexpr C inv_cs2s = C(1.0 / SL::cs2);
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
 
     __shared__ C sphi[NSLOT][LY][LX];
+    // this thread's own scalar populations of the current and the next plane
+    // (thread-private ring of two planes, [plane][slot][thread], no barriers needed)
+    __shared__ C spop[(STENCIL && LBM_LDS_POPS) ? 2 : 1][(STENCIL && LBM_LDS_POPS) ? 3 * QS : 1]
+                     [(STENCIL && LBM_LDS_POPS) ? NT : 1];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int x = blockIdx.x * TX + tx;
-    const int y = blockIdx.y * TY + ty;
+    // tile of this work-group: x fastest, then y, then the z chunk
+    const int tile = xcd_tile(blockIdx.x, P.tiles_x * P.tiles_y * P.tiles_z);
+    const int bx = tile % P.tiles_x;
+    const int by = (tile / P.tiles_x) % P.tiles_y;
+    const int bz = tile / (P.tiles_x * P.tiles_y);
+    const int x = bx * TX + tx;
+    const int y = by * TY + ty;
     const bool active = (x < P.nx) && (y < P.ny);
-    const int z0 = blockIdx.z * P.zc;
+    const int z0 = bz * P.zc;
     const int z1 = min(z0 + P.zc, P.nz);
 
-    auto load_scalars = [&](int idx, C (&gg)[QS], C (&aa)[QS], C (&bb)[QS], double& phis,
-                            double& cA, double& cB) __attribute__((always_inline)) {
+    using SLT = std::common_type<SL>;  // type tags of the lattices
+    using FLT = std::common_type<FL>;
+
+    // wave-uniform slot bases of the source and destination copies
+    auto src = [&](auto s_) __attribute__((always_inline)) -> const char* {
+        if constexpr (LBM_PTR_ARRAY) return static_cast<const char*>(P.src[decltype(s_)::value]);
+        else return P.src_base + slot_offset<SLOTS, decltype(s_)::value>(P);
+    };
+    auto dst = [&](auto s_) __attribute__((always_inline)) -> char* {
+        if constexpr (LBM_PTR_ARRAY) return static_cast<char*>(P.dst[decltype(s_)::value]);
+        else return P.dst_base + slot_offset<SLOTS, decltype(s_)::value>(P);
+    };
+    // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
+    auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {
+        using L = typename decltype(lat_)::type;
+        return float(L::w(decltype(k_)::value)) * P.fref[SLOTS::field(decltype(s_)::value)];
+    };
+    auto load = [&](auto s_, auto k_, auto lat_, unsigned idx) __attribute__((always_inline)) -> C {
+        constexpr int S = decltype(s_)::value;
+        return ld_at<PREC, SLOTS::rest(S)>(src(s_), idx, wref(s_, k_, lat_), P.finv[SLOTS::field(S)]);
+    };
+    auto store = [&](auto s_, auto k_, auto lat_, unsigned idx, C v) __attribute__((always_inline)) {
+        constexpr int S = decltype(s_)::value;
+        st_at<PREC, SLOTS::rest(S)>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[SLOTS::field(S)], v);
+    };
+
+    // scalar populations arriving at node idx (pull from idx - e_k)
+    auto load_scalars = [&](unsigned idx, const Nbr& nb, C (&gg)[QS], C (&aa)[QS], C (&bb)[QS],
+                            double& phis, double& cA, double& cB) __attribute__((always_inline)) {
         static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            gg[k] = ld_pop<PREC>(P.src[G0 + k], idx, k == 0, P.swref[G0 + k], P.sinv[G0 + k]);
-            aa[k] = ld_pop<PREC>(P.src[A0 + k], idx, k == 0, P.swref[A0 + k], P.sinv[A0 + k]);
-            bb[k] = ld_pop<PREC>(P.src[B0 + k], idx, k == 0, P.swref[B0 + k], P.sinv[B0 + k]);
+            const unsigned src_idx = unsigned(int(idx) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
+            gg[k] = load(IC<G0 + k>{}, kc, SLT{}, src_idx);
+            aa[k] = load(IC<A0 + k>{}, kc, SLT{}, src_idx);
+            bb[k] = load(IC<B0 + k>{}, kc, SLT{}, src_idx);
         });
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -199,7 +371,7 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
     auto node_phi = [&](int xx, int yy, int zz) __attribute__((always_inline)) -> C {
         C tg[QS], ta[QS], tb[QS];
         double ps, ca, cb;
-        load_scalars((zz * P.ny + yy) * P.nx + xx, tg, ta, tb, ps, ca, cb);
+        load_scalars(unsigned((zz * P.ny + yy) * P.nx + xx), neighbours(xx, yy, zz, P), tg, ta, tb, ps, ca, cb);
         return C(node_scalars(ps, ca, cb, P).phi);
     };
 
@@ -208,12 +380,23 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
     double c_ps = 0.0, c_cA = 0.0, c_cB = 0.0, n_ps = 0.0, n_cA = 0.0, n_cB = 0.0;
 
     // phi of plane zz (tile + ring) into LDS slot `slot`; this thread's own node
-    // populations go to (gg, aa, bb) when the node is inside the domain
-    auto fill_plane = [&](int zz, int slot, C (&gg)[QS], C (&aa)[QS], C (&bb)[QS], double& ps,
-                          double& cA, double& cB) __attribute__((always_inline)) {
+    // populations go to the private LDS ring entry `pbuf` when the node is inside
+    auto fill_plane = [&](int zz, int slot, int pbuf, double& ps, double& cA, double& cB)
+                          __attribute__((always_inline)) {
         const int zm = map_coord(zz, P.nz, P.wall_z);
         if (active) {
-            load_scalars((zm * P.ny + y) * P.nx + x, gg, aa, bb, ps, cA, cB);
+            if constexpr (LBM_LDS_POPS) {
+                C gg[QS], aa[QS], bb[QS];
+                load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), gg, aa, bb, ps, cA, cB);
+#pragma unroll
+                for (int k = 0; k < QS; ++k) {
+                    spop[pbuf][k][tid] = gg[k];
+                    spop[pbuf][QS + k][tid] = aa[k];
+                    spop[pbuf][2 * QS + k][tid] = bb[k];
+                }
+            } else {
+                load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), ng, na, nb, ps, cA, cB);
+            }
             sphi[slot][ty + OY][tx + 1] = C(node_scalars(ps, cA, cB, P).phi);
         } else if (x <= P.nx && y <= P.ny) {
             // ghost column / row just beyond the domain edge
@@ -232,8 +415,8 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
                 hx = (i == 0) ? 0 : LX - 1;
                 hy = 0;
             }
-            const int gx = int(blockIdx.x * TX) + hx - 1;
-            const int gy = HAS_Y ? int(blockIdx.y * TY) + hy - 1 : 0;
+            const int gx = bx * TX + hx - 1;
+            const int gy = HAS_Y ? by * TY + hy - 1 : 0;
             if (gx > P.nx || gy > P.ny) continue;  // beyond the ghost layer: never read
             sphi[slot][hy][hx] = node_phi(map_coord(gx, P.nx, P.wall_x),
                                           HAS_Y ? map_coord(gy, P.ny, P.wall_y) : 0, zm);
@@ -249,58 +432,89 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
 
     if constexpr (STENCIL) {
         if (z0 < z1) {
-            fill_plane(z0 - 1, 0, ng, na, nb, n_ps, n_cA, n_cB);  // ring only; registers discarded
-            fill_plane(z0, 1, cg, ca, cb, c_ps, c_cA, c_cB);
+            fill_plane(z0 - 1, 0, 1, n_ps, n_cA, n_cB);  // ring only; own entries overwritten next
+            fill_plane(z0, 1, 0, c_ps, c_cA, c_cB);
+            if constexpr (!LBM_LDS_POPS) {
+#pragma unroll
+                for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
+            }
         }
     }
 
     for (int z = z0; z < z1; ++z) {
         int sm = 0, sc = 0, sp = 0;
+        const unsigned idx = unsigned((z * P.ny + y) * P.nx + x);
+        const Nbr nbr = neighbours(x, y, z, P);
+        C fpop[QF > 0 ? QF : 1];
+        auto load_f = [&]() __attribute__((always_inline)) {
+            if constexpr (FLOW) {
+                if (active) {
+                    static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                        constexpr int k = decltype(kc)::value;
+                        const unsigned src_idx =
+                            unsigned(int(idx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(nbr));
+                        fpop[k] = load(kc, kc, FLT{}, src_idx);
+                    });
+                }
+            }
+        };
+        // fluid populations of this node do not depend on the LDS plane: with
+        // LBM_EARLY_F they are issued before the plane fill to overlap its latency
+        if constexpr (LBM_EARLY_F) load_f();
         if constexpr (STENCIL) {
             sm = (z - z0) % 3;
             sc = (z - z0 + 1) % 3;
             sp = (z - z0 + 2) % 3;
-            fill_plane(z + 1, sp, ng, na, nb, n_ps, n_cA, n_cB);
+            fill_plane(z + 1, sp, (z - z0 + 1) & 1, n_ps, n_cA, n_cB);
             __syncthreads();
+            if constexpr (LBM_LDS_POPS) {
+                if (active) {
+                    const int pb = (z - z0) & 1;
+#pragma unroll
+                    for (int k = 0; k < QS; ++k) {
+                        cg[k] = spop[pb][k][tid];
+                        ca[k] = spop[pb][QS + k][tid];
+                        cb[k] = spop[pb][2 * QS + k][tid];
+                    }
+                }
+            }
         } else {
-            if (active) load_scalars((z * P.ny + y) * P.nx + x, cg, ca, cb, c_ps, c_cA, c_cB);
+            if (active) load_scalars(idx, nbr, cg, ca, cb, c_ps, c_cA, c_cB);
         }
+        if constexpr (!LBM_EARLY_F) load_f();
         const C(&g)[QS] = cg;
         const C(&a)[QS] = ca;
         const C(&b)[QS] = cb;
         const double sA = c_cA, sB = c_cB;
 
         if (active) {
-            const int idx = (z * P.ny + y) * P.nx + x;
             const Scalars m = node_scalars(c_ps, sA, sB, P);
             const C phi = C(m.phi);
 
+            // isotropic gradient and Laplacian, Eqs. Grad and Laplacian (fluid lattice)
             C grad[3] = {C(0), C(0), C(0)};
             C lap = C(0);
             if constexpr (STENCIL) {
                 const C pc = sphi[sc][ty + OY][tx + 1];
-#pragma unroll
-                for (int k = 1; k < STL::Q; ++k) {
-                    const int ez = STL::ez(k);
+                C nsum = C(0);  // 3 sum_{k != 0} w_k phi(x + e_k)
+                static_for<1, STL::Q>([&](auto kc) __attribute__((always_inline)) {
+                    constexpr int k = decltype(kc)::value;
+                    constexpr int ex = STL::ex(k), ey = STL::ey(k), ez = STL::ez(k);
                     const int slot = ez == 0 ? sc : (ez > 0 ? sp : sm);
-                    const C v = sphi[slot][ty + OY + STL::ey(k)][tx + 1 + STL::ex(k)];
-                    const C w3 = C(3.0 * STL::w(k));
-                    grad[0] += w3 * C(STL::ex(k)) * v;
-                    grad[1] += w3 * C(STL::ey(k)) * v;
-                    grad[2] += w3 * C(STL::ez(k)) * v;
-                    lap += C(2.0) * w3 * (v - pc);
-                }
+                    const C v = sphi[slot][ty + OY + ey][tx + 1 + ex];
+                    const C wv = C(3.0 * STL::w(k)) * v;
+                    if constexpr (ex != 0) grad[0] += ex > 0 ? wv : -wv;
+                    if constexpr (ey != 0) grad[1] += ey > 0 ? wv : -wv;
+                    if constexpr (ez != 0) grad[2] += ez > 0 ? wv : -wv;
+                    nsum += wv;
+                });
+                lap = C(2) * (nsum - C(3.0 * (1.0 - STL::w(0))) * pc);
             }
 
             C u[3] = {C(0), C(0), C(0)};
             C p_h = C(0);
-            C fpop[QF > 0 ? QF : 1];
             C F[3] = {C(0), C(0), C(0)};
             if constexpr (FLOW) {
-                static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
-                    constexpr int k = decltype(kc)::value;
-                    fpop[k] = ld_pop<PREC>(P.src[k], idx, k == 0, P.swref[k], P.sinv[k]);
-                });
                 // Eq. SurfaceTension_Force plus buoyancy (phi - phi_ref) drho g
                 const C bracket = C(P.cap) * (C(dwell_d(m.phi)) * C(P.inv_W2) - lap);
                 const C buoy = C((m.phi - phi_ref) * P.drho);
@@ -309,13 +523,13 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
                 F[2] = buoy * C(P.gz) + bracket * grad[2];
                 // Eqs. HydroPressure and Velocity
                 C j0 = C(0), j1 = C(0), j2 = C(0);
-#pragma unroll
-                for (int k = 0; k < QF; ++k) {
+                static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                    constexpr int k = decltype(kc)::value;
                     p_h += fpop[k];
-                    if (FL::ex(k)) j0 += C(FL::ex(k)) * fpop[k];
-                    if (FL::ey(k)) j1 += C(FL::ey(k)) * fpop[k];
-                    if (FL::ez(k)) j2 += C(FL::ez(k)) * fpop[k];
-                }
+                    if constexpr (FL::ex(k) != 0) j0 += FL::ex(k) > 0 ? fpop[k] : -fpop[k];
+                    if constexpr (FL::ey(k) != 0) j1 += FL::ey(k) > 0 ? fpop[k] : -fpop[k];
+                    if constexpr (FL::ez(k) != 0) j2 += FL::ez(k) > 0 ? fpop[k] : -fpop[k];
+                });
                 const C inv_rho0 = C(1.0 / P.rho0);
                 u[0] = (C(3) * j0 + C(0.5) * F[0]) * inv_rho0;
                 u[1] = (C(3) * j1 + C(0.5) * F[1]) * inv_rho0;
@@ -325,95 +539,84 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
             if constexpr (MODE == MODE_STEP) {
                 if (P.mean_subtract) acc[0] += m.phi;
 
-                // ---- streaming targets ----
-                // push the post-collision value of slot S (direction (ex, ey, ez)) to the
-                // neighbour; across a wall it returns to this node in slot SOPP
-                auto push = [&](auto sc_, auto sopp_, int ex, int ey, int ez, C v) __attribute__((always_inline)) {
-                    constexpr int S = decltype(sc_)::value;
-                    constexpr int SOPP = decltype(sopp_)::value;
-                    int xt = x + ex, yt = y + ey, zt = z + ez;
-                    bool bounce = false;
-                    if (ex) {
-                        if (xt < 0 || xt >= P.nx) { if (P.wall_x) bounce = true; else xt = xt < 0 ? P.nx - 1 : 0; }
-                    }
-                    if (ey) {
-                        if (yt < 0 || yt >= P.ny) { if (P.wall_y) bounce = true; else yt = yt < 0 ? P.ny - 1 : 0; }
-                    }
-                    if (ez) {
-                        if (zt < 0 || zt >= P.nz) { if (P.wall_z) bounce = true; else zt = zt < 0 ? P.nz - 1 : 0; }
-                    }
-                    if (bounce)
-                        st_pop<PREC>(P.dst[SOPP], idx, false, P.swref[SOPP], P.sscale[SOPP], v);
-                    else
-                        st_pop<PREC>(P.dst[S], (zt * P.ny + yt) * P.nx + xt, P.srest[S] != 0, P.swref[S],
-                                     P.sscale[S], v);
+                // post-collision populations go to this node's own slots of the other copy
+                auto push = [&](auto s_, auto k_, auto lat_, C v) __attribute__((always_inline)) {
+                    store(s_, k_, lat_, idx, v);
                 };
 
                 // ---- f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq ----
+                // f* = (1 - w) f + w w_k [p + rho0 (eu + 3/2 eu^2 - uu/2)] + (1 - w/2) F_k,
+                // F_k = w_k [1 + 3 eu + 9/2 eu^2 - 3/2 uu] (e_k . F - u . F)
                 if constexpr (FLOW) {
                     const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                    const C uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
                     const C nu = C(P.nu0 * (1.0 - m.phi) + P.nu1 * m.phi);
-                    const C wf = C(1) / (C(3) * nu + C(0.5));
+                    const C wf = rcp<C>(C(3) * nu + C(0.5));
+                    const C keep = C(1) - wf, half = C(1) - C(0.5) * wf;
                     const C rho0 = C(P.rho0);
+                    const C g0 = C(1) - C(1.5) * uu, e0 = p_h - C(0.5) * rho0 * uu;
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
-                        const C eu = C(FL::ex(k)) * u[0] + C(FL::ey(k)) * u[1] + C(FL::ez(k)) * u[2];
+                        constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
                         const C wk = C(FL::w(k));
-                        const C gam = wk * (C(1) + C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-                        const C Fk = gam * ((C(FL::ex(k)) - u[0]) * F[0] + (C(FL::ey(k)) - u[1]) * F[1] +
-                                            (C(FL::ez(k)) - u[2]) * F[2]);
-                        const C feq = wk * (p_h + rho0 * (eu + C(1.5) * eu * eu - C(0.5) * uu)) - C(0.5) * Fk;
-                        const C post = fpop[k] - wf * (fpop[k] - feq) + Fk;
-                        push(std::integral_constant<int, k>{}, std::integral_constant<int, FL::opp(k)>{},
-                             FL::ex(k), FL::ey(k), FL::ez(k), post);
+                        const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
+                        const C eF = edot<ex, ey, ez>(F[0], F[1], F[2]);
+                        const C gam = wk * (g0 + eu * (C(3) + C(4.5) * eu));
+                        const C Fk = gam * (eF - uF);
+                        const C feq = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu));
+                        push(kc, kc, FLT{}, keep * fpop[k] + wf * feq + half * Fk);
                     });
                 }
 
+                LBM_FENCE();
                 // ---- g: Eqs. LBE_Phi, Geq, Source_LBE_Phi ----
+                // g* = (1 - w) g + w w_k phi (1 + eu / c_s^2) + (1 - w/2) w_k S
                 {
                     const C wg = C(P.omega_g);
-                    const C S = C(m.S);
+                    const C keep = C(1) - wg;
+                    const C wphi = wg * phi;
+                    const C srcS = (C(1) - C(0.5) * wg) * C(m.S);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
-                        const C eu = C(SL::ex(k)) * u[0] + C(SL::ey(k)) * u[1] + C(SL::ez(k)) * u[2];
-                        const C Gk = C(SL::w(k)) * S;
-                        const C geq = C(SL::w(k)) * phi * (C(1) + eu * inv_cs2s) - C(0.5) * Gk;
-                        const C post = g[k] - wg * (g[k] - geq) + Gk;
-                        push(std::integral_constant<int, G0 + k>{}, std::integral_constant<int, G0 + SL::opp(k)>{},
-                             SL::ex(k), SL::ey(k), SL::ez(k), post);
+                        constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                        const C wk = C(SL::w(k));
+                        C eq = wphi;
+                        if constexpr (ex != 0 || ey != 0 || ez != 0)
+                            eq = wphi * (C(1) + edot<ex, ey, ez>(u[0], u[1], u[2]) * inv_cs2s);
+                        push(IC<G0 + k>{}, kc, SLT{}, keep * g[k] + wk * (eq + srcS));
                     });
                 }
 
+                LBM_FENCE();
                 // ---- h^A, h^B: Eqs. LBE_c_alpha, Heq; mobility interpolated in phi ----
                 {
-                    const double MA = P.MA0 * (1.0 - m.phi) + P.MA1 * m.phi;
-                    const double MB = P.MB0 * (1.0 - m.phi) + P.MB1 * m.phi;
-                    const double whA = 1.0 / (MA / SL::cs2 + 0.5);
-                    const double whB = 1.0 / (MB / SL::cs2 + 0.5);
+                    const C MA = C(P.MA0) * (C(1) - phi) + C(P.MA1) * phi;
+                    const C MB = C(P.MB0) * (C(1) - phi) + C(P.MB1) * phi;
+                    const C wA = rcp<C>(MA * inv_cs2s + C(0.5));
+                    const C wB = rcp<C>(MB * inv_cs2s + C(0.5));
                     // rest populations in double: they carry the conserved composition
                     {
+                        const double whA = double(wA), whB = double(wB);
                         const double eqA = sA - (1.0 - SL::w(0)) * m.muA;
                         const double eqB = sB - (1.0 - SL::w(0)) * m.muB;
                         const double pa = double(a[0]) - whA * (double(a[0]) - eqA);
                         const double pb = double(b[0]) - whB * (double(b[0]) - eqB);
-                        push(std::integral_constant<int, A0>{}, std::integral_constant<int, A0>{}, 0, 0, 0, C(pa));
-                        push(std::integral_constant<int, B0>{}, std::integral_constant<int, B0>{}, 0, 0, 0, C(pb));
+                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb));
                     }
-                    const C wA = C(whA), wB = C(whB);
-                    const C muA = C(m.muA), muB = C(m.muB);
-                    const C cAc = C(sA), cBc = C(sB);
+                    const C keepA = C(1) - wA, keepB = C(1) - wB;
+                    const C wmuA = wA * C(m.muA), wmuB = wB * C(m.muB);
+                    const C wcA = wA * C(sA) * inv_cs2s, wcB = wB * C(sB) * inv_cs2s;
                     static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
-                        const C eu = (C(SL::ex(k)) * u[0] + C(SL::ey(k)) * u[1] + C(SL::ez(k)) * u[2]) * inv_cs2s;
+                        constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
                         const C wk = C(SL::w(k));
-                        const C eqA = wk * (muA + cAc * eu);
-                        const C eqB = wk * (muB + cBc * eu);
-                        push(std::integral_constant<int, A0 + k>{}, std::integral_constant<int, A0 + SL::opp(k)>{},
-                             SL::ex(k), SL::ey(k), SL::ez(k), a[k] - wA * (a[k] - eqA));
-                        push(std::integral_constant<int, B0 + k>{}, std::integral_constant<int, B0 + SL::opp(k)>{},
-                             SL::ex(k), SL::ey(k), SL::ez(k), b[k] - wB * (b[k] - eqB));
+                        const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
+                        push(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu));
+                        push(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu));
                     });
                 }
+
             } else if constexpr (MODE == MODE_MOMENTS) {
                 const double vals[kNumMom] = {m.phi, sA, sB, m.muA, m.muB, double(p_h),
                                               double(u[0]), double(u[1]), double(u[2])};
@@ -441,56 +644,150 @@ __global__ void __launch_bounds__(TX* TY) k_lbm(const KParams P) {
         }
         if constexpr (STENCIL) {
             // the next plane becomes the current one
+            if constexpr (!LBM_LDS_POPS) {
 #pragma unroll
-            for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
+                for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
+            }
             c_ps = n_ps; c_cA = n_cA; c_cB = n_cB;
             __syncthreads();
         }
     }
 
     if constexpr (MODE == MODE_DIAG) {
-        const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        block_reduce_store<8, NT>(acc, 4, P.partials + 8 * bid);
+        block_reduce_store<8, NT>(acc, 4, P.partials + 8 * tile);
     } else if constexpr (MODE == MODE_STEP) {
-        if (P.mean_subtract) {
-            const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-            block_reduce_store<1, NT>(acc, -1, P.partials + bid);
-        }
+        if (P.mean_subtract) block_reduce_store<1, NT>(acc, -1, P.partials + tile);
     }
 }
 
 // ---------------------------------------------------------------------------
-// initialisation at rest (Section 4.2.1): equilibrium populations from (phi_0, mu_0)
+// half-way bounce-back as a fix-up between steps (Section 4.2.4: walls at rest
+// with zero normal flux).  The next step pulls X_k(x) from slot k at
+// wrap(x - e_k).  When x - e_k lies across a wall, bounce-back wants instead the
+// post-collision population that left x towards the wall, slot opp(k) at x.
+// Node x' = wrap(x - e_k) is in the mirror situation: it pulls slot opp(k) at x
+// and wants its own slot k.  Exchanging the two entries serves both.  Each
+// exchange is done once, by the node x and direction k with k < opp(k); each
+// wall node is visited by exactly one thread: the face of its lowest-index wall
+// axis.
+
+template <class SL, class FL, int PREC>
+__global__ void __launch_bounds__(256) k_walls(const KParams P, int axis) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    // enumerate the two faces of `axis`: (b, c) span the other two axes
+    const int n[3] = {P.nx, P.ny, P.nz};
+    const int ab = axis == 0 ? 1 : 0, ac = axis == 2 ? 1 : 2;
+    const long long face = (long long)n[ab] * n[ac];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * face) return;
+    int c[3];
+    c[axis] = t < face ? 0 : n[axis] - 1;
+    const long long r = t % face;
+    c[ab] = int(r % n[ab]);
+    c[ac] = int(r / n[ab]);
+    const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
+    // skip nodes owned by the face of a lower wall axis
+    for (int a = 0; a < axis; ++a)
+        if (wall[a] && (c[a] == 0 || c[a] == n[a] - 1)) return;
+    if (n[axis] == 1 && t >= face) return;  // both faces are the same plane
+    const int idx = (c[2] * P.ny + c[1]) * P.nx + c[0];
+
+    // does x - e lie across a wall?
+    auto crosses = [&](int ex, int ey, int ez) {
+        const int e[3] = {ex, ey, ez};
+        for (int a = 0; a < 3; ++a)
+            if (wall[a] && e[a] != 0 && (c[a] - e[a] < 0 || c[a] - e[a] >= n[a])) return true;
+        return false;
+    };
+    // index of wrap(x - e)
+    auto source = [&](int ex, int ey, int ez) {
+        const int e[3] = {ex, ey, ez};
+        int q[3];
+        for (int a = 0; a < 3; ++a) q[a] = (c[a] - e[a] + n[a]) % n[a];
+        return (q[2] * P.ny + q[1]) * P.nx + q[0];
+    };
+    // exchange slot S at node i with slot SO at node j (raw storage bits)
+    auto swap = [&](auto s_, auto so_, int i, int j) {
+        constexpr int S = decltype(s_)::value, SO = decltype(so_)::value;
+        char* ps = P.dst_base + slot_offset<SLOTS, S>(P);
+        char* po = P.dst_base + slot_offset<SLOTS, SO>(P);
+        if constexpr (PREC == P64) {
+            double* a = reinterpret_cast<double*>(ps) + i;
+            double* b = reinterpret_cast<double*>(po) + j;
+            const double va = *a, vb = *b;
+            *a = vb; *b = va;
+        } else if constexpr (PREC == P32) {
+            float* a = reinterpret_cast<float*>(ps) + i;
+            float* b = reinterpret_cast<float*>(po) + j;
+            const float va = *a, vb = *b;
+            *a = vb; *b = va;
+        } else {  // moving populations only (k != 0): 16-bit words with equal references
+            unsigned short* a = reinterpret_cast<unsigned short*>(ps) + i;
+            unsigned short* b = reinterpret_cast<unsigned short*>(po) + j;
+            const unsigned short va = *a, vb = *b;
+            *a = vb; *b = va;
+        }
+    };
+    auto fix_lattice = [&](auto lat_, auto base_) {
+        using L = typename decltype(lat_)::type;
+        constexpr int B = decltype(base_)::value;
+        static_for<1, L::Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int o = L::opp(k);
+            if constexpr (k < o) {
+                if (crosses(L::ex(k), L::ey(k), L::ez(k)))
+                    swap(IC<B + k>{}, IC<B + o>{}, source(L::ex(k), L::ey(k), L::ez(k)), idx);
+            }
+        });
+    };
+    if constexpr (FL::Q > 0) fix_lattice(std::common_type<FL>{}, IC<0>{});
+    fix_lattice(std::common_type<SL>{}, IC<SLOTS::G0>{});
+    fix_lattice(std::common_type<SL>{}, IC<SLOTS::A0>{});
+    fix_lattice(std::common_type<SL>{}, IC<SLOTS::B0>{});
+}
+
+// ---------------------------------------------------------------------------
+// initialisation at rest (Section 4.2.1): equilibrium populations from (phi_0, mu_0).
+// A copy holds post-collision populations at the node that computed them; the
+// next step pulls X_k(x) from slot k at wrap(x - e_k).  The equilibrium X_k(x) is
+// therefore written to slot k at wrap(x - e_k).
 
 template <class SL, class FL, int PREC>
 __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __restrict__ phi0,
                                               const double* __restrict__ muA0,
                                               const double* __restrict__ muB0) {
-    constexpr int QS = SL::Q;
-    constexpr int QF = FL::Q;
-    constexpr int G0 = QF, A0 = QF + QS, B0 = QF + 2 * QS;
+    using C = typename Stor<PREC>::C;
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
     using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= P.nx) return;
     const int idx = (z * P.ny + y) * P.nx + x;
+    const Nbr nb = neighbours(x, y, z, P);
     const double phi = phi0[idx], muA = muA0[idx], muB = muB0[idx];
     const double pp = interp_p(phi);
     const double cA = muA + P.c0A + pp * (P.c1A - P.c0A);  // Eq. species_closure
     const double cB = muB + P.c0B + pp * (P.c1B - P.c0B);
     const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
     const double S0 = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
-#pragma unroll
-    for (int k = 0; k < QS; ++k) {
-        const double wk = SL::w(k);
-        st_pop<PREC>(P.dst[G0 + k], idx, k == 0, P.swref[G0 + k], P.sscale[G0 + k],
-                     typename Stor<PREC>::C(wk * phi - 0.5 * wk * S0));
-        const double hA = k == 0 ? cA - (1.0 - wk) * muA : wk * muA;
-        const double hB = k == 0 ? cB - (1.0 - wk) * muB : wk * muB;
-        st_pop<PREC>(P.dst[A0 + k], idx, k == 0, P.swref[A0 + k], P.sscale[A0 + k], typename Stor<PREC>::C(hA));
-        st_pop<PREC>(P.dst[B0 + k], idx, k == 0, P.swref[B0 + k], P.sscale[B0 + k], typename Stor<PREC>::C(hB));
-    }
-    if constexpr (QF > 0) {
+
+    auto put = [&](auto s_, auto k_, auto lat_, double v) {
+        using L = typename decltype(lat_)::type;
+        constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
+        char* slot = P.dst_base + slot_offset<SLOTS, S>(P);
+        const unsigned t = unsigned(idx + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
+        st_at<PREC, SLOTS::rest(S)>(slot, t, float(L::w(k)) * P.fref[SLOTS::field(S)],
+                                    P.fscale[SLOTS::field(S)], C(v));
+    };
+    static_for<0, SL::Q>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr double wk = SL::w(k);
+        put(IC<G0 + k>{}, kc, std::common_type<SL>{}, wk * phi - 0.5 * wk * S0);
+        put(IC<A0 + k>{}, kc, std::common_type<SL>{}, k == 0 ? cA - (1.0 - wk) * muA : wk * muA);
+        put(IC<B0 + k>{}, kc, std::common_type<SL>{}, k == 0 ? cB - (1.0 - wk) * muB : wk * muB);
+    });
+    if constexpr (FL::Q > 0) {
         double grad[3] = {0.0, 0.0, 0.0}, lap = 0.0;
 #pragma unroll
         for (int k = 1; k < STL::Q; ++k) {
@@ -508,38 +805,47 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
         const double buoy = (phi - phi_ref) * P.drho;
         const double F[3] = {buoy * P.gx + bracket * grad[0], buoy * P.gy + bracket * grad[1],
                              buoy * P.gz + bracket * grad[2]};
-#pragma unroll
-        for (int k = 0; k < QF; ++k) {
+        static_for<0, FL::Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             const double eF = FL::ex(k) * F[0] + FL::ey(k) * F[1] + FL::ez(k) * F[2];
             // f^eq at p_h = 0, u = 0 minus F_k / 2 with Gamma_k(u = 0) = w_k
-            st_pop<PREC>(P.dst[k], idx, k == 0, P.swref[k], P.sscale[k],
-                         typename Stor<PREC>::C(-0.5 * FL::w(k) * eF));
-        }
+            put(kc, kc, std::common_type<FL>{}, -0.5 * FL::w(k) * eF);
+        });
     }
 }
 
 // ---------------------------------------------------------------------------
-// canonical FP64 population access and reductions
+// canonical FP64 population access: X_k(x) lives in slot k at wrap(x - e_k)
 
-template <int PREC>
-__global__ void __launch_bounds__(256) k_get_pops(const KParams P, int nslots, long long nodes,
-                                                  double* __restrict__ out) {
+template <class SL, class FL, int PREC, bool SET>
+__global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, double* __restrict__ buf) {
+    using C = typename Stor<PREC>::C;
+    using SLOTS = Slots<FL::Q, SL::Q>;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (i >= nodes || s >= nslots) return;
-    const bool rest = P.srest[s] != 0;
-    out[s * nodes + i] = double(ld_pop<PREC>(P.src[s], int(i), rest, P.swref[s], P.sinv[s]));
-}
-
-template <int PREC>
-__global__ void __launch_bounds__(256) k_set_pops(const KParams P, int nslots, long long nodes,
-                                                  const double* __restrict__ in) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int s = blockIdx.y;
-    if (i >= nodes || s >= nslots) return;
-    const bool rest = P.srest[s] != 0;
-    st_pop<PREC>(P.dst[s], int(i), rest, P.swref[s], P.sscale[s],
-                 typename Stor<PREC>::C(in[s * nodes + i]));
+    if (i >= nodes) return;
+    const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
+    const Nbr nb = neighbours(x, y, z, P);
+    auto one = [&](auto s_, auto k_, auto lat_) {
+        using L = typename decltype(lat_)::type;
+        constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
+        const float wref = float(L::w(k)) * P.fref[SLOTS::field(S)];
+        if constexpr (SET) {
+            char* slot = P.dst_base + slot_offset<SLOTS, S>(P);
+            const unsigned t = unsigned(int(i) + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
+            st_at<PREC, SLOTS::rest(S)>(slot, t, wref, P.fscale[SLOTS::field(S)], C(buf[S * nodes + i]));
+        } else {
+            const char* slot = P.src_base + slot_offset<SLOTS, S>(P);
+            const unsigned t = unsigned(int(i) + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
+            buf[S * nodes + i] = double(ld_at<PREC, SLOTS::rest(S)>(slot, t, wref, P.finv[SLOTS::field(S)]));
+        }
+    };
+    static_for<0, FL::Q>([&](auto kc) { one(kc, kc, std::common_type<FL>{}); });
+    static_for<0, SL::Q>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        one(IC<SLOTS::G0 + k>{}, kc, std::common_type<SL>{});
+        one(IC<SLOTS::A0 + k>{}, kc, std::common_type<SL>{});
+        one(IC<SLOTS::B0 + k>{}, kc, std::common_type<SL>{});
+    });
 }
 
 // per-work-group sums of a double field (grid-stride, fixed order)

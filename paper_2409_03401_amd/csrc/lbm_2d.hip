@@ -1,12 +1,21 @@
 // 2D lattice families (D2Q5 scalars, optional D2Q9 fluid), run in the x-z plane
-// of the kernel frame with one row of 64 nodes per work-group.
+// of the kernel frame with one row of TX nodes per work-group.
 #include "family.hpp"
 
 namespace lbm {
 
-const KernelSet* kernels_2d(int fluid, int prec) {
-    if (fluid == 0) return family_for_prec<D2Q5K, NoLattice, 64, 1>(prec);
-    if (fluid == 9) return family_for_prec<D2Q5K, D2Q9K, 64, 1>(prec);
+template <class FL>
+static const KernelSet* by_tile(int prec, int tx) {
+    switch (tx) {
+        case 128: return family_for_prec<D2Q5K, FL, 128, 1>(prec);
+        case 256: return family_for_prec<D2Q5K, FL, 256, 1>(prec);
+        default: return family_for_prec<D2Q5K, FL, 64, 1>(prec);
+    }
+}
+
+const KernelSet* kernels_2d(int fluid, int prec, int tx) {
+    if (fluid == 0) return by_tile<NoLattice>(prec, tx);
+    if (fluid == 9) return by_tile<D2Q9K>(prec, tx);
     return nullptr;
 }
 

@@ -1,12 +1,18 @@
-// 3D lattice families (D3Q7 scalars, optional D3Q19 fluid) with 32 x 8 node
-// columns per work-group.
+// 3D lattice families (D3Q7 scalars, optional D3Q19 fluid) with 64 x 4 node
+// columns per work-group (32 x 8 on request).
 #include "family.hpp"
 
 namespace lbm {
 
-const KernelSet* kernels_3d(int fluid, int prec) {
-    if (fluid == 0) return family_for_prec<D3Q7K, NoLattice, 32, 8>(prec);
-    if (fluid == 19) return family_for_prec<D3Q7K, D3Q19K, 32, 8>(prec);
+template <class FL>
+static const KernelSet* by_tile(int prec, int tx, int ty) {
+    if (tx == 32 && ty == 8) return family_for_prec<D3Q7K, FL, 32, 8>(prec);
+    return family_for_prec<D3Q7K, FL, 64, 4>(prec);
+}
+
+const KernelSet* kernels_3d(int fluid, int prec, int tx, int ty) {
+    if (fluid == 0) return by_tile<NoLattice>(prec, tx, ty);
+    if (fluid == 19) return by_tile<D3Q19K>(prec, tx, ty);
     return nullptr;
 }
 

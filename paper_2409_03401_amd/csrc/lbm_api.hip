@@ -42,13 +42,16 @@ double lattice_w(int q, int k) {
 }
 
 struct Layout {
+    const KernelSet* ks;
     int dim, qf, qs, nslots, prec;
     int NX, NY, NZ;  // kernel frame
     long long nodes;
     size_t slot_off[kMaxSlots];
     size_t copy_bytes;
+    size_t stride_m, stride_r;  // bytes of a moving / rest slot
     int tx, ty, zc;
-    dim3 grid;
+    int tiles[3];
+    dim3 grid;        // 1D: one work-group per tile
     long long nparts;     // work-groups of the fused kernel
     size_t aux_bytes;
     size_t state_bytes;
@@ -114,18 +117,27 @@ int check_config(const lbm_config* c, Layout* L) {
     } else {
         L->NX = c->nx; L->NY = c->ny; L->NZ = c->nz;
     }
+    // slots in canonical order; every moving slot takes stride_m bytes, every rest
+    // slot stride_r bytes (the kernels rely on this)
+    L->stride_m = round_up((size_t)nodes * slot_bytes(L->prec, 1));
+    L->stride_r = round_up((size_t)nodes * slot_bytes(L->prec, 0));
     size_t off = 0;
     for (int s = 0; s < L->nslots; ++s) {
         const int k = s < L->qf ? s : (s - L->qf) % L->qs;
         L->slot_off[s] = off;
-        off += round_up((size_t)nodes * slot_bytes(L->prec, k));
+        off += k == 0 ? L->stride_r : L->stride_m;
     }
     L->copy_bytes = off;
 
-    // launch geometry: TX x TY node columns marching along z in chunks of zc planes,
-    // aiming at about 2048 work-groups (8 per compute unit)
-    L->tx = L->dim == 2 ? 64 : 32;
-    L->ty = L->dim == 2 ? 1 : 8;
+    // kernels and launch geometry: TX x TY node columns marching along z in chunks
+    // of zc planes, aiming at about 2048 work-groups (8 per compute unit).
+    // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
+    int want_tx = 0, want_ty = 0;
+    if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
+    L->ks = L->dim == 2 ? kernels_2d(L->qf, L->prec, want_tx) : kernels_3d(L->qf, L->prec, want_tx, want_ty);
+    if (!L->ks) return fail(LBM_EUNSUPPORTED, "no kernel for this lattice / precision");
+    L->tx = L->ks->tx;
+    L->ty = L->ks->ty;
     const long long gx = (L->NX + L->tx - 1) / L->tx, gy = (L->NY + L->ty - 1) / L->ty;
     long long nchunks = std::max(1LL, std::min<long long>(L->NZ, 2048 / std::max(1LL, gx * gy)));
     int zc = int((L->NZ + nchunks - 1) / nchunks);
@@ -135,7 +147,8 @@ int check_config(const lbm_config* c, Layout* L) {
     }
     L->zc = zc;
     const long long gz = (L->NZ + zc - 1) / zc;
-    L->grid = dim3(unsigned(gx), unsigned(gy), unsigned(gz));
+    L->tiles[0] = int(gx); L->tiles[1] = int(gy); L->tiles[2] = int(gz);
+    L->grid = dim3(unsigned(gx * gy * gz));
     L->nparts = gx * gy * gz;
     // aux: 16 doubles of scalars, then per-work-group partials (8 per group)
     const long long npart_doubles = std::max<long long>(8 * L->nparts, 1024);
@@ -160,6 +173,8 @@ struct lbm_handle {
 namespace {
 
 void set_slots(const lbm_handle* h, KParams& kp, const char* src, char* dst) {
+    kp.src_base = src;
+    kp.dst_base = dst;
     for (int s = 0; s < kMaxSlots; ++s) {
         kp.src[s] = (src && s < h->L.nslots) ? src + h->L.slot_off[s] : nullptr;
         kp.dst[s] = (dst && s < h->L.nslots) ? dst + h->L.slot_off[s] : nullptr;
@@ -180,6 +195,7 @@ void fill_params(lbm_handle* h) {
         kp.gx = c.g[0]; kp.gy = c.g[1]; kp.gz = c.g[2];
     }
     kp.zc = L.zc;
+    kp.tiles_x = L.tiles[0]; kp.tiles_y = L.tiles[1]; kp.tiles_z = L.tiles[2];
     kp.mean_subtract = c.gravity_mean_subtract ? 1 : 0;
     kp.W = c.W;
     kp.lam = c.lambda;
@@ -194,11 +210,19 @@ void fill_params(lbm_handle* h) {
     kp.drho = c.drho;
     kp.cap = 1.5 * c.sigma * c.W;
     kp.inv_W2 = 1.0 / (c.W * c.W);
+    const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
+    for (int f = 0; f < 4; ++f) {
+        const int sh = sixteen ? c.store_shift[f] : 0;
+        kp.fref[f] = sixteen ? float(c.store_ref[f]) : 0.0f;
+        kp.fscale[f] = std::ldexp(1.0f, sh);
+        kp.finv[f] = std::ldexp(1.0f, -sh);
+    }
+    kp.stride_m = L.stride_m;
+    kp.stride_r = L.stride_r;
     for (int s = 0; s < L.nslots; ++s) {
         const int field = s < L.qf ? 0 : 1 + (s - L.qf) / L.qs;
         const int k = s < L.qf ? s : (s - L.qf) % L.qs;
         const int q = s < L.qf ? L.qf : L.qs;
-        const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
         kp.srest[s] = k == 0;
         kp.swref[s] = (sixteen && k != 0) ? float(lattice_w(q, k) * c.store_ref[field]) : 0.0f;
         const int sh = sixteen ? c.store_shift[field] : 0;
@@ -253,8 +277,7 @@ int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const doubl
         return fail(LBM_EINVAL, "state must be 256-byte aligned");
     if (state_bytes < L.state_bytes)
         return fail(LBM_ESIZE, "state buffer smaller than lbm_state_bytes");
-    const KernelSet* ks = L.dim == 2 ? kernels_2d(L.qf, L.prec) : kernels_3d(L.qf, L.prec);
-    if (!ks) return fail(LBM_EUNSUPPORTED, "no kernel for this lattice / precision");
+    const KernelSet* ks = L.ks;
 
     lbm_handle* h = new lbm_handle();
     h->cfg = *cfg;
@@ -293,8 +316,11 @@ int lbm_step(lbm_handle* h, int64_t nsteps, void* stream) {
     KParams kp[2] = {h->base, h->base};
     set_slots(h, kp[0], h->copy[0], h->copy[1]);
     set_slots(h, kp[1], h->copy[1], h->copy[0]);
+    const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
     for (int64_t i = 0; i < nsteps; ++i) {
         h->ks->fused(MODE_STEP, h->L.grid, kp[h->cur], s);
+        for (int a = 0; a < 3; ++a)
+            if (walls[a]) h->ks->walls(kp[h->cur], a, s);
         if (h->cfg.gravity_mean_subtract)
             launch_finalize(h->aux + 16, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), h->aux, s);
         if (int r = launched("step kernel")) return r;

@@ -36,6 +36,7 @@ struct KParams {
     int nx, ny, nz;
     int wall_x, wall_y, wall_z;  // 1: half-way bounce-back walls on that axis
     int zc;                      // planes marched per work-group
+    int tiles_x, tiles_y, tiles_z;  // work-group tiles per axis (tiles_z = z chunks)
     int mean_subtract;           // buoyancy uses phi - phi_ref
     // model (Section 2), lattice units
     double W, lam, mphi_w2;      // mphi_w2 = M_phi / W^2 = 1 / tau_phi
@@ -46,6 +47,14 @@ struct KParams {
     double gx, gy, gz;           // gravity in the kernel frame
     double cap;                  // 3/2 sigma W of Eq. SurfaceTension_Force
     double inv_W2;
+    // population copies addressed by the fused kernel: slot s of a copy starts at
+    // base + (#moving slots before s) * stride_m + (#rest slots before s) * stride_r
+    const char* src_base;
+    char* dst_base;
+    unsigned long long stride_m, stride_r;
+    // 16-bit storage per field (0 f, 1 g, 2 hA, 3 hB): moving population k is
+    // value = w_k fref + d * finv, d = (value - w_k fref) * fscale
+    float fref[4], fscale[4], finv[4];
     // per-slot storage constants (canonical slot order): value = swref + d * sinv
     // for 16-bit moving populations, d = (value - swref) * sscale on store;
     // srest = 1 for rest populations (k = 0), stored in FP32 by the 16-bit formats
