@@ -13,6 +13,7 @@ with its algorithmic bytes (every population read once and written once per upda
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -162,6 +163,55 @@ def cpu_baseline(budget_s=12.0):
                       f"in {el:.1f} s (single thread; host has {os.cpu_count()} logical CPUs)"}
 
 
+def adjoint_timing(n=512, steps=4096, segment=None):
+    """Forward and backward wall time of the differentiable run on the sedimenting
+    drop (n x n, D2Q9 + 3 x D2Q5, FP32 storage, T = steps, checkpoints every
+    ceil(sqrt(T)) steps).  The backward pass includes the recomputation of every
+    segment, the adjoint steps and the adjoint of the initialisation."""
+    import torch
+    from paper_2409_03401_amd import inputs
+    from paper_2409_03401_amd.lbm import LBMConfig, Simulation, phase_field_run, theta_of
+
+    w = inputs.single_drop_2d(n=n)
+    cfg = LBMConfig(**w.params, precision="fp32")
+    sim = Simulation(cfg, w.phi0, w.muA0, w.muB0)
+    sim.step(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    sim.close()
+    del sim
+
+    phi0 = torch.tensor(w.phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    theta = torch.tensor(theta_of(cfg), dtype=torch.float64, requires_grad=True)
+    target = torch.tensor(w.phi0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phiT = phase_field_run(phi0, theta, cfg, steps, w.muA0, w.muB0, segment)
+    loss = ((phiT - target) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    finite = bool(torch.isfinite(phi0.grad).all()) and bool(torch.isfinite(theta.grad).all())
+    del phi0, theta, target, phiT, loss
+    torch.cuda.empty_cache()
+    seg = segment or (math.isqrt(steps - 1) + 1)
+    return {
+        "workload": f"single_drop_2d_{n}_fp32",
+        "steps": steps,
+        "segment": seg,
+        "forward_ms": round(fwd * 1e3, 2),
+        "forward_with_checkpoints_ms": round((t1 - t0) * 1e3, 2),
+        "backward_ms": round((t2 - t1) * 1e3, 2),
+        "ratio": round((t2 - t1) / fwd, 3),
+        "gradients_finite": finite,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,7 +219,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sediment_3d_256", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit storage variants")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 16-bit storage variants and the adjoint timing")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time the differentiable run (forward, backward, ratio)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale HBM counters")
     args = ap.parse_args()
@@ -195,6 +248,14 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+
+    if args.adjoint_only:
+        res = {}
+        for n in (512, 2048):
+            print(f"[bench] adjoint timing at {n}^2", file=sys.stderr, flush=True)
+            res[str(n)] = adjoint_timing(n=n)
+        print(json.dumps({"adjoint": res}), flush=True)
+        return
 
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
     w = build_workload(args.workload)
@@ -223,6 +284,10 @@ def main():
                 "kernel_ms": round(kms16, 4),
                 "GBps": round(bytes_per_update(c16) * c16.nodes / (kms16 * 1e-3) / 1e9, 1),
             }
+
+    if not args.no_extra:
+        print("[bench] timing the adjoint (forward, recompute + backward)", file=sys.stderr, flush=True)
+        extra["adjoint"] = adjoint_timing()
 
     cpu = None
     if not args.no_cpu_baseline:

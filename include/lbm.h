@@ -145,6 +145,37 @@ int lbm_set_populations(lbm_handle* h, const double* src, void* stream);
 int lbm_save(lbm_handle* h, void* dst, void* stream);
 int lbm_restore(lbm_handle* h, const void* src, void* stream);
 
+/* One step from the checkpoint `src` into the checkpoint `dst` (both laid out
+ * as lbm_save writes them; lbm_checkpoint_bytes each), without touching the
+ * handle's own copies.  Used to recompute states for the adjoint. */
+int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* stream);
+
+/*
+ * Discrete adjoint (reverse mode) of the step, for a loss of the final phase
+ * field.  The adjoint of a state is lambda_k(x) = dL / dX_k(x) for the arriving
+ * populations of Section 3; it lives in the caller's workspace `work`
+ * (lbm_adjoint_bytes, FP32).  Parameter gradients accumulate in `grad_theta`,
+ * six FP64 device values d/d(M_phi, M^A_0, M^A_1, M^B_0, M^B_1, W) (the
+ * caller zeroes them).  Supported for FP32 and FP64 storage without
+ * gravity_mean_subtract (LBM_EUNSUPPORTED otherwise).
+ *
+ *   lbm_adjoint_seed : lambda^T = dL/dphi_T * dphi/dX of Eq. Moment0_Phi, from the
+ *                      checkpoint of state T and dL/dphi_T (FP64 device, [node])
+ *   lbm_adjoint_step : lambda^(n+1) -> lambda^n through step n, given the
+ *                      checkpoint of state n (before the step)
+ *   lbm_adjoint_init : lambda^0 -> dL/dphi_0 (FP64 device [node], overwritten)
+ *                      through lbm_init with mu_0 held fixed
+ *   lbm_adjoint_get / lbm_adjoint_set : current lambda as FP64 [slot][node]
+ */
+int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes);
+int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, double* grad_theta,
+                     void* stream);
+int lbm_adjoint_step(lbm_handle* h, const void* state, void* work, double* grad_theta, void* stream);
+int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, const double* muB0, void* work,
+                     double* grad_phi0, double* grad_theta, void* stream);
+int lbm_adjoint_get(lbm_handle* h, void* work, double* dst, void* stream);
+int lbm_adjoint_set(lbm_handle* h, void* work, const double* src, void* stream);
+
 /* Number of steps taken since lbm_init (host counter). */
 int64_t lbm_step_count(const lbm_handle* h);
 

@@ -15,6 +15,13 @@ struct KernelSet {
     void (*set_pops)(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s);
     // bounce-back fix-up on the two faces of one wall axis (0 x, 1 y, 2 z), after a step
     void (*walls)(const KParams& kp, int axis, hipStream_t s);
+    // adjoint: nullptr when the storage precision has no adjoint (16-bit formats)
+    void (*adj_step)(dim3 grid, const KParams& kp, hipStream_t s);
+    void (*adj_seed)(const KParams& kp, long long nodes, const double* dL_dphi, hipStream_t s);
+    void (*adj_walls)(const KParams& kp, int axis, hipStream_t s);
+    void (*adj_gather)(const KParams& kp, long long nodes, int mode, double* grad_phi0, hipStream_t s);
+    void (*adj_init_local)(const KParams& kp, long long nodes, const double* phi0, const double* muA0,
+                           const double* muB0, hipStream_t s);
     int tx, ty;  // work-group tile of the fused kernel
 };
 
@@ -26,5 +33,8 @@ const KernelSet* kernels_3d(int fluid, int prec, int tx, int ty);
 void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
 void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,
                      double* out, hipStream_t s);
+// out[0..5] += sum of [nparts][6] partials (parameter gradients)
+void launch_accumulate6(const double* partials, int nparts, double* out, hipStream_t s);
+void launch_adj_copy(const KParams& kp, int nslots, long long nodes, double* buf, bool set, hipStream_t s);
 
 }  // namespace lbm

@@ -43,7 +43,34 @@ struct Family {
         const dim3 grid(unsigned((2 * face + 255) / 256));
         hipLaunchKernelGGL((k_walls<SL, FL, PREC>), grid, dim3(256), 0, s, kp, axis);
     }
-    static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, &walls, TX, TY};
+    static constexpr bool kAdj = PREC == P32 || PREC == P64;
+    static void adj_step(dim3 grid, const KParams& kp, hipStream_t s) {
+        if constexpr (kAdj)
+            hipLaunchKernelGGL((k_lbm<SL, FL, MODE_ADJ, PREC, TX, TY>), grid, dim3(TX, TY), 0, s, kp);
+    }
+    static void adj_seed(const KParams& kp, long long nodes, const double* dL_dphi, hipStream_t s) {
+        hipLaunchKernelGGL((k_adj_seed<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
+                           nodes, dL_dphi);
+    }
+    static void adj_walls(const KParams& kp, int axis, hipStream_t s) {
+        const long long n[3] = {kp.nx, kp.ny, kp.nz};
+        const long long face = n[axis == 0 ? 1 : 0] * n[axis == 2 ? 1 : 2];
+        hipLaunchKernelGGL((k_adj_walls<SL, FL>), dim3(unsigned((2 * face + 255) / 256)), dim3(256), 0, s, kp, axis);
+    }
+    static void adj_gather(const KParams& kp, long long nodes, int mode, double* grad_phi0, hipStream_t s) {
+        const dim3 grid(unsigned((nodes + 255) / 256));
+        if (mode == 0) hipLaunchKernelGGL((k_adj_gather<SL, FL, 0>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
+        else hipLaunchKernelGGL((k_adj_gather<SL, FL, 1>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
+    }
+    static void adj_init_local(const KParams& kp, long long nodes, const double* phi0, const double* muA0,
+                               const double* muB0, hipStream_t s) {
+        hipLaunchKernelGGL((k_adj_init_local<SL, FL>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
+                           nodes, phi0, muA0, muB0);
+    }
+    static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, &walls,
+                                   kAdj ? &adj_step : nullptr, kAdj ? &adj_seed : nullptr,
+                                   kAdj ? &adj_walls : nullptr, kAdj ? &adj_gather : nullptr,
+                                   kAdj ? &adj_init_local : nullptr, TX, TY};
 };
 
 template <class SL, class FL, int TX, int TY>

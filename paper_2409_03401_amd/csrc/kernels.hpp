@@ -21,46 +21,12 @@
 
 #include <type_traits>
 
+#include "adjoint.hpp"
 #include "lattice.hpp"
 #include "params.hpp"
+#include "physics.hpp"
 
 namespace lbm {
-
-// ---------------------------------------------------------------------------
-// thermodynamics (Section 2)
-
-__device__ __forceinline__ double interp_p(double f) { return f * f * (3.0 - 2.0 * f); }
-__device__ __forceinline__ double interp_dp(double f) { return 6.0 * f * (1.0 - f); }
-__device__ __forceinline__ double dwell(double f) { return 8.0 * f * f * (1.0 - f) * (1.0 - f); }
-__device__ __forceinline__ double dwell_d(double f) { return 16.0 * f * (1.0 - f) * (1.0 - 2.0 * f); }
-
-struct Scalars {
-    double phi, muA, muB, S;
-};
-
-// Potentials from compositions, Eq. PotChem with p(1 - phi) = 1 - p(phi),
-// and the source S_phi of Eq. SourceTerm_Phi with Delta omega = -sum mu (c_0 - c_1).
-__device__ __forceinline__ void potentials_and_source(double phi, double cA, double cB,
-                                                      const KParams& P, double& muA,
-                                                      double& muB, double& S) {
-    const double pp = interp_p(phi);
-    muA = cA - P.c0A - pp * (P.c1A - P.c0A);
-    muB = cB - P.c0B - pp * (P.c1B - P.c0B);
-    const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
-    S = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
-}
-
-// Moments of one node, Eqs. Moment0_c_alpha and Moment0_Phi.  phi = sum g + S/2
-// is implicit in phi; it is resolved by one predictor evaluation of S at sum g.
-__device__ __forceinline__ Scalars node_scalars(double phis, double cA, double cB,
-                                                const KParams& P) {
-    Scalars s;
-    double muA, muB, S;
-    potentials_and_source(phis, cA, cB, P, muA, muB, S);
-    s.phi = phis + 0.5 * S;
-    potentials_and_source(s.phi, cA, cB, P, s.muA, s.muB, s.S);
-    return s;
-}
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -292,6 +258,7 @@ k_lbm(const KParams P) {
     constexpr bool STENCIL = FLOW || MODE == MODE_DIAG;
     constexpr bool HAS_Y = SL::DIM == 3;
     using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
+    static_assert(MODE != MODE_ADJ || PREC == P32 || PREC == P64, "adjoint runs on FP32 / FP64 states");
     constexpr int LX = TX + 2;
     constexpr int LY = HAS_Y ? TY + 2 : 1;
     constexpr int OY = HAS_Y ? 1 : 0;
@@ -427,6 +394,9 @@ k_lbm(const KParams P) {
     double acc[NACC];
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+    double th[MODE == MODE_ADJ ? 6 : 1];
+#pragma unroll
+    for (int i = 0; i < (MODE == MODE_ADJ ? 6 : 1); ++i) th[i] = 0.0;
 
     const double phi_ref = P.mean_subtract ? *P.phi_ref : 0.0;
 
@@ -494,9 +464,10 @@ k_lbm(const KParams P) {
             // isotropic gradient and Laplacian, Eqs. Grad and Laplacian (fluid lattice)
             C grad[3] = {C(0), C(0), C(0)};
             C lap = C(0);
+            C pc = phi;
+            C nsum = C(0);  // 3 sum_{k != 0} w_k phi(x + e_k)
             if constexpr (STENCIL) {
-                const C pc = sphi[sc][ty + OY][tx + 1];
-                C nsum = C(0);  // 3 sum_{k != 0} w_k phi(x + e_k)
+                pc = sphi[sc][ty + OY][tx + 1];
                 static_for<1, STL::Q>([&](auto kc) __attribute__((always_inline)) {
                     constexpr int k = decltype(kc)::value;
                     constexpr int ex = STL::ex(k), ey = STL::ey(k), ez = STL::ez(k);
@@ -617,6 +588,46 @@ k_lbm(const KParams P) {
                     });
                 }
 
+            } else if constexpr (MODE == MODE_ADJ) {
+                // adjoint of this node's update: mu = dL/dQ(x) is the transposed
+                // streaming of lambda^(n+1), lambda_k(x + e_k) (walls were folded in by
+                // the pairwise exchange on lambda^(n+1)); lambda^n gets the local part
+                // here and the neighbour part in k_adj_gather.
+                constexpr int NS = SLOTS::N;
+                double Pf[QF > 0 ? QF : 1], Pg[QS], Pa[QS], Pb[QS];
+                double mu[NS], lb[NS];
+                static_for<0, QF>([&](auto kc) __attribute__((always_inline)) { Pf[kc.value] = double(fpop[kc.value]); });
+#pragma unroll
+                for (int k = 0; k < QS; ++k) { Pg[k] = double(g[k]); Pa[k] = double(a[k]); Pb[k] = double(b[k]); }
+                auto adj_load = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) {
+                    using L = typename decltype(lat_)::type;
+                    constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
+                    const unsigned t = unsigned(int(idx) + pull_offset<-L::ex(k), -L::ey(k), -L::ez(k)>(nbr));
+                    mu[S] = double(*reinterpret_cast<const float*>(P.adj_in + (unsigned long long)S * P.adj_stride +
+                                                                   (unsigned long long)t * 4u));
+                    lb[S] = 0.0;
+                };
+                static_for<0, QF>([&](auto kc) __attribute__((always_inline)) { adj_load(kc, kc, FLT{}); });
+                static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
+                    adj_load(IC<G0 + kc.value>{}, kc, SLT{});
+                    adj_load(IC<A0 + kc.value>{}, kc, SLT{});
+                    adj_load(IC<B0 + kc.value>{}, kc, SLT{});
+                });
+                const double Gd[3] = {double(grad[0]), double(grad[1]), double(grad[2])};
+                double Gb[3], Nb = 0.0;
+                node_adjoint<SL, FL>(Pf, Pg, Pa, Pb, Gd, double(nsum), double(pc), phi_ref, P, mu, mu + G0,
+                                     mu + A0, mu + B0, lb, lb + G0, lb + A0, lb + B0, Gb, Nb, th);
+#pragma unroll
+                for (int sidx = 0; sidx < NS; ++sidx)
+                    __builtin_nontemporal_store(float(lb[sidx]), reinterpret_cast<float*>(
+                        P.adj_out + (unsigned long long)sidx * P.adj_stride + (unsigned long long)idx * 4u));
+                double dphi[3];
+                dphi_dmoments(c_ps, sA, sB, P, dphi);
+                const float auxv[8] = {float(Gb[0]), float(Gb[1]), float(Gb[2]), float(Nb),
+                                       float(dphi[0]), float(dphi[1]), float(dphi[2]),
+                                       float(dphi_dK(c_ps, sA, sB, P))};
+#pragma unroll
+                for (int r = 0; r < 8; ++r) P.aux[(unsigned long long)r * P.aux_stride + idx] = auxv[r];
             } else if constexpr (MODE == MODE_MOMENTS) {
                 const double vals[kNumMom] = {m.phi, sA, sB, m.muA, m.muB, double(p_h),
                                               double(u[0]), double(u[1]), double(u[2])};
@@ -653,7 +664,9 @@ k_lbm(const KParams P) {
         }
     }
 
-    if constexpr (MODE == MODE_DIAG) {
+    if constexpr (MODE == MODE_ADJ) {
+        block_reduce_store<6, NT>(th, -1, P.partials + 6 * tile);
+    } else if constexpr (MODE == MODE_DIAG) {
         block_reduce_store<8, NT>(acc, 4, P.partials + 8 * tile);
     } else if constexpr (MODE == MODE_STEP) {
         if (P.mean_subtract) block_reduce_store<1, NT>(acc, -1, P.partials + tile);
@@ -848,6 +861,261 @@ __global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, 
     });
 }
 
+// ---------------------------------------------------------------------------
+// adjoint kernels.  Adjoint populations lambda_k(x) = dL / dX_k(x) of the arriving
+// populations live in FP32 [slot][node] buffers (P.adj_in / P.adj_out).
+
+template <class SL, class FL>
+__device__ __forceinline__ float& adj_at(char* base, const KParams& P, int slot, unsigned idx) {
+    return *reinterpret_cast<float*>(base + (unsigned long long)slot * P.adj_stride + (unsigned long long)idx * 4u);
+}
+
+// seed: lambda^T = dL/dphi_T * dphi/dP of the final moment phi (Eq. Moment0_Phi)
+// The moment depends on K = M_phi / W^2 through the predictor: dL/dK partials per
+// work-group go to P.partials (6 per work-group, theta order).
+template <class SL, class FL, int PREC>
+__global__ void __launch_bounds__(256) k_adj_seed(const KParams P, long long nodes,
+                                                  const double* __restrict__ dL_dphi) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double th[6] = {0, 0, 0, 0, 0, 0};
+    if (i < nodes) {
+    const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
+    const Nbr nb = neighbours(x, y, z, P);
+    double ps = 0.0, cA = 0.0, cB = 0.0;
+    static_for<0, SL::Q>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const unsigned t = unsigned(int(i) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
+        ps += double(ld_at<PREC, SLOTS::rest(SLOTS::G0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::G0 + k>(P), t,
+                                                                float(SL::w(k)) * P.fref[1], P.finv[1]));
+        cA += double(ld_at<PREC, SLOTS::rest(SLOTS::A0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::A0 + k>(P), t,
+                                                                float(SL::w(k)) * P.fref[2], P.finv[2]));
+        cB += double(ld_at<PREC, SLOTS::rest(SLOTS::B0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::B0 + k>(P), t,
+                                                                float(SL::w(k)) * P.fref[3], P.finv[3]));
+    });
+    double d[3];
+    dphi_dmoments(ps, cA, cB, P, d);
+    const double s = dL_dphi[i];
+    for (int k = 0; k < FL::Q; ++k) adj_at<SL, FL>(P.adj_out, P, k, unsigned(i)) = 0.0f;
+    for (int k = 0; k < SL::Q; ++k) {
+        adj_at<SL, FL>(P.adj_out, P, SLOTS::G0 + k, unsigned(i)) = float(s * d[0]);
+        adj_at<SL, FL>(P.adj_out, P, SLOTS::A0 + k, unsigned(i)) = float(s * d[1]);
+        adj_at<SL, FL>(P.adj_out, P, SLOTS::B0 + k, unsigned(i)) = float(s * d[2]);
+    }
+    const double K_b = s * dphi_dK(ps, cA, cB, P);
+    th[0] = K_b / (P.W * P.W);
+    th[5] = K_b * (-2.0 * P.mphi_w2 / P.W);
+    }
+    block_reduce_store<6, 256>(th, -1, P.partials + 6 * blockIdx.x);
+}
+
+// Transposed streaming needs mu_k(x) = lambda_k(x + e_k), or lambda_opp(k)(x) when
+// x + e_k lies across a wall.  Exchanging lambda_k at wrap(x + e_k) with
+// lambda_opp(k) at x for every such pair (once, k < opp(k)) lets the adjoint step
+// gather periodically.  Same face enumeration as k_walls.
+template <class SL, class FL>
+__global__ void __launch_bounds__(256) k_adj_walls(const KParams P, int axis) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    const int n[3] = {P.nx, P.ny, P.nz};
+    const int ab = axis == 0 ? 1 : 0, ac = axis == 2 ? 1 : 2;
+    const long long face = (long long)n[ab] * n[ac];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * face) return;
+    int c[3];
+    c[axis] = t < face ? 0 : n[axis] - 1;
+    const long long r = t % face;
+    c[ab] = int(r % n[ab]);
+    c[ac] = int(r / n[ab]);
+    const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
+    for (int a = 0; a < axis; ++a)
+        if (wall[a] && (c[a] == 0 || c[a] == n[a] - 1)) return;
+    if (n[axis] == 1 && t >= face) return;
+    const unsigned idx = unsigned((c[2] * P.ny + c[1]) * P.nx + c[0]);
+    char* buf = const_cast<char*>(P.adj_in);
+    auto fix_lattice = [&](auto lat_, auto base_) {
+        using L = typename decltype(lat_)::type;
+        constexpr int B = decltype(base_)::value;
+        static_for<1, L::Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int o = L::opp(k);
+            if constexpr (k < o) {
+                const int e[3] = {L::ex(k), L::ey(k), L::ez(k)};
+                bool cross = false;
+                int q[3];
+                for (int a = 0; a < 3; ++a) {
+                    if (wall[a] && e[a] != 0 && (c[a] + e[a] < 0 || c[a] + e[a] >= n[a])) cross = true;
+                    q[a] = (c[a] + e[a] + n[a]) % n[a];
+                }
+                if (cross) {
+                    float& va = adj_at<SL, FL>(buf, P, B + k, unsigned((q[2] * P.ny + q[1]) * P.nx + q[0]));
+                    float& vb = adj_at<SL, FL>(buf, P, B + o, idx);
+                    const float ta = va, tb = vb;
+                    va = tb;
+                    vb = ta;
+                }
+            }
+        });
+    };
+    if constexpr (FL::Q > 0) fix_lattice(std::common_type<FL>{}, IC<0>{});
+    fix_lattice(std::common_type<SL>{}, IC<SLOTS::G0>{});
+    fix_lattice(std::common_type<SL>{}, IC<SLOTS::A0>{});
+    fix_lattice(std::common_type<SL>{}, IC<SLOTS::B0>{});
+}
+
+// Transpose of the phi stencil (mirror ghosts at walls, wrap otherwise): node y
+// collects psi(y) = sum over (x, k) with map(x + e_k) = y of 3 w_k (e_k . Gb(x) + Nb(x)),
+// Gb, Nb = aux rows 0..3.  MODE 0 (adjoint step): lambda^n_{g,hA,hB}(y) += psi(y) *
+// dphi/d(phi*, c^A, c^B)(y) (aux rows 4..6), in place in adj_out, and psi(y) dphi/dK(y)
+// (aux row 7) reaches M_phi and W through K = M_phi / W^2 (work-group partials in
+// P.partials).  MODE 1 (initial
+// state): grad_phi0(y) = aux row 4 + psi(y).
+template <class SL, class FL, int GMODE>
+__global__ void __launch_bounds__(256) k_adj_gather(const KParams P, long long nodes, double* __restrict__ grad_phi0) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double th[6] = {0, 0, 0, 0, 0, 0};
+    if (i < nodes) {
+    const int yc[3] = {int(i % P.nx), int((i / P.nx) % P.ny), int(i / ((long long)P.nx * P.ny))};
+    const int n[3] = {P.nx, P.ny, P.nz};
+    const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
+    const unsigned long long as = P.aux_stride;
+    double psi = 0.0;
+    if constexpr (FL::Q > 0 || GMODE == 1) {
+        static_for<1, STL::Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int e[3] = {STL::ex(k), STL::ey(k), STL::ez(k)};
+            // candidate source coordinates per axis (at most two)
+            int cand[3][2], nc[3];
+            for (int a = 0; a < 3; ++a) {
+                nc[a] = 0;
+                if (e[a] == 0) {
+                    cand[a][nc[a]++] = yc[a];
+                } else if (!wall[a]) {
+                    cand[a][nc[a]++] = (yc[a] - e[a] + n[a]) % n[a];
+                } else {
+                    const int s = yc[a] - e[a];
+                    if (s >= 0 && s < n[a]) cand[a][nc[a]++] = s;
+                    if ((e[a] < 0 && yc[a] == 0) || (e[a] > 0 && yc[a] == n[a] - 1)) cand[a][nc[a]++] = yc[a];
+                }
+            }
+            const double w3 = 3.0 * STL::w(k);
+            for (int i0 = 0; i0 < nc[0]; ++i0)
+                for (int i1 = 0; i1 < nc[1]; ++i1)
+                    for (int i2 = 0; i2 < nc[2]; ++i2) {
+                        const unsigned long long xs =
+                            (unsigned long long)((cand[2][i2] * P.ny + cand[1][i1]) * P.nx + cand[0][i0]);
+                        const double gb = double(P.aux[0 * as + xs]) * e[0] + double(P.aux[1 * as + xs]) * e[1] +
+                                          double(P.aux[2 * as + xs]) * e[2];
+                        psi += w3 * (gb + double(P.aux[3 * as + xs]));
+                    }
+        });
+    }
+    if constexpr (GMODE == 1) {
+        grad_phi0[i] = double(P.aux[4 * as + i]) + psi;
+    } else {
+        const double d0 = P.aux[4 * as + i], d1 = P.aux[5 * as + i], d2 = P.aux[6 * as + i];
+        for (int k = 0; k < SL::Q; ++k) {
+            adj_at<SL, FL>(P.adj_out, P, SLOTS::G0 + k, unsigned(i)) += float(psi * d0);
+            adj_at<SL, FL>(P.adj_out, P, SLOTS::A0 + k, unsigned(i)) += float(psi * d1);
+            adj_at<SL, FL>(P.adj_out, P, SLOTS::B0 + k, unsigned(i)) += float(psi * d2);
+        }
+        // phi(y) also depends on K = M_phi / W^2 (aux row 7: dphi/dK)
+        const double K_b = psi * double(P.aux[7 * as + i]);
+        th[0] = K_b / (P.W * P.W);
+        th[5] = K_b * (-2.0 * P.mphi_w2 / P.W);
+    }
+    }
+    if constexpr (GMODE == 0) block_reduce_store<6, 256>(th, -1, P.partials + 6 * blockIdx.x);
+}
+
+// Adjoint of the initialisation (k_init) with mu_0 held fixed: lambda^0 (adj_in)
+// back to phi_0.  Local part per node into aux (rows 0..3: Gb, Nb of the F_0
+// stencil; row 4: local dL/dphi_0), parameter partials per work-group; the
+// stencil part closes in k_adj_gather<.., 1>.
+template <class SL, class FL>
+__global__ void __launch_bounds__(256) k_adj_init_local(const KParams P, long long nodes,
+                                                        const double* __restrict__ phi0,
+                                                        const double* __restrict__ muA0,
+                                                        const double* __restrict__ muB0) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double th[6] = {0, 0, 0, 0, 0, 0};
+    if (i < nodes) {
+        const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
+        char* lam = const_cast<char*>(P.adj_in);
+        const double phi = phi0[i], muA = muA0[i], muB = muB0[i];
+        const double dA = P.c1A - P.c0A, dB = P.c1B - P.c0B, eA = -dA, eB = -dB;
+        const double K = P.mphi_w2;
+        const double dw = -(muA * eA + muB * eB);
+        double phi_b = 0.0, S_b = 0.0;
+        // g_k = w_k phi - w_k S_0 / 2; h_0 = c - (1 - w_0) mu, c = mu + c_0 + p(phi)(c_1 - c_0)
+        for (int k = 0; k < SL::Q; ++k) {
+            const double lg = adj_at<SL, FL>(lam, P, SLOTS::G0 + k, unsigned(i));
+            phi_b += lg * SL::w(k);
+            S_b += -0.5 * lg * SL::w(k);
+        }
+        phi_b += (double(adj_at<SL, FL>(lam, P, SLOTS::A0, unsigned(i))) * dA +
+                  double(adj_at<SL, FL>(lam, P, SLOTS::B0, unsigned(i))) * dB) * interp_dp(phi);
+        // S_0 = K (lambda p'(phi) dw - omega_dw'(phi))
+        const double K_b = S_b * (P.lam * interp_dp(phi) * dw - dwell_d(phi));
+        phi_b += S_b * K * (P.lam * interp_ddp(phi) * dw - dwell_dd(phi));
+        th[0] += K_b / (P.W * P.W);
+        th[5] += K_b * (-2.0 * K / P.W);
+        double Gb[3] = {0.0, 0.0, 0.0}, Nb = 0.0;
+        if constexpr (FL::Q > 0) {
+            // f_k = -w_k (e_k . F_0) / 2
+            double F_b[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < FL::Q; ++k) {
+                const double lf = adj_at<SL, FL>(lam, P, k, unsigned(i));
+                F_b[0] += -0.5 * FL::w(k) * FL::ex(k) * lf;
+                F_b[1] += -0.5 * FL::w(k) * FL::ey(k) * lf;
+                F_b[2] += -0.5 * FL::w(k) * FL::ez(k) * lf;
+            }
+            double G[3] = {0.0, 0.0, 0.0}, N = 0.0;
+            for (int k = 1; k < STL::Q; ++k) {
+                const int xn = map_coord(x + STL::ex(k), P.nx, P.wall_x);
+                const int yn = map_coord(y + STL::ey(k), P.ny, P.wall_y);
+                const int zn = map_coord(z + STL::ez(k), P.nz, P.wall_z);
+                const double v = phi0[(zn * P.ny + yn) * P.nx + xn];
+                G[0] += 3.0 * STL::w(k) * STL::ex(k) * v;
+                G[1] += 3.0 * STL::w(k) * STL::ey(k) * v;
+                G[2] += 3.0 * STL::w(k) * STL::ez(k) * v;
+                N += 3.0 * STL::w(k) * v;
+            }
+            const double lap = 2.0 * N - 6.0 * (1.0 - STL::w(0)) * phi;
+            const double bracket = P.cap * (dwell_d(phi) * P.inv_W2 - lap);
+            phi_b += P.drho * (F_b[0] * P.gx + F_b[1] * P.gy + F_b[2] * P.gz);
+            const double bracket_b = F_b[0] * G[0] + F_b[1] * G[1] + F_b[2] * G[2];
+            for (int d = 0; d < 3; ++d) Gb[d] = bracket * F_b[d];
+            phi_b += bracket_b * P.cap * P.inv_W2 * dwell_dd(phi);
+            const double lap_b = -bracket_b * P.cap;
+            th[5] += bracket_b * (P.cap / P.W) * (-dwell_d(phi) * P.inv_W2 - lap);
+            Nb = 2.0 * lap_b;
+            phi_b += -6.0 * (1.0 - STL::w(0)) * lap_b;
+        }
+        const unsigned long long as = P.aux_stride;
+        P.aux[0 * as + i] = float(Gb[0]);
+        P.aux[1 * as + i] = float(Gb[1]);
+        P.aux[2 * as + i] = float(Gb[2]);
+        P.aux[3 * as + i] = float(Nb);
+        P.aux[4 * as + i] = float(phi_b);
+    }
+    block_reduce_store<6, 256>(th, -1, P.partials + 6 * blockIdx.x);
+}
+
+// copy of the current adjoint populations to / from FP64 [slot][node]
+template <bool SET>
+__global__ void __launch_bounds__(256) k_adj_copy(const KParams P, int nslots, long long nodes, double* buf) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= nodes || s >= nslots) return;
+    float* a = reinterpret_cast<float*>(const_cast<char*>(P.adj_in) + (unsigned long long)s * P.adj_stride) + i;
+    if constexpr (SET) *a = float(buf[s * nodes + i]);
+    else buf[s * nodes + i] = double(*a);
+}
+
 // per-work-group sums of a double field (grid-stride, fixed order)
 template <int NT = 256>
 __global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ v, long long n,
@@ -860,7 +1128,7 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__
 
 // final fixed-order reduction of per-work-group partials (one work-group).
 // partials are [nparts][N]; out[i] = scale[i] * reduce_i(partials[.][i])
-template <int N>
+template <int N, bool ACC = false>
 __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nparts,
                                                   int maxslot, double scale0, double* __restrict__ out) {
     double acc[N];
@@ -877,7 +1145,11 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
     block_reduce_store<N, 256>(acc, maxslot, res);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) out[i] = (i == 0) ? res[i] * scale0 : res[i];
+        for (int i = 0; i < N; ++i) {
+            const double v = (i == 0) ? res[i] * scale0 : res[i];
+            if constexpr (ACC) out[i] += v;
+            else out[i] = v;
+        }
     }
 }
 

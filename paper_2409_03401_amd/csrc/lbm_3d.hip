@@ -28,4 +28,14 @@ void launch_finalize(const double* partials, int nparts, int width, int maxslot,
         hipLaunchKernelGGL((k_finalize<8>), dim3(1), dim3(256), 0, s, partials, nparts, maxslot, scale0, out);
 }
 
+void launch_accumulate6(const double* partials, int nparts, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_finalize<6, true>), dim3(1), dim3(256), 0, s, partials, nparts, -1, 1.0, out);
+}
+
+void launch_adj_copy(const KParams& kp, int nslots, long long nodes, double* buf, bool set, hipStream_t s) {
+    const dim3 grid(unsigned((nodes + 255) / 256), nslots);
+    if (set) hipLaunchKernelGGL((k_adj_copy<true>), grid, dim3(256), 0, s, kp, nslots, nodes, buf);
+    else hipLaunchKernelGGL((k_adj_copy<false>), grid, dim3(256), 0, s, kp, nslots, nodes, buf);
+}
+
 }  // namespace lbm

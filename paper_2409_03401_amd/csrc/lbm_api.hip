@@ -55,6 +55,9 @@ struct Layout {
     long long nparts;     // work-groups of the fused kernel
     size_t aux_bytes;
     size_t state_bytes;
+    // adjoint workspace: two FP32 adjoint copies, 8 aux rows, parameter partials
+    size_t adj_stride, aux_stride_elems, adj_bytes;
+    long long adj_parts;
 };
 
 int check_config(const lbm_config* c, Layout* L) {
@@ -154,6 +157,11 @@ int check_config(const lbm_config* c, Layout* L) {
     const long long npart_doubles = std::max<long long>(8 * L->nparts, 1024);
     L->aux_bytes = round_up(sizeof(double) * (16 + npart_doubles));
     L->state_bytes = 2 * L->copy_bytes + L->aux_bytes;
+    L->adj_stride = round_up((size_t)nodes * 4);
+    L->aux_stride_elems = round_up((size_t)nodes * 4) / 4;
+    L->adj_parts = std::max<long long>(L->nparts, (nodes + 255) / 256);
+    L->adj_bytes = 2 * L->nslots * L->adj_stride + 8 * L->aux_stride_elems * 4 +
+                   round_up(sizeof(double) * 6 * L->adj_parts);
     return LBM_OK;
 }
 
@@ -167,6 +175,7 @@ struct lbm_handle {
     double* aux;
     int cur;
     int64_t steps;
+    int adj_cur;   // adjoint copy holding the current lambda (in the caller's workspace)
     KParams base;  // every field except src/dst/mout
 };
 
@@ -288,6 +297,7 @@ int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const doubl
     h->aux = reinterpret_cast<double*>(static_cast<char*>(state) + 2 * L.copy_bytes);
     h->cur = 0;
     h->steps = 0;
+    h->adj_cur = 0;
     fill_params(h);
     hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -410,6 +420,124 @@ int lbm_restore(lbm_handle* h, const void* src, void* stream) {
     LBM_HIP(hipMemcpyAsync(h->aux, static_cast<const char*>(src) + h->L.copy_bytes, sizeof(double),
                            hipMemcpyDeviceToDevice, s));
     return LBM_OK;
+}
+
+int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes) {
+    Layout L;
+    if (int r = check_config(cfg, &L)) return r;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = L.adj_bytes;
+    return LBM_OK;
+}
+
+int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!src || !dst || src == dst) return fail(LBM_EINVAL, "src and dst must be distinct checkpoint buffers");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp = h->base;
+    set_slots(h, kp, static_cast<const char*>(src), static_cast<char*>(dst));
+    const double* ref_in = reinterpret_cast<const double*>(static_cast<const char*>(src) + h->L.copy_bytes);
+    double* ref_out = reinterpret_cast<double*>(static_cast<char*>(dst) + h->L.copy_bytes);
+    kp.phi_ref = ref_in;
+    h->ks->fused(MODE_STEP, h->L.grid, kp, s);
+    const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
+    for (int a = 0; a < 3; ++a)
+        if (walls[a]) h->ks->walls(kp, a, s);
+    if (h->cfg.gravity_mean_subtract)
+        launch_finalize(h->aux + 16, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
+    else
+        LBM_HIP(hipMemcpyAsync(ref_out, ref_in, sizeof(double), hipMemcpyDeviceToDevice, s));
+    return launched("step_external kernels");
+}
+
+namespace {
+
+int adjoint_ready(const lbm_handle* h, const void* work) {
+    if (int r = check_handle(h)) return r;
+    if (!work) return fail(LBM_EINVAL, "work is NULL");
+    if (!h->ks->adj_step) return fail(LBM_EUNSUPPORTED, "the adjoint runs on FP32 or FP64 storage");
+    if (h->cfg.gravity_mean_subtract)
+        return fail(LBM_EUNSUPPORTED, "the adjoint does not support gravity_mean_subtract");
+    return LBM_OK;
+}
+
+// adjoint fields of a KParams: lambda copy `in` -> `out` inside the caller's workspace
+void adjoint_params(const lbm_handle* h, KParams& kp, void* work, int in, int out) {
+    char* w = static_cast<char*>(work);
+    const size_t copy = h->L.nslots * h->L.adj_stride;
+    kp.adj_in = in >= 0 ? w + in * copy : nullptr;
+    kp.adj_out = out >= 0 ? w + out * copy : nullptr;
+    kp.adj_stride = h->L.adj_stride;
+    kp.aux = reinterpret_cast<float*>(w + 2 * copy);
+    kp.aux_stride = h->L.aux_stride_elems;
+    kp.partials = reinterpret_cast<double*>(w + 2 * copy + 8 * h->L.aux_stride_elems * 4);
+}
+
+}  // namespace
+
+int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, double* grad_theta,
+                     void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!state || !dL_dphi || !grad_theta) return fail(LBM_EINVAL, "NULL pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp = h->base;
+    set_slots(h, kp, static_cast<const char*>(state), nullptr);
+    adjoint_params(h, kp, work, -1, 0);
+    h->ks->adj_seed(kp, h->L.nodes, dL_dphi, s);
+    launch_accumulate6(kp.partials, int((h->L.nodes + 255) / 256), grad_theta, s);
+    h->adj_cur = 0;
+    return launched("adjoint seed kernel");
+}
+
+int lbm_adjoint_step(lbm_handle* h, const void* state, void* work, double* grad_theta, void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!state || !grad_theta) return fail(LBM_EINVAL, "NULL pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp = h->base;
+    set_slots(h, kp, static_cast<const char*>(state), nullptr);
+    kp.phi_ref = reinterpret_cast<const double*>(static_cast<const char*>(state) + h->L.copy_bytes);
+    adjoint_params(h, kp, work, h->adj_cur, 1 - h->adj_cur);
+    const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
+    for (int a = 0; a < 3; ++a)
+        if (walls[a]) h->ks->adj_walls(kp, a, s);
+    h->ks->adj_step(h->L.grid, kp, s);
+    launch_accumulate6(kp.partials, int(h->L.nparts), grad_theta, s);
+    h->ks->adj_gather(kp, h->L.nodes, 0, nullptr, s);
+    launch_accumulate6(kp.partials, int((h->L.nodes + 255) / 256), grad_theta, s);
+    h->adj_cur = 1 - h->adj_cur;
+    return launched("adjoint step kernels");
+}
+
+int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, const double* muB0, void* work,
+                     double* grad_phi0, double* grad_theta, void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!phi0 || !muA0 || !muB0 || !grad_phi0 || !grad_theta) return fail(LBM_EINVAL, "NULL pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    KParams kp = h->base;
+    adjoint_params(h, kp, work, h->adj_cur, -1);
+    h->ks->adj_init_local(kp, h->L.nodes, phi0, muA0, muB0, s);
+    launch_accumulate6(kp.partials, int((h->L.nodes + 255) / 256), grad_theta, s);
+    h->ks->adj_gather(kp, h->L.nodes, 1, grad_phi0, s);
+    return launched("adjoint init kernels");
+}
+
+int lbm_adjoint_get(lbm_handle* h, void* work, double* dst, void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+    KParams kp = h->base;
+    adjoint_params(h, kp, work, h->adj_cur, -1);
+    launch_adj_copy(kp, h->L.nslots, h->L.nodes, dst, false, static_cast<hipStream_t>(stream));
+    return launched("adjoint copy kernel");
+}
+
+int lbm_adjoint_set(lbm_handle* h, void* work, const double* src, void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!src) return fail(LBM_EINVAL, "src is NULL");
+    KParams kp = h->base;
+    adjoint_params(h, kp, work, 0, -1);
+    launch_adj_copy(kp, h->L.nslots, h->L.nodes, const_cast<double*>(src), true, static_cast<hipStream_t>(stream));
+    h->adj_cur = 0;
+    return launched("adjoint copy kernel");
 }
 
 int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }

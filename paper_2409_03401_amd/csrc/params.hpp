@@ -14,7 +14,7 @@ constexpr int kNumMom = 9;
 constexpr int kNumDiag = 8;
 
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
-enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2 };
+enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_ADJ = 3 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -69,6 +69,14 @@ struct KParams {
     // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame)
     void* mout[kNumMom];
     int mout_f32;
+    // adjoint (MODE_ADJ and the adjoint kernels): adjoint populations in FP32,
+    // [slot][node] with slot stride adj_stride bytes, in the natural indexing
+    // lambda_k(x) = dL / dX_k(x) of the arriving populations; aux = [8][node] FP32
+    const char* adj_in;
+    char* adj_out;
+    unsigned long long adj_stride;
+    float* aux;
+    unsigned long long aux_stride;  // elements per aux row
 };
 
 }  // namespace lbm

@@ -30,7 +30,8 @@ TIE_LINE = ((0.2, 0.1), (0.6, 0.3))
 
 
 def rng_for(i: int) -> np.random.Generator:
-    return np.random.default_rng(np.random.SeedSequence(SEED).spawn(8)[i])
+    """Independent stream number i (child i of SeedSequence(SEED))."""
+    return np.random.default_rng(np.random.SeedSequence(SEED).spawn(i + 1)[i])
 
 
 def place_droplets(shape, n, rmin, rmax, W, rng, wall_axes=(), max_tries=200000):

@@ -7,8 +7,9 @@ not been built or no GPU is present: there is no CPU fallback.
 """
 
 import ctypes
+import math
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 from typing import Dict, Optional, Sequence, Tuple
 
 import torch
@@ -70,6 +71,16 @@ _SIGS = {
     "lbm_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_restore": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_step_external": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_adjoint_bytes": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_adjoint_seed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_adjoint_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "lbm_adjoint_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_adjoint_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_adjoint_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_step_count": (ctypes.c_int64, [ctypes.c_void_p]),
     "lbm_destroy": (None, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
@@ -174,6 +185,16 @@ def checkpoint_bytes(cfg: LBMConfig) -> int:
     return n.value
 
 
+def adjoint_bytes(cfg: LBMConfig) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_adjoint_bytes(ctypes.byref(cfg.to_c()), ctypes.byref(n)))
+    return n.value
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _stream_ptr(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -268,3 +289,112 @@ class Simulation:
 
     def restore(self, ckpt: torch.Tensor, stream=None):
         _check(lib().lbm_restore(self._h, ctypes.c_void_p(ckpt.data_ptr()), _stream_ptr(stream)))
+
+    # ---- discrete adjoint (reverse mode) ----------------------------------------------
+    def step_external(self, src: torch.Tensor, dst: torch.Tensor, stream=None):
+        """One step from checkpoint `src` into checkpoint `dst` (lbm_save layout)."""
+        _check(lib().lbm_step_external(self._h, _ptr(src), _ptr(dst), _stream_ptr(stream)))
+
+    def adjoint_workspace(self) -> torch.Tensor:
+        return torch.zeros(adjoint_bytes(self.cfg), dtype=torch.uint8, device=self.device)
+
+    def adjoint_seed(self, state: torch.Tensor, dL_dphi: torch.Tensor, work: torch.Tensor,
+                     grad_theta: torch.Tensor, stream=None):
+        d = _dev_f64(dL_dphi, self.cfg.nodes, self.device)
+        _check(lib().lbm_adjoint_seed(self._h, _ptr(state), _ptr(d), _ptr(work), _ptr(grad_theta),
+                                      _stream_ptr(stream)))
+
+    def adjoint_step(self, state: torch.Tensor, work: torch.Tensor, grad_theta: torch.Tensor, stream=None):
+        _check(lib().lbm_adjoint_step(self._h, _ptr(state), _ptr(work), _ptr(grad_theta), _stream_ptr(stream)))
+
+    def adjoint_init(self, work: torch.Tensor, grad_phi0: torch.Tensor, grad_theta: torch.Tensor, stream=None):
+        """dL/dphi_0 (written into grad_phi0) through lbm_init, mu_0 held fixed."""
+        phi0, muA0, muB0 = self._inputs
+        _check(lib().lbm_adjoint_init(self._h, _ptr(phi0), _ptr(muA0), _ptr(muB0), _ptr(work), _ptr(grad_phi0),
+                                      _ptr(grad_theta), _stream_ptr(stream)))
+
+    def adjoint_get(self, work: torch.Tensor, stream=None) -> torch.Tensor:
+        t = torch.empty((self.nslots,) + self.cfg.shape, dtype=torch.float64, device=self.device)
+        _check(lib().lbm_adjoint_get(self._h, _ptr(work), _ptr(t), _stream_ptr(stream)))
+        return t
+
+    def adjoint_set(self, work: torch.Tensor, lam, stream=None):
+        t = torch.as_tensor(lam, dtype=torch.float64, device=self.device).contiguous()
+        if t.numel() != self.nslots * self.cfg.nodes:
+            raise ValueError("wrong adjoint population count")
+        _check(lib().lbm_adjoint_set(self._h, _ptr(work), _ptr(t), _stream_ptr(stream)))
+        torch.cuda.current_stream().synchronize()
+
+
+# parameters the adjoint differentiates, in the order of grad_theta
+THETA_NAMES = ("M_phi", "M_A0", "M_A1", "M_B0", "M_B1", "W")
+
+
+def theta_of(cfg: LBMConfig):
+    return (cfg.M_phi, cfg.M_A[0], cfg.M_A[1], cfg.M_B[0], cfg.M_B[1], cfg.W)
+
+
+def with_theta(cfg: LBMConfig, theta) -> LBMConfig:
+    t = [float(v) for v in theta]
+    return replace(cfg, M_phi=t[0], M_A=(t[1], t[2]), M_B=(t[3], t[4]), W=t[5])
+
+
+class PhaseFieldRun(torch.autograd.Function):
+    """phi_T = run(phi_0, theta) for `steps` steps on the GPU, differentiable in
+    phi_0 and theta = (M_phi, M^A_0, M^A_1, M^B_0, M^B_1, W) (THETA_NAMES).
+
+    Forward keeps a checkpoint every `segment` steps (default ceil(sqrt(steps)));
+    backward recomputes each segment from its checkpoint into `segment` state
+    buffers and runs the adjoint steps through it in reverse, then the adjoint of
+    the initialisation.  Peak memory: about (steps / segment + segment) checkpoints.
+    mu_0 enters as a constant."""
+
+    @staticmethod
+    def forward(ctx, phi0, theta, cfg, steps, muA0, muB0, segment=None):
+        steps = int(steps)
+        seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
+        c = with_theta(cfg, theta.detach().double().cpu().tolist())
+        sim = Simulation(c, phi0.detach(), muA0, muB0, device=phi0.device)
+        ckpts = []
+        n = 0
+        while n < steps:
+            ckpts.append(sim.save())
+            k = min(seg, steps - n)
+            sim.step(k)
+            n += k
+        phiT = sim.moments(["phi"])["phi"].reshape(phi0.shape).to(phi0.dtype)
+        ctx.sim, ctx.ckpts, ctx.final = sim, ckpts, sim.save()
+        ctx.seg, ctx.steps = seg, steps
+        ctx.phi_shape, ctx.phi_dtype = phi0.shape, phi0.dtype
+        ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
+        return phiT
+
+    @staticmethod
+    def backward(ctx, grad_phiT):
+        sim = ctx.sim
+        dev = sim.device
+        work = sim.adjoint_workspace()
+        gth = torch.zeros(6, dtype=torch.float64, device=dev)
+        sim.adjoint_seed(ctx.final, grad_phiT.detach().to(torch.float64).contiguous(), work, gth)
+        nbytes = ctx.final.numel()
+        seg_states = [None] + [torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                               for _ in range(min(ctx.seg, ctx.steps) - 1)]
+        for s in reversed(range(len(ctx.ckpts))):
+            n0 = s * ctx.seg
+            length = min(ctx.seg, ctx.steps - n0)
+            states = [ctx.ckpts[s]]
+            for j in range(1, length):
+                sim.step_external(states[j - 1], seg_states[j])
+                states.append(seg_states[j])
+            for j in reversed(range(length)):
+                sim.adjoint_step(states[j], work, gth)
+        gphi0 = torch.empty(sim.cfg.shape, dtype=torch.float64, device=dev)
+        sim.adjoint_init(work, gphi0, gth)
+        ctx.sim = ctx.ckpts = ctx.final = None
+        return (gphi0.reshape(ctx.phi_shape).to(ctx.phi_dtype), gth.to(ctx.theta_device, ctx.theta_dtype),
+                None, None, None, None, None)
+
+
+def phase_field_run(phi0, theta, cfg: LBMConfig, steps: int, muA0, muB0, segment=None):
+    """Differentiable final phase field; see PhaseFieldRun."""
+    return PhaseFieldRun.apply(phi0, theta, cfg, steps, muA0, muB0, segment)
