@@ -223,6 +223,9 @@ def main():
                     help="skip the 16-bit storage variants and the adjoint timing")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time the differentiable run (forward, backward, ratio)")
+    ap.add_argument("--adjoint-n", type=int, nargs="+", default=[512, 2048],
+                    help="grid sizes n (n x n) for --adjoint-only")
+    ap.add_argument("--adjoint-steps", type=int, default=4096)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale HBM counters")
     args = ap.parse_args()
@@ -251,9 +254,9 @@ def main():
 
     if args.adjoint_only:
         res = {}
-        for n in (512, 2048):
+        for n in args.adjoint_n:
             print(f"[bench] adjoint timing at {n}^2", file=sys.stderr, flush=True)
-            res[str(n)] = adjoint_timing(n=n)
+            res[str(n)] = adjoint_timing(n=n, steps=args.adjoint_steps)
         print(json.dumps({"adjoint": res}), flush=True)
         return
 

@@ -147,32 +147,47 @@ int lbm_restore(lbm_handle* h, const void* src, void* stream);
 
 /* One step from the checkpoint `src` into the checkpoint `dst` (both laid out
  * as lbm_save writes them; lbm_checkpoint_bytes each), without touching the
- * handle's own copies.  Used to recompute states for the adjoint. */
-int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* stream);
+ * handle's own copies.  When phi_src is not NULL it receives phi of `src`
+ * (Eq. Moment0_Phi, [node], FP64 for LBM_FP64 storage, FP32 otherwise), the
+ * field the step's stencil used.  Used to recompute states for the adjoint. */
+int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, void* stream);
+
+/* phi of the checkpoint `state` into `phi` ([node], same type as above). */
+int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
 
 /*
- * Discrete adjoint (reverse mode) of the step, for a loss of the final phase
- * field.  The adjoint of a state is lambda_k(x) = dL / dX_k(x) for the arriving
- * populations of Section 3; it lives in the caller's workspace `work`
- * (lbm_adjoint_bytes, FP32).  Parameter gradients accumulate in `grad_theta`,
- * six FP64 device values d/d(M_phi, M^A_0, M^A_1, M^B_0, M^B_1, W) (the
- * caller zeroes them).  Supported for FP32 and FP64 storage without
- * gravity_mean_subtract (LBM_EUNSUPPORTED otherwise).
+ * Discrete adjoint (reverse mode) of the step, for a loss L of the final phase
+ * field.  The adjoint of a state is dL/dX_k(x) for its arriving populations
+ * (Section 3); it lives in the caller's device workspace `work` of
+ * lbm_adjoint_bytes (FP32 adjoint populations, scratch rows and FP64 parameter
+ * partials).  Supported for LBM_FP32 and LBM_FP64 storage without
+ * gravity_mean_subtract; other configurations return LBM_EUNSUPPORTED.
+ * Calls that share one workspace must not overlap.
  *
- *   lbm_adjoint_seed : lambda^T = dL/dphi_T * dphi/dX of Eq. Moment0_Phi, from the
- *                      checkpoint of state T and dL/dphi_T (FP64 device, [node])
- *   lbm_adjoint_step : lambda^(n+1) -> lambda^n through step n, given the
- *                      checkpoint of state n (before the step)
- *   lbm_adjoint_init : lambda^0 -> dL/dphi_0 (FP64 device [node], overwritten)
- *                      through lbm_init with mu_0 held fixed
- *   lbm_adjoint_get / lbm_adjoint_set : current lambda as FP64 [slot][node]
+ *   lbm_adjoint_seed  : start from dL/dphi_T (FP64 device [node]) at the final
+ *                       state `state` (a checkpoint, lbm_save layout), through
+ *                       phi of Eq. Moment0_Phi with its predictor.  Clears the
+ *                       parameter partials.
+ *   lbm_adjoint_step  : adjoint of the step n -> n + 1, given the checkpoint of
+ *                       state n (before the step) and its phi (lbm_step_external
+ *                       or lbm_phase_field): the adjoint of state n + 1 becomes
+ *                       that of state n.
+ *   lbm_adjoint_init  : adjoint of lbm_init with mu_0 held fixed: writes dL/dphi_0
+ *                       (FP64 device [node]); phi0, muA0, muB0 as given to lbm_init.
+ *   lbm_adjoint_theta : writes grad_theta[6] (FP64 device) = dL/d(M_phi, M^A_0,
+ *                       M^A_1, M^B_0, M^B_1, W) accumulated since the last seed or
+ *                       set (Eqs. SourceTerm_Phi, LBE_Phi, LBE_c_alpha,
+ *                       SurfaceTension_Force and the mobility interpolation).
+ *   lbm_adjoint_get / lbm_adjoint_set : the current adjoint as FP64 [slot][node]
+ *                       in the canonical slot order of lbm_get_populations; set
+ *                       also clears the parameter partials.
  */
 int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes);
-int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, double* grad_theta,
-                     void* stream);
-int lbm_adjoint_step(lbm_handle* h, const void* state, void* work, double* grad_theta, void* stream);
+int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, void* stream);
+int lbm_adjoint_step(lbm_handle* h, const void* state, const void* phi, void* work, void* stream);
 int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, const double* muB0, void* work,
-                     double* grad_phi0, double* grad_theta, void* stream);
+                     double* grad_phi0, void* stream);
+int lbm_adjoint_theta(lbm_handle* h, void* work, double* grad_theta, void* stream);
 int lbm_adjoint_get(lbm_handle* h, void* work, double* dst, void* stream);
 int lbm_adjoint_set(lbm_handle* h, void* work, const double* src, void* stream);
 

@@ -16,12 +16,15 @@ struct KernelSet {
     // bounce-back fix-up on the two faces of one wall axis (0 x, 1 y, 2 z), after a step
     void (*walls)(const KParams& kp, int axis, hipStream_t s);
     // adjoint: nullptr when the storage precision has no adjoint (16-bit formats)
-    void (*adj_step)(dim3 grid, const KParams& kp, hipStream_t s);
+    void (*adj_step)(const KParams& kp, long long nodes, const void* phi, hipStream_t s);
     void (*adj_seed)(const KParams& kp, long long nodes, const double* dL_dphi, hipStream_t s);
+    // exchange of the wall pairs of the current adjoint before an adjoint step
     void (*adj_walls)(const KParams& kp, int axis, hipStream_t s);
     void (*adj_gather)(const KParams& kp, long long nodes, int mode, double* grad_phi0, hipStream_t s);
     void (*adj_init_local)(const KParams& kp, long long nodes, const double* phi0, const double* muA0,
                            const double* muB0, hipStream_t s);
+    // adjoint to (set = false) or from (set = true) an FP64 [slot][node] array
+    void (*adj_copy)(const KParams& kp, int nslots, long long nodes, double* buf, bool set, hipStream_t s);
     int tx, ty;  // work-group tile of the fused kernel
 };
 
@@ -33,8 +36,8 @@ const KernelSet* kernels_3d(int fluid, int prec, int tx, int ty);
 void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
 void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,
                      double* out, hipStream_t s);
-// out[0..5] += sum of [nparts][6] partials (parameter gradients)
-void launch_accumulate6(const double* partials, int nparts, double* out, hipStream_t s);
-void launch_adj_copy(const KParams& kp, int nslots, long long nodes, double* buf, bool set, hipStream_t s);
+// out[0..5] (+)= sum of [nparts][6] partials (parameter gradients)
+void launch_sum6(const double* partials, int nparts, double* out, bool accumulate, hipStream_t s);
+void launch_zero(double* p, long long n, hipStream_t s);
 
 }  // namespace lbm

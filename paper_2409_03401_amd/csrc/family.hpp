@@ -44,9 +44,10 @@ struct Family {
         hipLaunchKernelGGL((k_walls<SL, FL, PREC>), grid, dim3(256), 0, s, kp, axis);
     }
     static constexpr bool kAdj = PREC == P32 || PREC == P64;
-    static void adj_step(dim3 grid, const KParams& kp, hipStream_t s) {
+    static void adj_step(const KParams& kp, long long nodes, const void* phi, hipStream_t s) {
         if constexpr (kAdj)
-            hipLaunchKernelGGL((k_lbm<SL, FL, MODE_ADJ, PREC, TX, TY>), grid, dim3(TX, TY), 0, s, kp);
+            hipLaunchKernelGGL((k_adj_node<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
+                               nodes, static_cast<const typename Stor<PREC>::C*>(phi));
     }
     static void adj_seed(const KParams& kp, long long nodes, const double* dL_dphi, hipStream_t s) {
         hipLaunchKernelGGL((k_adj_seed<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
@@ -67,10 +68,16 @@ struct Family {
         hipLaunchKernelGGL((k_adj_init_local<SL, FL>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
                            nodes, phi0, muA0, muB0);
     }
+    static void adj_copy(const KParams& kp, int nslots, long long nodes, double* buf, bool set_, hipStream_t s) {
+        const dim3 grid(unsigned((nodes + 255) / 256), nslots);
+        if (set_) hipLaunchKernelGGL((k_adj_copy<SL, FL, true>), grid, dim3(256), 0, s, kp, nodes, buf);
+        else hipLaunchKernelGGL((k_adj_copy<SL, FL, false>), grid, dim3(256), 0, s, kp, nodes, buf);
+    }
     static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, &walls,
                                    kAdj ? &adj_step : nullptr, kAdj ? &adj_seed : nullptr,
                                    kAdj ? &adj_walls : nullptr, kAdj ? &adj_gather : nullptr,
-                                   kAdj ? &adj_init_local : nullptr, TX, TY};
+                                   kAdj ? &adj_init_local : nullptr,
+                                   kAdj ? &adj_copy : nullptr, TX, TY};
 };
 
 template <class SL, class FL, int TX, int TY>

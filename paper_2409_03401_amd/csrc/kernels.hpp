@@ -31,33 +31,7 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 // helpers
 
-// compile-time loop: f(std::integral_constant<int, k>) for k in [B, E)
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
 
-template <int V>
-using IC = std::integral_constant<int, V>;
-
-// e . v for a lattice vector with components in {-1, 0, 1}, without the zero terms
-template <int EX, int EY, int EZ, class C>
-__device__ __forceinline__ C edot(C a, C b, C c) {
-    C r = C(0);
-    if constexpr (EX != 0) r = EX > 0 ? a : -a;
-    if constexpr (EY != 0) {
-        if constexpr (EX != 0) r += EY > 0 ? b : -b;
-        else r = EY > 0 ? b : -b;
-    }
-    if constexpr (EZ != 0) {
-        if constexpr (EX != 0 || EY != 0) r += EZ > 0 ? c : -c;
-        else r = EZ > 0 ? c : -c;
-    }
-    return r;
-}
 
 // 1/x: exact in FP64, the hardware reciprocal (1 ulp) in FP32
 template <class C>
@@ -112,6 +86,34 @@ __device__ __forceinline__ int pull_offset(const Nbr& n) {
     if constexpr (EZ > 0) d += n.zm;
     if constexpr (EZ < 0) d += n.zp;
     return d;
+}
+
+// A 32-bit byte offset the optimiser may not widen to 64 bits (an empty asm with a
+// register operand, no instruction).  Base (SGPR) + this offset selects the
+// `global_* voffset, saddr` form instead of a 64-bit per-lane address.
+__device__ __forceinline__ unsigned voff(unsigned byte_offset) {
+    asm("" : "+v"(byte_offset));
+    return byte_offset;
+}
+
+// index offsets of the axis neighbours for the phi stencil: periodic wrap, or the
+// node itself beyond a wall (mirror ghost of a half-way wall)
+__device__ __forceinline__ Nbr stencil_neighbours(int x, int y, int z, const KParams& P) {
+    const int nxny = P.nx * P.ny;
+    Nbr n;
+    n.xp = (x + 1 < P.nx) ? 1 : (P.wall_x ? 0 : 1 - P.nx);
+    n.xm = (x > 0) ? -1 : (P.wall_x ? 0 : P.nx - 1);
+    n.yp = (y + 1 < P.ny) ? P.nx : (P.wall_y ? 0 : (1 - P.ny) * P.nx);
+    n.ym = (y > 0) ? -P.nx : (P.wall_y ? 0 : (P.ny - 1) * P.nx);
+    n.zp = (z + 1 < P.nz) ? nxny : (P.wall_z ? 0 : (1 - P.nz) * nxny);
+    n.zm = (z > 0) ? -nxny : (P.wall_z ? 0 : (P.nz - 1) * nxny);
+    return n;
+}
+
+// offset of the node x + e
+template <int EX, int EY, int EZ>
+__device__ __forceinline__ int push_offset(const Nbr& n) {
+    return pull_offset<-EX, -EY, -EZ>(n);
 }
 
 // ---------------------------------------------------------------------------
@@ -195,7 +197,9 @@ __device__ __forceinline__ void st_pop(void* base, int idx, bool rest, float wre
 // block reduction of N doubles (entry `maxslot` takes a max, the others a sum),
 // fixed order, one result per work-group
 
-template <int N, int NT>
+// ACC: add to out (each work-group owns its out entries, so repeated launches
+// accumulate deterministically)
+template <int N, int NT, bool ACC = false>
 __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, double* out) {
     static_assert(NT % 64 == 0, "work-group must be whole waves");
     __shared__ double red[NT / 64][N];
@@ -218,7 +222,8 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
         for (int i = 0; i < N; ++i) {
             double a = red[0][i];
             for (int w = 1; w < NT / 64; ++w) a = (i == maxslot) ? fmax(a, red[w][i]) : a + red[w][i];
-            out[i] = a;
+            if constexpr (ACC) out[i] += a;
+            else out[i] = a;
         }
     }
 }
@@ -228,6 +233,14 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 1
+#endif
+// occupancy target of the adjoint node kernel (register budget 512 / waves): the
+// largest at which it does not spill (2D: 165 VGPRs, 3D: 234 VGPRs in FP32)
+#ifndef LBM_ADJ_WAVES_2D
+#define LBM_ADJ_WAVES_2D 3
+#endif
+#ifndef LBM_ADJ_WAVES_3D
+#define LBM_ADJ_WAVES_3D 2
 #endif
 #ifndef LBM_EARLY_F
 #define LBM_EARLY_F 1
@@ -258,7 +271,6 @@ k_lbm(const KParams P) {
     constexpr bool STENCIL = FLOW || MODE == MODE_DIAG;
     constexpr bool HAS_Y = SL::DIM == 3;
     using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
-    static_assert(MODE != MODE_ADJ || PREC == P32 || PREC == P64, "adjoint runs on FP32 / FP64 states");
     constexpr int LX = TX + 2;
     constexpr int LY = HAS_Y ? TY + 2 : 1;
     constexpr int OY = HAS_Y ? 1 : 0;
@@ -394,9 +406,6 @@ k_lbm(const KParams P) {
     double acc[NACC];
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
-    double th[MODE == MODE_ADJ ? 6 : 1];
-#pragma unroll
-    for (int i = 0; i < (MODE == MODE_ADJ ? 6 : 1); ++i) th[i] = 0.0;
 
     const double phi_ref = P.mean_subtract ? *P.phi_ref : 0.0;
 
@@ -509,6 +518,9 @@ k_lbm(const KParams P) {
 
             if constexpr (MODE == MODE_STEP) {
                 if (P.mean_subtract) acc[0] += m.phi;
+                if (P.ref_copy && blockIdx.x == 0 && tid == 0) *P.ref_copy = *P.phi_ref;
+                // phi of the source state, as the stencil saw it (for the adjoint)
+                if (P.phi_out) static_cast<C*>(P.phi_out)[idx] = phi;
 
                 // post-collision populations go to this node's own slots of the other copy
                 auto push = [&](auto s_, auto k_, auto lat_, C v) __attribute__((always_inline)) {
@@ -588,46 +600,6 @@ k_lbm(const KParams P) {
                     });
                 }
 
-            } else if constexpr (MODE == MODE_ADJ) {
-                // adjoint of this node's update: mu = dL/dQ(x) is the transposed
-                // streaming of lambda^(n+1), lambda_k(x + e_k) (walls were folded in by
-                // the pairwise exchange on lambda^(n+1)); lambda^n gets the local part
-                // here and the neighbour part in k_adj_gather.
-                constexpr int NS = SLOTS::N;
-                double Pf[QF > 0 ? QF : 1], Pg[QS], Pa[QS], Pb[QS];
-                double mu[NS], lb[NS];
-                static_for<0, QF>([&](auto kc) __attribute__((always_inline)) { Pf[kc.value] = double(fpop[kc.value]); });
-#pragma unroll
-                for (int k = 0; k < QS; ++k) { Pg[k] = double(g[k]); Pa[k] = double(a[k]); Pb[k] = double(b[k]); }
-                auto adj_load = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) {
-                    using L = typename decltype(lat_)::type;
-                    constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
-                    const unsigned t = unsigned(int(idx) + pull_offset<-L::ex(k), -L::ey(k), -L::ez(k)>(nbr));
-                    mu[S] = double(*reinterpret_cast<const float*>(P.adj_in + (unsigned long long)S * P.adj_stride +
-                                                                   (unsigned long long)t * 4u));
-                    lb[S] = 0.0;
-                };
-                static_for<0, QF>([&](auto kc) __attribute__((always_inline)) { adj_load(kc, kc, FLT{}); });
-                static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
-                    adj_load(IC<G0 + kc.value>{}, kc, SLT{});
-                    adj_load(IC<A0 + kc.value>{}, kc, SLT{});
-                    adj_load(IC<B0 + kc.value>{}, kc, SLT{});
-                });
-                const double Gd[3] = {double(grad[0]), double(grad[1]), double(grad[2])};
-                double Gb[3], Nb = 0.0;
-                node_adjoint<SL, FL>(Pf, Pg, Pa, Pb, Gd, double(nsum), double(pc), phi_ref, P, mu, mu + G0,
-                                     mu + A0, mu + B0, lb, lb + G0, lb + A0, lb + B0, Gb, Nb, th);
-#pragma unroll
-                for (int sidx = 0; sidx < NS; ++sidx)
-                    __builtin_nontemporal_store(float(lb[sidx]), reinterpret_cast<float*>(
-                        P.adj_out + (unsigned long long)sidx * P.adj_stride + (unsigned long long)idx * 4u));
-                double dphi[3];
-                dphi_dmoments(c_ps, sA, sB, P, dphi);
-                const float auxv[8] = {float(Gb[0]), float(Gb[1]), float(Gb[2]), float(Nb),
-                                       float(dphi[0]), float(dphi[1]), float(dphi[2]),
-                                       float(dphi_dK(c_ps, sA, sB, P))};
-#pragma unroll
-                for (int r = 0; r < 8; ++r) P.aux[(unsigned long long)r * P.aux_stride + idx] = auxv[r];
             } else if constexpr (MODE == MODE_MOMENTS) {
                 const double vals[kNumMom] = {m.phi, sA, sB, m.muA, m.muB, double(p_h),
                                               double(u[0]), double(u[1]), double(u[2])};
@@ -664,9 +636,7 @@ k_lbm(const KParams P) {
         }
     }
 
-    if constexpr (MODE == MODE_ADJ) {
-        block_reduce_store<6, NT>(th, -1, P.partials + 6 * tile);
-    } else if constexpr (MODE == MODE_DIAG) {
+    if constexpr (MODE == MODE_DIAG) {
         block_reduce_store<8, NT>(acc, 4, P.partials + 8 * tile);
     } else if constexpr (MODE == MODE_STEP) {
         if (P.mean_subtract) block_reduce_store<1, NT>(acc, -1, P.partials + tile);
@@ -719,44 +689,51 @@ __global__ void __launch_bounds__(256) k_walls(const KParams P, int axis) {
         for (int a = 0; a < 3; ++a) q[a] = (c[a] - e[a] + n[a]) % n[a];
         return (q[2] * P.ny + q[1]) * P.nx + q[0];
     };
-    // exchange slot S at node i with slot SO at node j (raw storage bits)
-    auto swap = [&](auto s_, auto so_, int i, int j) {
-        constexpr int S = decltype(s_)::value, SO = decltype(so_)::value;
-        char* ps = P.dst_base + slot_offset<SLOTS, S>(P);
-        char* po = P.dst_base + slot_offset<SLOTS, SO>(P);
-        if constexpr (PREC == P64) {
-            double* a = reinterpret_cast<double*>(ps) + i;
-            double* b = reinterpret_cast<double*>(po) + j;
-            const double va = *a, vb = *b;
-            *a = vb; *b = va;
-        } else if constexpr (PREC == P32) {
-            float* a = reinterpret_cast<float*>(ps) + i;
-            float* b = reinterpret_cast<float*>(po) + j;
-            const float va = *a, vb = *b;
-            *a = vb; *b = va;
-        } else {  // moving populations only (k != 0): 16-bit words with equal references
-            unsigned short* a = reinterpret_cast<unsigned short*>(ps) + i;
-            unsigned short* b = reinterpret_cast<unsigned short*>(po) + j;
-            const unsigned short va = *a, vb = *b;
-            *a = vb; *b = va;
+    // raw storage word of slot S at node i
+    using Word = typename std::conditional<PREC == P64, double,
+                                           typename std::conditional<PREC == P32, float, unsigned short>::type>::type;
+    auto word = [&](auto s_, int i) -> Word* {
+        constexpr int S = decltype(s_)::value;
+        return reinterpret_cast<Word*>(P.dst_base + slot_offset<SLOTS, S>(P)) + i;
+    };
+    // every exchange pair (slot k at wrap(x - e_k), slot opp(k) at x), k < opp(k);
+    // 16-bit formats: moving populations only (equal references for k and opp(k))
+    auto pairs = [&](auto&& fn) {
+        auto lattice = [&](auto lat_, auto base_) {
+            using L = typename decltype(lat_)::type;
+            constexpr int B = decltype(base_)::value;
+            static_for<1, L::Q>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int o = L::opp(k);
+                if constexpr (k < o) fn(IC<B + k>{}, IC<B + o>{}, IC<L::ex(k)>{}, IC<L::ey(k)>{}, IC<L::ez(k)>{});
+            });
+        };
+        if constexpr (FL::Q > 0) lattice(std::common_type<FL>{}, IC<0>{});
+        lattice(std::common_type<SL>{}, IC<SLOTS::G0>{});
+        lattice(std::common_type<SL>{}, IC<SLOTS::A0>{});
+        lattice(std::common_type<SL>{}, IC<SLOTS::B0>{});
+    };
+    constexpr int NP = (FL::Q > 0 ? (FL::Q - 1) / 2 : 0) + 3 * ((SL::Q - 1) / 2);
+    // all loads first, then all stores: the round trips overlap
+    Word va[NP], vb[NP];
+    bool cr[NP];
+    int np = 0;
+    pairs([&](auto s_, auto o_, auto ex_, auto ey_, auto ez_) {
+        const int p = np++;
+        cr[p] = crosses(ex_.value, ey_.value, ez_.value);
+        if (cr[p]) {
+            va[p] = *word(s_, source(ex_.value, ey_.value, ez_.value));
+            vb[p] = *word(o_, idx);
         }
-    };
-    auto fix_lattice = [&](auto lat_, auto base_) {
-        using L = typename decltype(lat_)::type;
-        constexpr int B = decltype(base_)::value;
-        static_for<1, L::Q>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            constexpr int o = L::opp(k);
-            if constexpr (k < o) {
-                if (crosses(L::ex(k), L::ey(k), L::ez(k)))
-                    swap(IC<B + k>{}, IC<B + o>{}, source(L::ex(k), L::ey(k), L::ez(k)), idx);
-            }
-        });
-    };
-    if constexpr (FL::Q > 0) fix_lattice(std::common_type<FL>{}, IC<0>{});
-    fix_lattice(std::common_type<SL>{}, IC<SLOTS::G0>{});
-    fix_lattice(std::common_type<SL>{}, IC<SLOTS::A0>{});
-    fix_lattice(std::common_type<SL>{}, IC<SLOTS::B0>{});
+    });
+    np = 0;
+    pairs([&](auto s_, auto o_, auto ex_, auto ey_, auto ez_) {
+        const int p = np++;
+        if (cr[p]) {
+            *word(s_, source(ex_.value, ey_.value, ez_.value)) = vb[p];
+            *word(o_, idx) = va[p];
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -862,56 +839,27 @@ __global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, 
 }
 
 // ---------------------------------------------------------------------------
-// adjoint kernels.  Adjoint populations lambda_k(x) = dL / dX_k(x) of the arriving
-// populations live in FP32 [slot][node] buffers (P.adj_in / P.adj_out).
+// adjoint kernels.  The adjoint of the arriving population X_s(x) is lambda_s(x)
+// (FP32 [slot][node], P.adj_in / P.adj_out) plus c_F(x) (aux rows 7..9) when s is a
+// scalar population of field F.  Kernels over nodes use 256-thread work-groups; their
+// theta partials accumulate in P.partials + 6 * blockIdx.x.
 
 template <class SL, class FL>
-__device__ __forceinline__ float& adj_at(char* base, const KParams& P, int slot, unsigned idx) {
-    return *reinterpret_cast<float*>(base + (unsigned long long)slot * P.adj_stride + (unsigned long long)idx * 4u);
+__device__ __forceinline__ float* adj_at(const char* base, const KParams& P, int slot, unsigned long long idx) {
+    return reinterpret_cast<float*>(const_cast<char*>(base) + (unsigned long long)slot * P.adj_stride + idx * 4u);
 }
 
-// seed: lambda^T = dL/dphi_T * dphi/dP of the final moment phi (Eq. Moment0_Phi)
-// The moment depends on K = M_phi / W^2 through the predictor: dL/dK partials per
-// work-group go to P.partials (6 per work-group, theta order).
-template <class SL, class FL, int PREC>
-__global__ void __launch_bounds__(256) k_adj_seed(const KParams P, long long nodes,
-                                                  const double* __restrict__ dL_dphi) {
-    using SLOTS = Slots<FL::Q, SL::Q>;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double th[6] = {0, 0, 0, 0, 0, 0};
-    if (i < nodes) {
-    const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
-    const Nbr nb = neighbours(x, y, z, P);
-    double ps = 0.0, cA = 0.0, cB = 0.0;
-    static_for<0, SL::Q>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        const unsigned t = unsigned(int(i) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
-        ps += double(ld_at<PREC, SLOTS::rest(SLOTS::G0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::G0 + k>(P), t,
-                                                                float(SL::w(k)) * P.fref[1], P.finv[1]));
-        cA += double(ld_at<PREC, SLOTS::rest(SLOTS::A0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::A0 + k>(P), t,
-                                                                float(SL::w(k)) * P.fref[2], P.finv[2]));
-        cB += double(ld_at<PREC, SLOTS::rest(SLOTS::B0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::B0 + k>(P), t,
-                                                                float(SL::w(k)) * P.fref[3], P.finv[3]));
-    });
-    double d[3];
-    dphi_dmoments(ps, cA, cB, P, d);
-    const double s = dL_dphi[i];
-    for (int k = 0; k < FL::Q; ++k) adj_at<SL, FL>(P.adj_out, P, k, unsigned(i)) = 0.0f;
-    for (int k = 0; k < SL::Q; ++k) {
-        adj_at<SL, FL>(P.adj_out, P, SLOTS::G0 + k, unsigned(i)) = float(s * d[0]);
-        adj_at<SL, FL>(P.adj_out, P, SLOTS::A0 + k, unsigned(i)) = float(s * d[1]);
-        adj_at<SL, FL>(P.adj_out, P, SLOTS::B0 + k, unsigned(i)) = float(s * d[2]);
-    }
-    const double K_b = s * dphi_dK(ps, cA, cB, P);
-    th[0] = K_b / (P.W * P.W);
-    th[5] = K_b * (-2.0 * P.mphi_w2 / P.W);
-    }
-    block_reduce_store<6, 256>(th, -1, P.partials + 6 * blockIdx.x);
+__device__ __forceinline__ void theta_from_K(double K_b, const KParams& P, double (&th)[6]) {
+    // K = M_phi / W^2
+    th[0] += K_b / (P.W * P.W);
+    th[5] += K_b * (-2.0 * P.mphi_w2 / P.W);
 }
 
-// Transposed streaming needs mu_k(x) = lambda_k(x + e_k), or lambda_opp(k)(x) when
-// x + e_k lies across a wall.  Exchanging lambda_k at wrap(x + e_k) with
-// lambda_opp(k) at x for every such pair (once, k < opp(k)) lets the adjoint step
+// Transposed streaming at walls.  The adjoint step needs mu_k(x) = Lambda_k(x + e_k),
+// or Lambda_opp(k)(x) when x + e_k lies across a wall (bounce-back), where Lambda =
+// lambda (+ c_F for scalar fields).  For every such pair (once, k < opp(k)) this
+// kernel exchanges the full adjoints Lambda_k(x'') and Lambda_opp(k)(x), x'' =
+// wrap(x + e_k), storing each minus the c_F of its new node, so that the step can
 // gather periodically.  Same face enumeration as k_walls.
 template <class SL, class FL>
 __global__ void __launch_bounds__(256) k_adj_walls(const KParams P, int axis) {
@@ -930,109 +878,296 @@ __global__ void __launch_bounds__(256) k_adj_walls(const KParams P, int axis) {
     for (int a = 0; a < axis; ++a)
         if (wall[a] && (c[a] == 0 || c[a] == n[a] - 1)) return;
     if (n[axis] == 1 && t >= face) return;
-    const unsigned idx = unsigned((c[2] * P.ny + c[1]) * P.nx + c[0]);
-    char* buf = const_cast<char*>(P.adj_in);
-    auto fix_lattice = [&](auto lat_, auto base_) {
-        using L = typename decltype(lat_)::type;
-        constexpr int B = decltype(base_)::value;
-        static_for<1, L::Q>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            constexpr int o = L::opp(k);
-            if constexpr (k < o) {
-                const int e[3] = {L::ex(k), L::ey(k), L::ez(k)};
-                bool cross = false;
-                int q[3];
-                for (int a = 0; a < 3; ++a) {
-                    if (wall[a] && e[a] != 0 && (c[a] + e[a] < 0 || c[a] + e[a] >= n[a])) cross = true;
-                    q[a] = (c[a] + e[a] + n[a]) % n[a];
-                }
-                if (cross) {
-                    float& va = adj_at<SL, FL>(buf, P, B + k, unsigned((q[2] * P.ny + q[1]) * P.nx + q[0]));
-                    float& vb = adj_at<SL, FL>(buf, P, B + o, idx);
-                    const float ta = va, tb = vb;
-                    va = tb;
-                    vb = ta;
-                }
-            }
-        });
+    const unsigned long long idx = (unsigned long long)((c[2] * P.ny + c[1]) * P.nx + c[0]);
+    float* lam = reinterpret_cast<float*>(const_cast<char*>(P.adj_in));
+    const unsigned long long ls = P.adj_stride / 4;
+    const float* cin = P.aux + kAuxC * P.aux_stride;
+    auto pairs = [&](auto&& fn) {
+        auto lattice = [&](auto lat_, auto base_, auto field_) {
+            using L = typename decltype(lat_)::type;
+            constexpr int B = decltype(base_)::value;
+            static_for<1, L::Q>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int o = L::opp(k);
+                if constexpr (k < o) fn(IC<B + k>{}, IC<B + o>{}, field_, IC<L::ex(k)>{}, IC<L::ey(k)>{}, IC<L::ez(k)>{});
+            });
+        };
+        if constexpr (FL::Q > 0) lattice(std::common_type<FL>{}, IC<0>{}, IC<-1>{});
+        lattice(std::common_type<SL>{}, IC<SLOTS::G0>{}, IC<0>{});
+        lattice(std::common_type<SL>{}, IC<SLOTS::A0>{}, IC<1>{});
+        lattice(std::common_type<SL>{}, IC<SLOTS::B0>{}, IC<2>{});
     };
-    if constexpr (FL::Q > 0) fix_lattice(std::common_type<FL>{}, IC<0>{});
-    fix_lattice(std::common_type<SL>{}, IC<SLOTS::G0>{});
-    fix_lattice(std::common_type<SL>{}, IC<SLOTS::A0>{});
-    fix_lattice(std::common_type<SL>{}, IC<SLOTS::B0>{});
+    // node wrap(x + e) and whether x + e lies across a wall
+    auto target = [&](int ex, int ey, int ez, bool& cross) {
+        const int e[3] = {ex, ey, ez};
+        int q[3];
+        cross = false;
+        for (int a = 0; a < 3; ++a) {
+            if (wall[a] && e[a] != 0 && (c[a] + e[a] < 0 || c[a] + e[a] >= n[a])) cross = true;
+            q[a] = (c[a] + e[a] + n[a]) % n[a];
+        }
+        return (unsigned long long)((q[2] * P.ny + q[1]) * P.nx + q[0]);
+    };
+    constexpr int NP = (FL::Q > 0 ? (FL::Q - 1) / 2 : 0) + 3 * ((SL::Q - 1) / 2);
+    float fa[NP], fb[NP], ca[NP], cb[NP];
+    bool cr[NP];
+    int np = 0;
+    // loads of every pair first, then the stores
+    pairs([&](auto s_, auto o_, auto f_, auto ex_, auto ey_, auto ez_) {
+        constexpr int S = decltype(s_)::value, O = decltype(o_)::value, F = decltype(f_)::value;
+        const int p = np++;
+        const unsigned long long xq = target(ex_.value, ey_.value, ez_.value, cr[p]);
+        if (cr[p]) {
+            ca[p] = F >= 0 ? cin[F * P.aux_stride + xq] : 0.0f;
+            cb[p] = F >= 0 ? cin[F * P.aux_stride + idx] : 0.0f;
+            fa[p] = lam[S * ls + xq] + ca[p];
+            fb[p] = lam[O * ls + idx] + cb[p];
+        }
+    });
+    np = 0;
+    pairs([&](auto s_, auto o_, auto f_, auto ex_, auto ey_, auto ez_) {
+        constexpr int S = decltype(s_)::value, O = decltype(o_)::value;
+        const int p = np++;
+        bool cross;
+        const unsigned long long xq = target(ex_.value, ey_.value, ez_.value, cross);
+        if (cr[p]) {
+            lam[S * ls + xq] = fb[p] - ca[p];
+            lam[O * ls + idx] = fa[p] - cb[p];
+        }
+    });
+}
+
+// Adjoint of one step, one thread per node.  mu = dL/dQ(x) is the transposed
+// streaming of the adjoint of step n + 1 (walls exchanged by k_adj_walls).  The arriving populations of state n are pulled
+// as in the step; the phi stencil reads phi of state n (`phi`, written by the step
+// that left state n).  lambda^n gets the local part (P.adj_out); dL/dG, dL/dN and the
+// sensitivities of phi go to aux rows 0..6 for k_adj_gather; theta partials
+// accumulate per work-group.
+template <class SL, class FL, int PREC>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(SL::DIM == 2 ? LBM_ADJ_WAVES_2D : LBM_ADJ_WAVES_3D)))
+k_adj_node(const KParams P, long long nodes, const typename Stor<PREC>::C* __restrict__ phi) {
+    using C = typename Stor<PREC>::C;
+    using T = C;
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
+    constexpr int QS = SL::Q, QF = FL::Q;
+    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
+    using SLT = std::common_type<SL>;
+    using FLT = std::common_type<FL>;
+    // 32-bit node index (nodes < 2^31): keeps every access in the voffset + saddr form
+    const unsigned idx = blockIdx.x * 256u + threadIdx.x;
+    double th[6] = {0, 0, 0, 0, 0, 0};
+    if (idx < (unsigned long long)nodes) {
+        const unsigned nxny = unsigned(P.nx) * unsigned(P.ny);
+        const int z = int(idx / nxny), r = int(idx - unsigned(z) * nxny);
+        const int y = r / P.nx, x = r - y * P.nx;
+        const Nbr nbr = neighbours(x, y, z, P);
+        auto load = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> C {
+            using L = typename decltype(lat_)::type;
+            constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
+            const unsigned t = unsigned(int(idx) + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nbr));
+            return ld_at<PREC, SLOTS::rest(S)>(P.src_base + slot_offset<SLOTS, S>(P), t,
+                                               float(L::w(k)) * P.fref[SLOTS::field(S)], P.finv[SLOTS::field(S)]);
+        };
+        C fpop[QF > 0 ? QF : 1], g[QS], a[QS], b[QS];
+        static_for<0, QF>([&](auto kc) __attribute__((always_inline)) { fpop[kc.value] = load(kc, kc, FLT{}); });
+        static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
+            g[kc.value] = load(IC<G0 + kc.value>{}, kc, SLT{});
+            a[kc.value] = load(IC<A0 + kc.value>{}, kc, SLT{});
+            b[kc.value] = load(IC<B0 + kc.value>{}, kc, SLT{});
+        });
+        // phi stencil inputs of Eqs. Grad and Laplacian (mirror ghosts at walls)
+        double G[3] = {0.0, 0.0, 0.0}, Nsum = 0.0, pc = 0.0;
+        if constexpr (QF > 0) {
+            const Nbr sn = stencil_neighbours(x, y, z, P);
+            const char* pb = reinterpret_cast<const char*>(phi);
+            pc = double(*reinterpret_cast<const C*>(pb + voff(idx * unsigned(sizeof(C)))));
+            static_for<1, STL::Q>([&](auto kc) __attribute__((always_inline)) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int ex = STL::ex(k), ey = STL::ey(k), ez = STL::ez(k);
+                const unsigned t = unsigned(int(idx) + push_offset<ex, ey, ez>(sn));
+                const double v = double(*reinterpret_cast<const C*>(pb + voff(t * unsigned(sizeof(C))))) *
+                                 (3.0 * STL::w(k));
+                if constexpr (ex != 0) G[0] += ex > 0 ? v : -v;
+                if constexpr (ey != 0) G[1] += ey > 0 ? v : -v;
+                if constexpr (ez != 0) G[2] += ez > 0 ? v : -v;
+                Nsum += v;
+            });
+        }
+        const float* cin = P.aux + kAuxC * P.aux_stride;
+        // mu_s(x) = Lambda_s(wrap(x + e_s)); wall pairs were exchanged by k_adj_walls
+        auto mu_of = [&](auto s_) __attribute__((always_inline)) -> T {
+            constexpr int S = decltype(s_)::value;
+            constexpr bool FLUID = S < G0;
+            constexpr int F = FLUID ? -1 : (S - G0) / QS;  // scalar field 0 g, 1 hA, 2 hB
+            constexpr int k = FLUID ? S : (S - G0) % QS;
+            using L = typename std::conditional<FLUID, FL, SL>::type;
+            // wave-uniform bases, 32-bit byte offsets (global_load voffset, saddr)
+            const unsigned t = unsigned(int(idx) + push_offset<L::ex(k), L::ey(k), L::ez(k)>(nbr));
+            const char* ls = P.adj_in + (unsigned long long)S * P.adj_stride;
+            const unsigned o = voff(t * 4u);
+            float v = *reinterpret_cast<const float*>(ls + o);
+            if constexpr (F >= 0) {
+                const char* cf = reinterpret_cast<const char*>(cin + (unsigned long long)F * P.aux_stride);
+                v += *reinterpret_cast<const float*>(cf + o);
+            }
+            return T(v);
+        };
+        // adjoint of step n + 1 read once into registers
+        T muv[SLOTS::N];
+        static_for<0, SLOTS::N>([&](auto sc) __attribute__((always_inline)) { muv[sc.value] = mu_of(sc); });
+        auto mu_reg = [&](auto s_) __attribute__((always_inline)) -> T { return muv[decltype(s_)::value]; };
+        const unsigned own = voff(idx * 4u);
+        auto put = [&](auto s_, T v) __attribute__((always_inline)) {
+            char* o = P.adj_out + (unsigned long long)decltype(s_)::value * P.adj_stride;
+            __builtin_nontemporal_store(float(v), reinterpret_cast<float*>(o + own));
+        };
+        const double phi_ref = P.mean_subtract ? *P.phi_ref : 0.0;
+        double Gb[3], Nb = 0.0;
+        node_adjoint<SL, FL, T>(fpop, g, a, b, G, Nsum, pc, phi_ref, P, mu_reg, put, Gb, Nb, th);
+        double ps = 0.0, sA = 0.0, sB = 0.0;
+        for (int k = 0; k < QS; ++k) { ps += double(g[k]); sA += double(a[k]); sB += double(b[k]); }
+        const PhiSens ds = phi_sensitivities(ps, sA, sB, P);
+        auto aux_put = [&](int row, double v) __attribute__((always_inline)) {
+            char* o = reinterpret_cast<char*>(P.aux + (unsigned long long)row * P.aux_stride);
+            *reinterpret_cast<float*>(o + own) = float(v);
+        };
+        if constexpr (QF > 0) {
+            aux_put(0, Gb[0]);
+            if constexpr (SL::DIM == 3) aux_put(1, Gb[1]);
+            aux_put(2, Gb[2]);
+            aux_put(3, Nb);
+        }
+        aux_put(4, ds.d0);
+        aux_put(5, ds.q);
+        aux_put(6, ds.dK);
+    }
+    block_reduce_store<6, 256, true>(th, -1, P.partials + 6 * blockIdx.x);
+}
+
+// seed: the final moment phi_T (Eq. Moment0_Phi) of the state at P.src_base receives
+// dL/dphi_T: lambda = 0, c_F = dL/dphi dphi/dF, theta via dphi/dK
+template <class SL, class FL, int PREC>
+__global__ void __launch_bounds__(256) k_adj_seed(const KParams P, long long nodes,
+                                                  const double* __restrict__ dL_dphi) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double th[6] = {0, 0, 0, 0, 0, 0};
+    if (i < nodes) {
+        const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
+        const Nbr nb = neighbours(x, y, z, P);
+        double ps = 0.0, cA = 0.0, cB = 0.0;
+        static_for<0, SL::Q>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const unsigned t = unsigned(int(i) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
+            ps += double(ld_at<PREC, SLOTS::rest(SLOTS::G0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::G0 + k>(P), t,
+                                                                    float(SL::w(k)) * P.fref[1], P.finv[1]));
+            cA += double(ld_at<PREC, SLOTS::rest(SLOTS::A0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::A0 + k>(P), t,
+                                                                    float(SL::w(k)) * P.fref[2], P.finv[2]));
+            cB += double(ld_at<PREC, SLOTS::rest(SLOTS::B0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::B0 + k>(P), t,
+                                                                    float(SL::w(k)) * P.fref[3], P.finv[3]));
+        });
+        const PhiSens ds = phi_sensitivities(ps, cA, cB, P);
+        const double s = dL_dphi[i];
+        for (int k = 0; k < SLOTS::N; ++k) *adj_at<SL, FL>(P.adj_out, P, k, i) = 0.0f;
+        float* c = P.aux + kAuxC * P.aux_stride;
+        c[0 * P.aux_stride + i] = float(s * ds.d0);
+        c[1 * P.aux_stride + i] = float(s * ds.q * (P.c1A - P.c0A));
+        c[2 * P.aux_stride + i] = float(s * ds.q * (P.c1B - P.c0B));
+        theta_from_K(s * ds.dK, P, th);
+    }
+    block_reduce_store<6, 256, true>(th, -1, P.partials + 6 * blockIdx.x);
 }
 
 // Transpose of the phi stencil (mirror ghosts at walls, wrap otherwise): node y
 // collects psi(y) = sum over (x, k) with map(x + e_k) = y of 3 w_k (e_k . Gb(x) + Nb(x)),
-// Gb, Nb = aux rows 0..3.  MODE 0 (adjoint step): lambda^n_{g,hA,hB}(y) += psi(y) *
-// dphi/d(phi*, c^A, c^B)(y) (aux rows 4..6), in place in adj_out, and psi(y) dphi/dK(y)
-// (aux row 7) reaches M_phi and W through K = M_phi / W^2 (work-group partials in
-// P.partials).  MODE 1 (initial
-// state): grad_phi0(y) = aux row 4 + psi(y).
+// Gb, Nb = aux rows 0..3.  GMODE 0 (adjoint step): phi(y) = Phi(sum g, c^A, c^B)(y), so
+// c_F(y) = psi(y) dphi/dF(y) (aux rows 4, 5) and theta receives psi(y) dphi/dK(y)
+// (aux row 6).  GMODE 1 (initial state, phi_0 an input): grad_phi0(y) = aux row 4 + psi(y).
 template <class SL, class FL, int GMODE>
 __global__ void __launch_bounds__(256) k_adj_gather(const KParams P, long long nodes, double* __restrict__ grad_phi0) {
-    using SLOTS = Slots<FL::Q, SL::Q>;
     using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned i = blockIdx.x * 256u + threadIdx.x;
     double th[6] = {0, 0, 0, 0, 0, 0};
-    if (i < nodes) {
-    const int yc[3] = {int(i % P.nx), int((i / P.nx) % P.ny), int(i / ((long long)P.nx * P.ny))};
-    const int n[3] = {P.nx, P.ny, P.nz};
-    const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
-    const unsigned long long as = P.aux_stride;
-    double psi = 0.0;
-    if constexpr (FL::Q > 0 || GMODE == 1) {
-        static_for<1, STL::Q>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            const int e[3] = {STL::ex(k), STL::ey(k), STL::ez(k)};
-            // candidate source coordinates per axis (at most two)
-            int cand[3][2], nc[3];
-            for (int a = 0; a < 3; ++a) {
-                nc[a] = 0;
-                if (e[a] == 0) {
-                    cand[a][nc[a]++] = yc[a];
-                } else if (!wall[a]) {
-                    cand[a][nc[a]++] = (yc[a] - e[a] + n[a]) % n[a];
-                } else {
-                    const int s = yc[a] - e[a];
-                    if (s >= 0 && s < n[a]) cand[a][nc[a]++] = s;
-                    if ((e[a] < 0 && yc[a] == 0) || (e[a] > 0 && yc[a] == n[a] - 1)) cand[a][nc[a]++] = yc[a];
-                }
-            }
-            const double w3 = 3.0 * STL::w(k);
-            for (int i0 = 0; i0 < nc[0]; ++i0)
-                for (int i1 = 0; i1 < nc[1]; ++i1)
-                    for (int i2 = 0; i2 < nc[2]; ++i2) {
-                        const unsigned long long xs =
-                            (unsigned long long)((cand[2][i2] * P.ny + cand[1][i1]) * P.nx + cand[0][i0]);
-                        const double gb = double(P.aux[0 * as + xs]) * e[0] + double(P.aux[1 * as + xs]) * e[1] +
-                                          double(P.aux[2 * as + xs]) * e[2];
-                        psi += w3 * (gb + double(P.aux[3 * as + xs]));
+    if (i < (unsigned long long)nodes) {
+        const unsigned nxny = unsigned(P.nx) * unsigned(P.ny);
+        const int z = int(i / nxny), r = int(i - unsigned(z) * nxny);
+        const int y = r / P.nx, x = r - y * P.nx;
+        const int yc[3] = {x, y, z};
+        const int n[3] = {P.nx, P.ny, P.nz};
+        const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
+        const unsigned long long as = P.aux_stride;
+        auto row = [&](int rr) { return reinterpret_cast<const char*>(P.aux + (unsigned long long)rr * as); };
+        auto at = [&](int rr, unsigned node) { return *reinterpret_cast<const float*>(row(rr) + voff(node * 4u)); };
+        float psi = 0.0f;
+        if constexpr (FL::Q > 0) {
+            bool near_wall = false;
+            for (int a = 0; a < 3; ++a) near_wall |= wall[a] && (yc[a] == 0 || yc[a] == n[a] - 1);
+            if (!near_wall) {
+                // sources x = wrap(y - e_k)
+                const Nbr nb = neighbours(x, y, z, P);
+                static_for<1, STL::Q>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    constexpr int ex = STL::ex(k), ey = STL::ey(k), ez = STL::ez(k);
+                    const unsigned xs = unsigned(int(i) + pull_offset<ex, ey, ez>(nb));
+                    float gb = at(3, xs);
+                    if constexpr (ex != 0) gb += ex > 0 ? at(0, xs) : -at(0, xs);
+                    if constexpr (ey != 0) gb += ey > 0 ? at(1, xs) : -at(1, xs);
+                    if constexpr (ez != 0) gb += ez > 0 ? at(2, xs) : -at(2, xs);
+                    psi += float(3.0 * STL::w(k)) * gb;
+                });
+            } else {
+                // along a wall axis a source is y - e_k when inside, and y itself when
+                // y + e_k lies beyond the wall (its mirror ghost is y)
+                static_for<1, STL::Q>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    constexpr int e[3] = {STL::ex(k), STL::ey(k), STL::ez(k)};
+                    int cand[3][2], nc[3];
+                    for (int a = 0; a < 3; ++a) {
+                        nc[a] = 0;
+                        if (e[a] == 0) {
+                            cand[a][nc[a]++] = yc[a];
+                        } else if (!wall[a]) {
+                            cand[a][nc[a]++] = (yc[a] - e[a] + n[a]) % n[a];
+                        } else {
+                            const int sa = yc[a] - e[a];
+                            if (sa >= 0 && sa < n[a]) cand[a][nc[a]++] = sa;
+                            if ((e[a] < 0 && yc[a] == 0) || (e[a] > 0 && yc[a] == n[a] - 1)) cand[a][nc[a]++] = yc[a];
+                        }
                     }
-        });
-    }
-    if constexpr (GMODE == 1) {
-        grad_phi0[i] = double(P.aux[4 * as + i]) + psi;
-    } else {
-        const double d0 = P.aux[4 * as + i], d1 = P.aux[5 * as + i], d2 = P.aux[6 * as + i];
-        for (int k = 0; k < SL::Q; ++k) {
-            adj_at<SL, FL>(P.adj_out, P, SLOTS::G0 + k, unsigned(i)) += float(psi * d0);
-            adj_at<SL, FL>(P.adj_out, P, SLOTS::A0 + k, unsigned(i)) += float(psi * d1);
-            adj_at<SL, FL>(P.adj_out, P, SLOTS::B0 + k, unsigned(i)) += float(psi * d2);
+                    for (int i0 = 0; i0 < nc[0]; ++i0)
+                        for (int i1 = 0; i1 < nc[1]; ++i1)
+                            for (int i2 = 0; i2 < nc[2]; ++i2) {
+                                const unsigned xs = unsigned((cand[2][i2] * P.ny + cand[1][i1]) * P.nx + cand[0][i0]);
+                                float gb = at(3, xs);
+                                if constexpr (e[0] != 0) gb += e[0] * at(0, xs);
+                                if constexpr (e[1] != 0) gb += e[1] * at(1, xs);
+                                if constexpr (e[2] != 0) gb += e[2] * at(2, xs);
+                                psi += float(3.0 * STL::w(k)) * gb;
+                            }
+                });
+            }
         }
-        // phi(y) also depends on K = M_phi / W^2 (aux row 7: dphi/dK)
-        const double K_b = psi * double(P.aux[7 * as + i]);
-        th[0] = K_b / (P.W * P.W);
-        th[5] = K_b * (-2.0 * P.mphi_w2 / P.W);
+        if constexpr (GMODE == 1) {
+            grad_phi0[i] = double(at(4, i)) + double(psi);
+        } else {
+            const float q = at(5, i);
+            char* cbase = reinterpret_cast<char*>(P.aux + kAuxC * as);
+            const unsigned o = voff(i * 4u);
+            *reinterpret_cast<float*>(cbase + o) = psi * at(4, i);
+            *reinterpret_cast<float*>(cbase + as * 4u + o) = psi * q * float(P.c1A - P.c0A);
+            *reinterpret_cast<float*>(cbase + 2 * as * 4u + o) = psi * q * float(P.c1B - P.c0B);
+            theta_from_K(double(psi) * double(at(6, i)), P, th);
+        }
     }
-    }
-    if constexpr (GMODE == 0) block_reduce_store<6, 256>(th, -1, P.partials + 6 * blockIdx.x);
+    if constexpr (GMODE == 0) block_reduce_store<6, 256, true>(th, -1, P.partials + 6 * blockIdx.x);
 }
 
-// Adjoint of the initialisation (k_init) with mu_0 held fixed: lambda^0 (adj_in)
-// back to phi_0.  Local part per node into aux (rows 0..3: Gb, Nb of the F_0
-// stencil; row 4: local dL/dphi_0), parameter partials per work-group; the
-// stencil part closes in k_adj_gather<.., 1>.
+// Adjoint of the initialisation (k_init) with mu_0 held fixed: the adjoint of the
+// initial populations (lambda + c in P.adj_in / aux) back to phi_0.  Local part per
+// node into aux (rows 0..3: Gb, Nb of the F_0 stencil; row 4: local dL/dphi_0), theta
+// partials per work-group; the stencil part closes in k_adj_gather<.., 1>.
 template <class SL, class FL>
 __global__ void __launch_bounds__(256) k_adj_init_local(const KParams P, long long nodes,
                                                         const double* __restrict__ phi0,
@@ -1044,31 +1179,32 @@ __global__ void __launch_bounds__(256) k_adj_init_local(const KParams P, long lo
     double th[6] = {0, 0, 0, 0, 0, 0};
     if (i < nodes) {
         const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
-        char* lam = const_cast<char*>(P.adj_in);
+        const unsigned long long as = P.aux_stride;
+        const float* c = P.aux + kAuxC * as;
+        const double cg = c[0 * as + i], cAa = c[1 * as + i], cBb = c[2 * as + i];
         const double phi = phi0[i], muA = muA0[i], muB = muB0[i];
-        const double dA = P.c1A - P.c0A, dB = P.c1B - P.c0B, eA = -dA, eB = -dB;
+        const double dA = P.c1A - P.c0A, dB = P.c1B - P.c0B;
         const double K = P.mphi_w2;
-        const double dw = -(muA * eA + muB * eB);
+        const double dw = muA * dA + muB * dB;
         double phi_b = 0.0, S_b = 0.0;
         // g_k = w_k phi - w_k S_0 / 2; h_0 = c - (1 - w_0) mu, c = mu + c_0 + p(phi)(c_1 - c_0)
         for (int k = 0; k < SL::Q; ++k) {
-            const double lg = adj_at<SL, FL>(lam, P, SLOTS::G0 + k, unsigned(i));
+            const double lg = double(*adj_at<SL, FL>(P.adj_in, P, SLOTS::G0 + k, i)) + cg;
             phi_b += lg * SL::w(k);
             S_b += -0.5 * lg * SL::w(k);
         }
-        phi_b += (double(adj_at<SL, FL>(lam, P, SLOTS::A0, unsigned(i))) * dA +
-                  double(adj_at<SL, FL>(lam, P, SLOTS::B0, unsigned(i))) * dB) * interp_dp(phi);
+        const double lA = double(*adj_at<SL, FL>(P.adj_in, P, SLOTS::A0, i)) + cAa;
+        const double lB = double(*adj_at<SL, FL>(P.adj_in, P, SLOTS::B0, i)) + cBb;
+        phi_b += (lA * dA + lB * dB) * interp_dp(phi);
         // S_0 = K (lambda p'(phi) dw - omega_dw'(phi))
-        const double K_b = S_b * (P.lam * interp_dp(phi) * dw - dwell_d(phi));
+        theta_from_K(S_b * (P.lam * interp_dp(phi) * dw - dwell_d(phi)), P, th);
         phi_b += S_b * K * (P.lam * interp_ddp(phi) * dw - dwell_dd(phi));
-        th[0] += K_b / (P.W * P.W);
-        th[5] += K_b * (-2.0 * K / P.W);
         double Gb[3] = {0.0, 0.0, 0.0}, Nb = 0.0;
         if constexpr (FL::Q > 0) {
             // f_k = -w_k (e_k . F_0) / 2
             double F_b[3] = {0.0, 0.0, 0.0};
             for (int k = 0; k < FL::Q; ++k) {
-                const double lf = adj_at<SL, FL>(lam, P, k, unsigned(i));
+                const double lf = *adj_at<SL, FL>(P.adj_in, P, k, i);
                 F_b[0] += -0.5 * FL::w(k) * FL::ex(k) * lf;
                 F_b[1] += -0.5 * FL::w(k) * FL::ey(k) * lf;
                 F_b[2] += -0.5 * FL::w(k) * FL::ez(k) * lf;
@@ -1095,25 +1231,42 @@ __global__ void __launch_bounds__(256) k_adj_init_local(const KParams P, long lo
             Nb = 2.0 * lap_b;
             phi_b += -6.0 * (1.0 - STL::w(0)) * lap_b;
         }
-        const unsigned long long as = P.aux_stride;
         P.aux[0 * as + i] = float(Gb[0]);
         P.aux[1 * as + i] = float(Gb[1]);
         P.aux[2 * as + i] = float(Gb[2]);
         P.aux[3 * as + i] = float(Nb);
         P.aux[4 * as + i] = float(phi_b);
     }
-    block_reduce_store<6, 256>(th, -1, P.partials + 6 * blockIdx.x);
+    block_reduce_store<6, 256, true>(th, -1, P.partials + 6 * blockIdx.x);
 }
 
-// copy of the current adjoint populations to / from FP64 [slot][node]
-template <bool SET>
-__global__ void __launch_bounds__(256) k_adj_copy(const KParams P, int nslots, long long nodes, double* buf) {
+// the adjoint as FP64 [slot][node] (lambda + c_F) from P.adj_in, or from such an
+// array into P.adj_out (lambda = value, c_F = 0)
+template <class SL, class FL, bool SET>
+__global__ void __launch_bounds__(256) k_adj_copy(const KParams P, long long nodes, double* buf) {
+    using SLOTS = Slots<FL::Q, SL::Q>;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
-    if (i >= nodes || s >= nslots) return;
-    float* a = reinterpret_cast<float*>(const_cast<char*>(P.adj_in) + (unsigned long long)s * P.adj_stride) + i;
-    if constexpr (SET) *a = float(buf[s * nodes + i]);
-    else buf[s * nodes + i] = double(*a);
+    if (i >= nodes || s >= SLOTS::N) return;
+    const int F = s < SLOTS::G0 ? -1 : (s - SLOTS::G0) / SL::Q;
+    float* c = P.aux + kAuxC * P.aux_stride;
+    if constexpr (SET) {
+        *adj_at<SL, FL>(P.adj_out, P, s, i) = float(buf[s * nodes + i]);
+        if (s == 0) {
+            for (int f = 0; f < 3; ++f) c[f * P.aux_stride + i] = 0.0f;
+        }
+    } else {
+        double v = *adj_at<SL, FL>(P.adj_in, P, s, i);
+        if (F >= 0) v += double(c[F * P.aux_stride + i]);
+        buf[s * nodes + i] = v;
+    }
+}
+
+// zero n doubles
+template <int NT = 256>
+__global__ void __launch_bounds__(NT) k_zero_f64(double* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
 }
 
 // per-work-group sums of a double field (grid-stride, fixed order)

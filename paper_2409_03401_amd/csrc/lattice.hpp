@@ -8,7 +8,38 @@
 // weights 1/3, 1/6 and 1/4, 1/8 (c_s^2 = 1/3 and 1/4).
 #pragma once
 
+#include <type_traits>
+
 namespace lbm {
+
+// compile-time loop: f(std::integral_constant<int, k>) for k in [B, E)
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// e . v for a lattice vector with components in {-1, 0, 1}, without the zero terms
+template <int EX, int EY, int EZ, class C>
+__device__ __forceinline__ C edot(C a, C b, C c) {
+    C r = C(0);
+    if constexpr (EX != 0) r = EX > 0 ? a : -a;
+    if constexpr (EY != 0) {
+        if constexpr (EX != 0) r += EY > 0 ? b : -b;
+        else r = EY > 0 ? b : -b;
+    }
+    if constexpr (EZ != 0) {
+        if constexpr (EX != 0 || EY != 0) r += EZ > 0 ? c : -c;
+        else r = EZ > 0 ? c : -c;
+    }
+    return r;
+}
+
 
 struct NoLattice {
     static constexpr int Q = 0;

@@ -28,14 +28,15 @@ void launch_finalize(const double* partials, int nparts, int width, int maxslot,
         hipLaunchKernelGGL((k_finalize<8>), dim3(1), dim3(256), 0, s, partials, nparts, maxslot, scale0, out);
 }
 
-void launch_accumulate6(const double* partials, int nparts, double* out, hipStream_t s) {
-    hipLaunchKernelGGL((k_finalize<6, true>), dim3(1), dim3(256), 0, s, partials, nparts, -1, 1.0, out);
+void launch_sum6(const double* partials, int nparts, double* out, bool accumulate, hipStream_t s) {
+    if (accumulate)
+        hipLaunchKernelGGL((k_finalize<6, true>), dim3(1), dim3(256), 0, s, partials, nparts, -1, 1.0, out);
+    else
+        hipLaunchKernelGGL((k_finalize<6, false>), dim3(1), dim3(256), 0, s, partials, nparts, -1, 1.0, out);
 }
 
-void launch_adj_copy(const KParams& kp, int nslots, long long nodes, double* buf, bool set, hipStream_t s) {
-    const dim3 grid(unsigned((nodes + 255) / 256), nslots);
-    if (set) hipLaunchKernelGGL((k_adj_copy<true>), grid, dim3(256), 0, s, kp, nslots, nodes, buf);
-    else hipLaunchKernelGGL((k_adj_copy<false>), grid, dim3(256), 0, s, kp, nslots, nodes, buf);
+void launch_zero(double* p, long long n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL((k_zero_f64<256>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
 }  // namespace lbm

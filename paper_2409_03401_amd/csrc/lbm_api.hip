@@ -55,7 +55,8 @@ struct Layout {
     long long nparts;     // work-groups of the fused kernel
     size_t aux_bytes;
     size_t state_bytes;
-    // adjoint workspace: two FP32 adjoint copies, 8 aux rows, parameter partials
+    // adjoint workspace: two FP32 lambda copies, kAuxRows FP32 rows, theta partials of
+    // the adjoint kernels (6 per 256-node work-group)
     size_t adj_stride, aux_stride_elems, adj_bytes;
     long long adj_parts;
 };
@@ -159,8 +160,8 @@ int check_config(const lbm_config* c, Layout* L) {
     L->state_bytes = 2 * L->copy_bytes + L->aux_bytes;
     L->adj_stride = round_up((size_t)nodes * 4);
     L->aux_stride_elems = round_up((size_t)nodes * 4) / 4;
-    L->adj_parts = std::max<long long>(L->nparts, (nodes + 255) / 256);
-    L->adj_bytes = 2 * L->nslots * L->adj_stride + 8 * L->aux_stride_elems * 4 +
+    L->adj_parts = (nodes + 255) / 256;
+    L->adj_bytes = 2 * L->nslots * L->adj_stride + kAuxRows * L->aux_stride_elems * 4 +
                    round_up(sizeof(double) * 6 * L->adj_parts);
     return LBM_OK;
 }
@@ -219,6 +220,8 @@ void fill_params(lbm_handle* h) {
     kp.drho = c.drho;
     kp.cap = 1.5 * c.sigma * c.W;
     kp.inv_W2 = 1.0 / (c.W * c.W);
+    kp.dK_dW = -2.0 * c.M_phi / (c.W * c.W * c.W);
+    kp.dcap_dW = 1.5 * c.sigma;
     const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
     for (int f = 0; f < 4; ++f) {
         const int sh = sixteen ? c.store_shift[f] : 0;
@@ -228,16 +231,6 @@ void fill_params(lbm_handle* h) {
     }
     kp.stride_m = L.stride_m;
     kp.stride_r = L.stride_r;
-    for (int s = 0; s < L.nslots; ++s) {
-        const int field = s < L.qf ? 0 : 1 + (s - L.qf) / L.qs;
-        const int k = s < L.qf ? s : (s - L.qf) % L.qs;
-        const int q = s < L.qf ? L.qf : L.qs;
-        kp.srest[s] = k == 0;
-        kp.swref[s] = (sixteen && k != 0) ? float(lattice_w(q, k) * c.store_ref[field]) : 0.0f;
-        const int sh = sixteen ? c.store_shift[field] : 0;
-        kp.sscale[s] = std::ldexp(1.0f, sh);
-        kp.sinv[s] = std::ldexp(1.0f, -sh);
-    }
     kp.phi_ref = h->aux;
     kp.partials = h->aux + 16;
 }
@@ -430,24 +423,38 @@ int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes) {
     return LBM_OK;
 }
 
-int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* stream) {
+int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, void* stream) {
     if (int r = check_handle(h)) return r;
     if (!src || !dst || src == dst) return fail(LBM_EINVAL, "src and dst must be distinct checkpoint buffers");
     hipStream_t s = static_cast<hipStream_t>(stream);
     KParams kp = h->base;
     set_slots(h, kp, static_cast<const char*>(src), static_cast<char*>(dst));
+    kp.phi_out = phi_src;
     const double* ref_in = reinterpret_cast<const double*>(static_cast<const char*>(src) + h->L.copy_bytes);
     double* ref_out = reinterpret_cast<double*>(static_cast<char*>(dst) + h->L.copy_bytes);
     kp.phi_ref = ref_in;
+    // the buffered <phi> is recomputed with the mean subtraction, else carried over
+    kp.ref_copy = h->cfg.gravity_mean_subtract ? nullptr : ref_out;
     h->ks->fused(MODE_STEP, h->L.grid, kp, s);
     const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
     for (int a = 0; a < 3; ++a)
         if (walls[a]) h->ks->walls(kp, a, s);
     if (h->cfg.gravity_mean_subtract)
         launch_finalize(h->aux + 16, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
-    else
-        LBM_HIP(hipMemcpyAsync(ref_out, ref_in, sizeof(double), hipMemcpyDeviceToDevice, s));
     return launched("step_external kernels");
+}
+
+int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!state || !phi) return fail(LBM_EINVAL, "NULL pointer");
+    KParams kp = h->base;
+    set_slots(h, kp, static_cast<const char*>(state), nullptr);
+    kp.phi_ref = reinterpret_cast<const double*>(static_cast<const char*>(state) + h->L.copy_bytes);
+    for (int i = 0; i < kNumMom; ++i) kp.mout[i] = nullptr;
+    kp.mout[0] = phi;
+    kp.mout_f32 = h->L.prec == LBM_FP64 ? 0 : 1;
+    h->ks->fused(MODE_MOMENTS, h->L.grid, kp, static_cast<hipStream_t>(stream));
+    return launched("phase-field kernel");
 }
 
 namespace {
@@ -461,81 +468,113 @@ int adjoint_ready(const lbm_handle* h, const void* work) {
     return LBM_OK;
 }
 
-// adjoint fields of a KParams: lambda copy `in` -> `out` inside the caller's workspace
-void adjoint_params(const lbm_handle* h, KParams& kp, void* work, int in, int out) {
+// workspace pieces
+struct AdjWork {
+    char* lam[2];
+    float* aux;
+    double* part;   // ceil(nodes / 256) x 6, indexed by work-group of the node kernels
+    long long nparts;
+};
+
+AdjWork adjoint_work(const lbm_handle* h, void* work) {
     char* w = static_cast<char*>(work);
     const size_t copy = h->L.nslots * h->L.adj_stride;
-    kp.adj_in = in >= 0 ? w + in * copy : nullptr;
-    kp.adj_out = out >= 0 ? w + out * copy : nullptr;
-    kp.adj_stride = h->L.adj_stride;
-    kp.aux = reinterpret_cast<float*>(w + 2 * copy);
-    kp.aux_stride = h->L.aux_stride_elems;
-    kp.partials = reinterpret_cast<double*>(w + 2 * copy + 8 * h->L.aux_stride_elems * 4);
+    AdjWork a;
+    a.lam[0] = w;
+    a.lam[1] = w + copy;
+    a.aux = reinterpret_cast<float*>(w + 2 * copy);
+    a.part = reinterpret_cast<double*>(w + 2 * copy + kAuxRows * h->L.aux_stride_elems * 4);
+    a.nparts = h->L.adj_parts;
+    return a;
 }
+
+// adjoint fields of a KParams: lambda copy `in` -> `out`
+void adjoint_params(const lbm_handle* h, KParams& kp, const AdjWork& a, int in, int out) {
+    kp.adj_in = in >= 0 ? a.lam[in] : nullptr;
+    kp.adj_out = out >= 0 ? a.lam[out] : nullptr;
+    kp.adj_stride = h->L.adj_stride;
+    kp.aux = a.aux;
+    kp.aux_stride = h->L.aux_stride_elems;
+    kp.partials = a.part;
+}
+
+void zero_partials(const AdjWork& a, hipStream_t s) { launch_zero(a.part, 6 * a.nparts, s); }
 
 }  // namespace
 
-int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, double* grad_theta,
-                     void* stream) {
+int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
-    if (!state || !dL_dphi || !grad_theta) return fail(LBM_EINVAL, "NULL pointer");
+    if (!state || !dL_dphi) return fail(LBM_EINVAL, "NULL pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const AdjWork a = adjoint_work(h, work);
+    zero_partials(a, s);
     KParams kp = h->base;
     set_slots(h, kp, static_cast<const char*>(state), nullptr);
-    adjoint_params(h, kp, work, -1, 0);
+    adjoint_params(h, kp, a, -1, 0);
     h->ks->adj_seed(kp, h->L.nodes, dL_dphi, s);
-    launch_accumulate6(kp.partials, int((h->L.nodes + 255) / 256), grad_theta, s);
     h->adj_cur = 0;
-    return launched("adjoint seed kernel");
+    return launched("adjoint seed kernels");
 }
 
-int lbm_adjoint_step(lbm_handle* h, const void* state, void* work, double* grad_theta, void* stream) {
+int lbm_adjoint_step(lbm_handle* h, const void* state, const void* phi, void* work, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
-    if (!state || !grad_theta) return fail(LBM_EINVAL, "NULL pointer");
+    if (!state || !phi) return fail(LBM_EINVAL, "NULL pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const AdjWork a = adjoint_work(h, work);
     KParams kp = h->base;
     set_slots(h, kp, static_cast<const char*>(state), nullptr);
     kp.phi_ref = reinterpret_cast<const double*>(static_cast<const char*>(state) + h->L.copy_bytes);
-    adjoint_params(h, kp, work, h->adj_cur, 1 - h->adj_cur);
+    adjoint_params(h, kp, a, h->adj_cur, 1 - h->adj_cur);
     const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
-    for (int a = 0; a < 3; ++a)
-        if (walls[a]) h->ks->adj_walls(kp, a, s);
-    h->ks->adj_step(h->L.grid, kp, s);
-    launch_accumulate6(kp.partials, int(h->L.nparts), grad_theta, s);
+    for (int ax = 0; ax < 3; ++ax)
+        if (walls[ax]) h->ks->adj_walls(kp, ax, s);
+    h->ks->adj_step(kp, h->L.nodes, phi, s);
     h->ks->adj_gather(kp, h->L.nodes, 0, nullptr, s);
-    launch_accumulate6(kp.partials, int((h->L.nodes + 255) / 256), grad_theta, s);
     h->adj_cur = 1 - h->adj_cur;
     return launched("adjoint step kernels");
 }
 
 int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, const double* muB0, void* work,
-                     double* grad_phi0, double* grad_theta, void* stream) {
+                     double* grad_phi0, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
-    if (!phi0 || !muA0 || !muB0 || !grad_phi0 || !grad_theta) return fail(LBM_EINVAL, "NULL pointer");
+    if (!phi0 || !muA0 || !muB0 || !grad_phi0) return fail(LBM_EINVAL, "NULL pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const AdjWork a = adjoint_work(h, work);
     KParams kp = h->base;
-    adjoint_params(h, kp, work, h->adj_cur, -1);
+    adjoint_params(h, kp, a, h->adj_cur, -1);
     h->ks->adj_init_local(kp, h->L.nodes, phi0, muA0, muB0, s);
-    launch_accumulate6(kp.partials, int((h->L.nodes + 255) / 256), grad_theta, s);
     h->ks->adj_gather(kp, h->L.nodes, 1, grad_phi0, s);
     return launched("adjoint init kernels");
+}
+
+int lbm_adjoint_theta(lbm_handle* h, void* work, double* grad_theta, void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!grad_theta) return fail(LBM_EINVAL, "grad_theta is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const AdjWork a = adjoint_work(h, work);
+    launch_sum6(a.part, int(a.nparts), grad_theta, false, s);
+    return launched("adjoint parameter reduction");
 }
 
 int lbm_adjoint_get(lbm_handle* h, void* work, double* dst, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
     if (!dst) return fail(LBM_EINVAL, "dst is NULL");
+    const AdjWork a = adjoint_work(h, work);
     KParams kp = h->base;
-    adjoint_params(h, kp, work, h->adj_cur, -1);
-    launch_adj_copy(kp, h->L.nslots, h->L.nodes, dst, false, static_cast<hipStream_t>(stream));
+    adjoint_params(h, kp, a, h->adj_cur, -1);
+    h->ks->adj_copy(kp, h->L.nslots, h->L.nodes, dst, false, static_cast<hipStream_t>(stream));
     return launched("adjoint copy kernel");
 }
 
 int lbm_adjoint_set(lbm_handle* h, void* work, const double* src, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
     if (!src) return fail(LBM_EINVAL, "src is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const AdjWork a = adjoint_work(h, work);
+    zero_partials(a, s);
     KParams kp = h->base;
-    adjoint_params(h, kp, work, 0, -1);
-    launch_adj_copy(kp, h->L.nslots, h->L.nodes, const_cast<double*>(src), true, static_cast<hipStream_t>(stream));
+    adjoint_params(h, kp, a, -1, 0);
+    h->ks->adj_copy(kp, h->L.nslots, h->L.nodes, const_cast<double*>(src), true, s);
     h->adj_cur = 0;
     return launched("adjoint copy kernel");
 }

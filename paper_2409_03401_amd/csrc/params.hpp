@@ -14,7 +14,7 @@ constexpr int kNumMom = 9;
 constexpr int kNumDiag = 8;
 
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
-enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_ADJ = 3 };
+enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -47,6 +47,7 @@ struct KParams {
     double gx, gy, gz;           // gravity in the kernel frame
     double cap;                  // 3/2 sigma W of Eq. SurfaceTension_Force
     double inv_W2;
+    double dK_dW, dcap_dW;       // -2 M_phi / W^3 and 3/2 sigma (adjoint: d/dW)
     // population copies addressed by the fused kernel: slot s of a copy starts at
     // base + (#moving slots before s) * stride_m + (#rest slots before s) * stride_r
     const char* src_base;
@@ -55,11 +56,6 @@ struct KParams {
     // 16-bit storage per field (0 f, 1 g, 2 hA, 3 hB): moving population k is
     // value = w_k fref + d * finv, d = (value - w_k fref) * fscale
     float fref[4], fscale[4], finv[4];
-    // per-slot storage constants (canonical slot order): value = swref + d * sinv
-    // for 16-bit moving populations, d = (value - swref) * sscale on store;
-    // srest = 1 for rest populations (k = 0), stored in FP32 by the 16-bit formats
-    float swref[kMaxSlots], sscale[kMaxSlots], sinv[kMaxSlots];
-    int srest[kMaxSlots];
     // device scalars
     const double* phi_ref;       // buoyancy reference <phi> (aux area)
     double* partials;            // per-work-group partial sums
@@ -69,14 +65,23 @@ struct KParams {
     // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame)
     void* mout[kNumMom];
     int mout_f32;
-    // adjoint (MODE_ADJ and the adjoint kernels): adjoint populations in FP32,
-    // [slot][node] with slot stride adj_stride bytes, in the natural indexing
-    // lambda_k(x) = dL / dX_k(x) of the arriving populations; aux = [8][node] FP32
+    // adjoint kernels.  The adjoint of the arriving
+    // population X_s(x) is lambda_s(x) plus, for a scalar population of field F
+    // (g, h^A, h^B), the field-wide term c_F(x) (aux rows 7..9).  lambda is FP32
+    // [slot][node] with slot stride adj_stride bytes.  aux is FP32 [row][node]:
+    // rows 0-2 dL/dG, 3 dL/dN, 4 dphi/dphi*, 5 q of dphi/dc, 6 dphi/dK, 7-9 c_F.
     const char* adj_in;
     char* adj_out;
     unsigned long long adj_stride;
     float* aux;
     unsigned long long aux_stride;  // elements per aux row
+    // MODE_STEP: when set, receives *phi_ref (steps between caller checkpoints)
+    double* ref_copy;
+    // MODE_STEP: when set, receives phi of the source state ([node], compute type)
+    void* phi_out;
 };
+
+constexpr int kAuxRows = 10;
+constexpr int kAuxC = 7;  // first row of c_F
 
 }  // namespace lbm

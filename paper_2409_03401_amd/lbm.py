@@ -15,7 +15,8 @@ from typing import Dict, Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbm.so")
+# LBM_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_HERE, "liblbm.so")
 
 # ---- constants of include/lbm.h ------------------------------------------------------
 LBM_OK, LBM_EINVAL, LBM_ESIZE, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_EHIP = 0, -1, -2, -3, -4, -5
@@ -71,14 +72,17 @@ _SIGS = {
     "lbm_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_restore": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
-    "lbm_step_external": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_step_external": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
+    "lbm_phase_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_bytes": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_adjoint_seed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.c_void_p, ctypes.c_void_p]),
+                                        ctypes.c_void_p]),
     "lbm_adjoint_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "lbm_adjoint_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_adjoint_theta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_step_count": (ctypes.c_int64, [ctypes.c_void_p]),
@@ -291,27 +295,48 @@ class Simulation:
         _check(lib().lbm_restore(self._h, ctypes.c_void_p(ckpt.data_ptr()), _stream_ptr(stream)))
 
     # ---- discrete adjoint (reverse mode) ----------------------------------------------
-    def step_external(self, src: torch.Tensor, dst: torch.Tensor, stream=None):
-        """One step from checkpoint `src` into checkpoint `dst` (lbm_save layout)."""
-        _check(lib().lbm_step_external(self._h, _ptr(src), _ptr(dst), _stream_ptr(stream)))
+    @property
+    def phi_dtype(self):
+        """Type of the phi fields of step_external / phase_field (the compute type)."""
+        return torch.float64 if self.cfg.precision == "fp64" else torch.float32
+
+    def step_external(self, src: torch.Tensor, dst: torch.Tensor, phi_src: Optional[torch.Tensor] = None,
+                      stream=None):
+        """One step from checkpoint `src` into checkpoint `dst` (lbm_save layout);
+        phi_src, when given, receives phi of `src`."""
+        _check(lib().lbm_step_external(self._h, _ptr(src), _ptr(dst),
+                                       _ptr(phi_src) if phi_src is not None else None, _stream_ptr(stream)))
+
+    def phase_field(self, state: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """phi of the checkpoint `state` in the compute type ([node])."""
+        if out is None:
+            out = torch.empty(self.cfg.nodes, dtype=self.phi_dtype, device=self.device)
+        _check(lib().lbm_phase_field(self._h, _ptr(state), _ptr(out), _stream_ptr(stream)))
+        return out
 
     def adjoint_workspace(self) -> torch.Tensor:
         return torch.zeros(adjoint_bytes(self.cfg), dtype=torch.uint8, device=self.device)
 
-    def adjoint_seed(self, state: torch.Tensor, dL_dphi: torch.Tensor, work: torch.Tensor,
-                     grad_theta: torch.Tensor, stream=None):
+    def adjoint_seed(self, state: torch.Tensor, dL_dphi: torch.Tensor, work: torch.Tensor, stream=None):
+        """Start the adjoint from dL/dphi_T at the checkpoint `state`; clears the theta partials."""
         d = _dev_f64(dL_dphi, self.cfg.nodes, self.device)
-        _check(lib().lbm_adjoint_seed(self._h, _ptr(state), _ptr(d), _ptr(work), _ptr(grad_theta),
-                                      _stream_ptr(stream)))
+        _check(lib().lbm_adjoint_seed(self._h, _ptr(state), _ptr(d), _ptr(work), _stream_ptr(stream)))
 
-    def adjoint_step(self, state: torch.Tensor, work: torch.Tensor, grad_theta: torch.Tensor, stream=None):
-        _check(lib().lbm_adjoint_step(self._h, _ptr(state), _ptr(work), _ptr(grad_theta), _stream_ptr(stream)))
+    def adjoint_step(self, state: torch.Tensor, phi: torch.Tensor, work: torch.Tensor, stream=None):
+        """Adjoint of the step taken from checkpoint `state` whose phi is `phi`."""
+        _check(lib().lbm_adjoint_step(self._h, _ptr(state), _ptr(phi), _ptr(work), _stream_ptr(stream)))
 
-    def adjoint_init(self, work: torch.Tensor, grad_phi0: torch.Tensor, grad_theta: torch.Tensor, stream=None):
+    def adjoint_init(self, work: torch.Tensor, grad_phi0: torch.Tensor, stream=None):
         """dL/dphi_0 (written into grad_phi0) through lbm_init, mu_0 held fixed."""
         phi0, muA0, muB0 = self._inputs
         _check(lib().lbm_adjoint_init(self._h, _ptr(phi0), _ptr(muA0), _ptr(muB0), _ptr(work), _ptr(grad_phi0),
-                                      _ptr(grad_theta), _stream_ptr(stream)))
+                                      _stream_ptr(stream)))
+
+    def adjoint_theta(self, work: torch.Tensor, stream=None) -> torch.Tensor:
+        """dL/dtheta (THETA_NAMES order) accumulated since the last seed or set."""
+        out = torch.empty(6, dtype=torch.float64, device=self.device)
+        _check(lib().lbm_adjoint_theta(self._h, _ptr(work), _ptr(out), _stream_ptr(stream)))
+        return out
 
     def adjoint_get(self, work: torch.Tensor, stream=None) -> torch.Tensor:
         t = torch.empty((self.nslots,) + self.cfg.shape, dtype=torch.float64, device=self.device)
@@ -345,8 +370,9 @@ class PhaseFieldRun(torch.autograd.Function):
 
     Forward keeps a checkpoint every `segment` steps (default ceil(sqrt(steps)));
     backward recomputes each segment from its checkpoint into `segment` state
-    buffers and runs the adjoint steps through it in reverse, then the adjoint of
-    the initialisation.  Peak memory: about (steps / segment + segment) checkpoints.
+    buffers (keeping phi of each state, which the step computes anyway) and runs
+    the adjoint steps through it in reverse, then the adjoint of the
+    initialisation.  Peak memory: about (steps / segment + segment) checkpoints.
     mu_0 enters as a constant."""
 
     @staticmethod
@@ -374,22 +400,24 @@ class PhaseFieldRun(torch.autograd.Function):
         sim = ctx.sim
         dev = sim.device
         work = sim.adjoint_workspace()
-        gth = torch.zeros(6, dtype=torch.float64, device=dev)
-        sim.adjoint_seed(ctx.final, grad_phiT.detach().to(torch.float64).contiguous(), work, gth)
+        sim.adjoint_seed(ctx.final, grad_phiT.detach().to(torch.float64).contiguous(), work)
         nbytes = ctx.final.numel()
-        seg_states = [None] + [torch.empty(nbytes, dtype=torch.uint8, device=dev)
-                               for _ in range(min(ctx.seg, ctx.steps) - 1)]
+        width = min(ctx.seg, ctx.steps)
+        seg_states = [None] + [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(width - 1)]
+        seg_phi = [torch.empty(sim.cfg.nodes, dtype=sim.phi_dtype, device=dev) for _ in range(width)]
         for s in reversed(range(len(ctx.ckpts))):
             n0 = s * ctx.seg
             length = min(ctx.seg, ctx.steps - n0)
             states = [ctx.ckpts[s]]
             for j in range(1, length):
-                sim.step_external(states[j - 1], seg_states[j])
+                sim.step_external(states[j - 1], seg_states[j], seg_phi[j - 1])
                 states.append(seg_states[j])
+            sim.phase_field(states[length - 1], seg_phi[length - 1])
             for j in reversed(range(length)):
-                sim.adjoint_step(states[j], work, gth)
+                sim.adjoint_step(states[j], seg_phi[j], work)
         gphi0 = torch.empty(sim.cfg.shape, dtype=torch.float64, device=dev)
-        sim.adjoint_init(work, gphi0, gth)
+        sim.adjoint_init(work, gphi0)
+        gth = sim.adjoint_theta(work)
         ctx.sim = ctx.ckpts = ctx.final = None
         return (gphi0.reshape(ctx.phi_shape).to(ctx.phi_dtype), gth.to(ctx.theta_device, ctx.theta_dtype),
                 None, None, None, None, None)

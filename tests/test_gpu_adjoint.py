@@ -116,10 +116,9 @@ def _gpu_adjoint_step(p, prec, pops, phi0, muA0, muB0, lam):
     ck = sim.save()
     work = sim.adjoint_workspace()
     sim.adjoint_set(work, lam)
-    gth = torch.zeros(6, dtype=torch.float64, device="cuda")
-    sim.adjoint_step(ck, work, gth)
+    sim.adjoint_step(ck, sim.phase_field(ck), work)
     out = sim.adjoint_get(work).cpu().numpy()
-    return out, gth.cpu().numpy()
+    return out, sim.adjoint_theta(work).cpu().numpy()
 
 
 def _oracle_column(pops, p, j):
@@ -222,10 +221,9 @@ def test_adjoint_init_entrywise():
     work = sim.adjoint_workspace()
     sim.adjoint_set(work, lam)
     gphi = torch.empty(prm.shape, dtype=torch.float64, device="cuda")
-    gth = torch.zeros(6, dtype=torch.float64, device="cuda")
-    sim.adjoint_init(work, gphi, gth)
+    sim.adjoint_init(work, gphi)
     gphi = gphi.cpu().numpy()
-    gth = gth.cpu().numpy()
+    gth = sim.adjoint_theta(work).cpu().numpy()
 
     def init_pops(ph, q):
         qp = oracle_params(q)
@@ -370,5 +368,6 @@ def test_adjoint_unsupported_precisions():
     sim = Simulation(gpu_config(p, "bf16"), phi0, muA0, muB0)
     work = sim.adjoint_workspace()
     with pytest.raises(LBMError) as e:
-        sim.adjoint_step(sim.save(), work, torch.zeros(6, dtype=torch.float64, device="cuda"))
+        ck = sim.save()
+        sim.adjoint_step(ck, sim.phase_field(ck), work)
     assert e.value.code == LBM_EUNSUPPORTED
