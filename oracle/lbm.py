@@ -281,7 +281,7 @@ def moments(st, prm):
 # ----------------------------------------------------------------------------------------
 # init and step
 
-def init(phi0, muA0, muB0, prm):
+def init(phi0, muA0, muB0, prm, phi_ref=None):
     """Populations at rest from (phi_0, mu_0), with u = 0 and p_h = 0 (Section 4.2.1):
     c from the closure Eq. species_closure, every population set to its equilibrium
     including the -G_k/2 and -F_k/2 shifts, so that the moments of Eqs. Moment0_Phi
@@ -298,7 +298,8 @@ def init(phi0, muA0, muB0, prm):
     g = np.stack([g_equilibrium_k(slat, k, phi0, u0, slat.w[k] * S0) for k in range(slat.Q)])
     hA = np.stack([h_equilibrium_k(slat, k, c[0], mu0[0], u0) + zero for k in range(slat.Q)])
     hB = np.stack([h_equilibrium_k(slat, k, c[1], mu0[1], u0) + zero for k in range(slat.Q)])
-    phi_ref = phi0.mean() if prm.gravity_mean_subtract else 0.0
+    if phi_ref is None:  # buoyancy reference of the initial force (given for a window of a larger box)
+        phi_ref = phi0.mean() if prm.gravity_mean_subtract else 0.0
     f = None
     if prm.fluid:
         flat = prm.flat

@@ -1,0 +1,142 @@
+"""Parity at the benchmark sizes, on sampled nodes.
+
+The GPU runs the full workload (grid, storage and launch configuration of bench.py)
+for K steps.  For each sampled node the FP64 oracle runs the same K steps on a
+window of the seeded initial fields centred on the node.  After K steps the node
+depends only on initial data within 2K + 1 nodes (one node through the initial
+force stencil, two per step: the pulled neighbour and its phi stencil), so a window
+of half-width R = 3K + 3 reproduces it exactly whatever the window's own edges do
+(they are periodic, or walls where the domain has walls on that axis).  With the
+buoyancy mean subtraction the reference of the first step is the mean of phi_0
+over the whole box, which is passed to the window; later steps would need the
+global mean of a later state, so that workload runs one step.
+
+Bars as in test_gpu_parity.py: FP32 within 1e-5 of each field's scale in the
+window; 16-bit storage within 1e-3 relative on c^A, c^B and 1e-2 on phi.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from helpers import MOMENT_NAMES, gpu_config, oracle_params
+from oracle import lbm as olbm
+from paper_2409_03401_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+WORKLOADS = {
+    # name: (builder, precision, steps)
+    "sediment_3d_256_fp32": (lambda: inputs.sediment_3d(n=256, precision="fp32"), "fp32", 3),
+    "sediment_3d_256_bf16": (lambda: inputs.sediment_3d(n=256, precision="bf16"), "bf16", 3),
+    "ostwald_2d_1024_fp32": (lambda: inputs.ostwald_2d(n=1024, precision="fp32"), "fp32", 3),
+    "single_drop_2d_512_fp32": (lambda: inputs.single_drop_2d(n=512, precision="fp32"), "fp32", 3),
+    "spinodal_3d_512_bf16": (lambda: inputs.spinodal_3d(n=512, precision="bf16"), "bf16", 1),
+}
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@functools.lru_cache(maxsize=1)
+def workload(name):
+    return WORKLOADS[name][0]()
+
+
+def sample_nodes(w, count=10, seed=60):
+    """Seeded sample: half near phi = 1/2 (interfaces), the rest uniform; plus the two
+    wall layers of a walled axis."""
+    rng = inputs.rng_for(seed)
+    shape = w.phi0.shape
+    flat = w.phi0.reshape(-1)
+    near = np.flatnonzero(np.abs(flat - 0.5) < 0.25)
+    picks = list(rng.choice(near, count // 2, replace=False)) if near.size else []
+    picks += list(rng.integers(0, flat.size, count - len(picks)))
+    nodes = [np.unravel_index(int(i), shape) for i in picks]
+    p = w.params
+    for a in range(3):  # a: x, y, z -> array axis 2 - a
+        if p["bc"][a] == "walls" and shape[2 - a] > 1:
+            for edge in (0, shape[2 - a] - 1):
+                c = list(np.unravel_index(int(rng.choice(near if near.size else np.arange(flat.size))), shape))
+                c[2 - a] = edge
+                nodes.append(tuple(c))
+    return nodes
+
+
+def window_oracle(w, centre, steps):
+    """FP64 oracle moments at `centre` (z, y, x) after `steps` steps on a window."""
+    p = dict(w.params)
+    shape = w.phi0.shape
+    R = 3 * steps + 3
+    index, bcs, local = [], [], []
+    for ax in range(3):  # array axis: z, y, x
+        a = 2 - ax       # parameter axis: x, y, z
+        n, c = shape[ax], centre[ax]
+        if n <= 2 * R + 1:
+            idx, bc, loc = np.arange(n), p["bc"][a], c
+        elif p["bc"][a] == "periodic":
+            idx, bc, loc = np.arange(c - R, c + R + 1) % n, "periodic", R
+        else:
+            lo, hi = max(0, c - R), min(n - 1, c + R)
+            idx, bc, loc = np.arange(lo, hi + 1), "walls", c - lo
+        index.append(idx)
+        bcs.append((a, bc))
+        local.append(loc)
+    sub = np.ix_(*index)
+    q = dict(p, nz=len(index[0]), ny=len(index[1]), nx=len(index[2]))
+    bc = list(p["bc"])
+    for a, b in bcs:
+        bc[a] = b
+    q["bc"] = tuple(bc)
+    ref = None
+    if p.get("gravity_mean_subtract"):
+        assert steps == 1, "the mean of later states is not local"
+        ref = float(w.phi0.mean())
+        q["gravity_mean_subtract"] = False
+    prm = oracle_params(q)
+    st = olbm.init(w.phi0[sub], w.muA0[sub], w.muB0[sub], prm, phi_ref=ref)
+    st = olbm.run(st, prm, steps)
+    m = olbm.moments(st, prm)
+    win = {k: np.asarray(m[k]) for k in MOMENT_NAMES}
+    return {k: v[tuple(local)] for k, v in win.items()}, {k: np.abs(v).max() for k, v in win.items()}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_fullsize_sampled(name):
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    w = workload(name)
+    prec, steps = WORKLOADS[name][1], WORKLOADS[name][2]
+    print(f"[fullsize] {name} grid {w.phi0.shape} {prec} steps={steps}", flush=True)
+    sim = Simulation(gpu_config(w.params, prec), w.phi0, w.muA0, w.muB0)
+    sim.step(steps)
+    nodes = sample_nodes(w)
+    flat = torch.tensor([np.ravel_multi_index(c, w.phi0.shape) for c in nodes], device="cuda")
+    mom = sim.moments(dtype=torch.float32 if w.nodes > 50_000_000 else torch.float64)
+    gpu = {k: v.reshape(-1).index_select(0, flat).double().cpu().numpy() for k, v in mom.items()}
+    del mom
+    sim.close()
+    torch.cuda.empty_cache()
+    worst = {}
+    for i, c in enumerate(nodes):
+        ora, scale = window_oracle(w, c, steps)
+        for k in MOMENT_NAMES:
+            err = abs(gpu[k][i] - ora[k])
+            if prec == "fp32":
+                s = scale[k]
+                if k in ("muA", "muB"):
+                    s = max(scale["cA"], scale["cB"])
+                if k in ("ux", "uy", "uz"):
+                    s = max(scale["ux"], scale["uy"], scale["uz"])
+                bar = 1e-5 * s + 1e-12
+            else:
+                bar = {"cA": 1e-3 * scale["cA"], "cB": 1e-3 * scale["cB"], "phi": 1e-2 * scale["phi"]}.get(k)
+            worst[k] = max(worst.get(k, 0.0), err)
+            if bar is not None:
+                assert err <= bar, (name, c, k, gpu[k][i], ora[k])
+    print("  max abs error per field:", {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
