@@ -184,18 +184,21 @@ def adjoint_timing(n=512, steps=4096, segment=None):
     sim.close()
     del sim
 
-    phi0 = torch.tensor(w.phi0, dtype=torch.float64, device="cuda", requires_grad=True)
-    theta = torch.tensor(theta_of(cfg), dtype=torch.float64, requires_grad=True)
     target = torch.tensor(w.phi0, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    phiT = phase_field_run(phi0, theta, cfg, steps, w.muA0, w.muB0, segment)
-    loss = ((phiT - target) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    # the first pass fills the caching allocator with the checkpoint and segment
+    # buffers; the second is timed
+    for _ in range(2):
+        phi0 = torch.tensor(w.phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+        theta = torch.tensor(theta_of(cfg), dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phiT = phase_field_run(phi0, theta, cfg, steps, w.muA0, w.muB0, segment)
+        loss = ((phiT - target) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
     finite = bool(torch.isfinite(phi0.grad).all()) and bool(torch.isfinite(theta.grad).all())
     del phi0, theta, target, phiT, loss
     torch.cuda.empty_cache()

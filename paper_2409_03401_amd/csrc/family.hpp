@@ -15,6 +15,9 @@ struct Family {
             case MODE_STEP:
                 hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP, PREC, TX, TY>), grid, block, 0, s, kp);
                 break;
+            case MODE_STEP_PHI:
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP_PHI, PREC, TX, TY>), grid, block, 0, s, kp);
+                break;
             case MODE_MOMENTS:
                 hipLaunchKernelGGL((k_lbm<SL, FL, MODE_MOMENTS, PREC, TX, TY>), grid, block, 0, s, kp);
                 break;

@@ -408,6 +408,10 @@ k_lbm(const KParams P) {
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
 
     const double phi_ref = P.mean_subtract ? *P.phi_ref : 0.0;
+    if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_PHI) {
+        // a step between caller checkpoints carries the buffered <phi> over
+        if (P.ref_copy && blockIdx.x == 0 && tid == 0) *P.ref_copy = *P.phi_ref;
+    }
 
     if constexpr (STENCIL) {
         if (z0 < z1) {
@@ -516,11 +520,10 @@ k_lbm(const KParams P) {
                 u[2] = (C(3) * j2 + C(0.5) * F[2]) * inv_rho0;
             }
 
-            if constexpr (MODE == MODE_STEP) {
+            if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_PHI) {
                 if (P.mean_subtract) acc[0] += m.phi;
-                if (P.ref_copy && blockIdx.x == 0 && tid == 0) *P.ref_copy = *P.phi_ref;
                 // phi of the source state, as the stencil saw it (for the adjoint)
-                if (P.phi_out) static_cast<C*>(P.phi_out)[idx] = phi;
+                if constexpr (MODE == MODE_STEP_PHI) static_cast<C*>(P.phi_out)[idx] = phi;
 
                 // post-collision populations go to this node's own slots of the other copy
                 auto push = [&](auto s_, auto k_, auto lat_, C v) __attribute__((always_inline)) {
@@ -638,7 +641,7 @@ k_lbm(const KParams P) {
 
     if constexpr (MODE == MODE_DIAG) {
         block_reduce_store<8, NT>(acc, 4, P.partials + 8 * tile);
-    } else if constexpr (MODE == MODE_STEP) {
+    } else if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_PHI) {
         if (P.mean_subtract) block_reduce_store<1, NT>(acc, -1, P.partials + tile);
     }
 }

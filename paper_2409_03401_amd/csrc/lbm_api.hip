@@ -435,7 +435,7 @@ int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, 
     kp.phi_ref = ref_in;
     // the buffered <phi> is recomputed with the mean subtraction, else carried over
     kp.ref_copy = h->cfg.gravity_mean_subtract ? nullptr : ref_out;
-    h->ks->fused(MODE_STEP, h->L.grid, kp, s);
+    h->ks->fused(phi_src ? MODE_STEP_PHI : MODE_STEP, h->L.grid, kp, s);
     const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
     for (int a = 0; a < 3; ++a)
         if (walls[a]) h->ks->walls(kp, a, s);

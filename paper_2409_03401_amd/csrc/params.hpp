@@ -14,7 +14,8 @@ constexpr int kNumMom = 9;
 constexpr int kNumDiag = 8;
 
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
-enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2 };
+// MODE_STEP_PHI: a step that also writes phi of its source state (P.phi_out)
+enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_STEP_PHI = 3 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -77,7 +78,7 @@ struct KParams {
     unsigned long long aux_stride;  // elements per aux row
     // MODE_STEP: when set, receives *phi_ref (steps between caller checkpoints)
     double* ref_copy;
-    // MODE_STEP: when set, receives phi of the source state ([node], compute type)
+    // MODE_STEP_PHI: receives phi of the source state ([node], compute type)
     void* phi_out;
 };
 
