@@ -248,6 +248,9 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #ifndef LBM_LDS_POPS
 #define LBM_LDS_POPS 1
 #endif
+#ifndef LBM_SCALAR_BASES
+#define LBM_SCALAR_BASES 1
+#endif
 #ifndef LBM_PTR_ARRAY
 #define LBM_PTR_ARRAY 0
 #endif
@@ -302,14 +305,34 @@ k_lbm(const KParams P) {
     using SLT = std::common_type<SL>;  // type tags of the lattices
     using FLT = std::common_type<FL>;
 
-    // wave-uniform slot bases of the source and destination copies
+    // wave-uniform slot bases of the source and destination copies.  The 2 x Q_tot
+    // 64-bit bases do not fit in the SGPR file: hoisted out of the plane loop they
+    // would be spilled to VGPR lanes and read back with v_readlane (a VALU
+    // instruction each).  refresh_bases() at the top of every iteration hands the
+    // loop opaque copies of the copy bases and strides, so each slot base is
+    // recomputed on the scalar unit next to its use.
+    const char* sbase = P.src_base;
+    char* dbase = P.dst_base;
+    unsigned long long smov = P.stride_m, srest = P.stride_r;
+    // measured: +26% for 16-bit storage (VALU-bound), +6% for 2D with flow, -1% for
+    // the HBM-bound FP32 3D step, which keeps its hoisted bases
+    constexpr bool kScalarBases =
+        LBM_SCALAR_BASES && (PREC == P16 || PREC == PB16 || (FLOW && SL::DIM == 2));
+    auto refresh_bases = [&]() __attribute__((always_inline)) {
+        if constexpr (kScalarBases) asm volatile("" : "+s"(sbase), "+s"(dbase), "+s"(smov), "+s"(srest));
+    };
+    auto slot_off = [&](auto s_) __attribute__((always_inline)) -> unsigned long long {
+        constexpr int S = decltype(s_)::value;
+        constexpr int rb = SLOTS::rest_before(S);
+        return (unsigned long long)(S - rb) * smov + (unsigned long long)rb * srest;
+    };
     auto src = [&](auto s_) __attribute__((always_inline)) -> const char* {
         if constexpr (LBM_PTR_ARRAY) return static_cast<const char*>(P.src[decltype(s_)::value]);
-        else return P.src_base + slot_offset<SLOTS, decltype(s_)::value>(P);
+        else return sbase + slot_off(s_);
     };
     auto dst = [&](auto s_) __attribute__((always_inline)) -> char* {
         if constexpr (LBM_PTR_ARRAY) return static_cast<char*>(P.dst[decltype(s_)::value]);
-        else return P.dst_base + slot_offset<SLOTS, decltype(s_)::value>(P);
+        else return dbase + slot_off(s_);
     };
     // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
     auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {
@@ -425,6 +448,7 @@ k_lbm(const KParams P) {
     }
 
     for (int z = z0; z < z1; ++z) {
+        refresh_bases();
         int sm = 0, sc = 0, sp = 0;
         const unsigned idx = unsigned((z * P.ny + y) * P.nx + x);
         const Nbr nbr = neighbours(x, y, z, P);
