@@ -314,25 +314,27 @@ k_lbm(const KParams P) {
     const char* sbase = P.src_base;
     char* dbase = P.dst_base;
     unsigned long long smov = P.stride_m, srest = P.stride_r;
-    // measured: +26% for 16-bit storage (VALU-bound), +6% for 2D with flow, -1% for
-    // the HBM-bound FP32 3D step, which keeps its hoisted bases
-    constexpr bool kScalarBases =
-        LBM_SCALAR_BASES && (PREC == P16 || PREC == PB16 || (FLOW && SL::DIM == 2));
+    // measured on 256^3: BF16 storage 15.0 -> 19.4 GLUPS (the 16-bit step is
+    // instruction-bound); FP32 unchanged (HBM-bound)
     auto refresh_bases = [&]() __attribute__((always_inline)) {
-        if constexpr (kScalarBases) asm volatile("" : "+s"(sbase), "+s"(dbase), "+s"(smov), "+s"(srest));
+        if constexpr (LBM_SCALAR_BASES) asm volatile("" : "+s"(sbase), "+s"(dbase), "+s"(smov), "+s"(srest));
     };
     auto slot_off = [&](auto s_) __attribute__((always_inline)) -> unsigned long long {
         constexpr int S = decltype(s_)::value;
         constexpr int rb = SLOTS::rest_before(S);
         return (unsigned long long)(S - rb) * smov + (unsigned long long)rb * srest;
     };
+    // the opaque copies lose the address space; the casts restore `global` so the
+    // accesses stay global_* with a 32-bit voffset instead of flat_* with 64-bit addresses
+    using gconst = __attribute__((address_space(1))) const char;
+    using gmut = __attribute__((address_space(1))) char;
     auto src = [&](auto s_) __attribute__((always_inline)) -> const char* {
         if constexpr (LBM_PTR_ARRAY) return static_cast<const char*>(P.src[decltype(s_)::value]);
-        else return sbase + slot_off(s_);
+        else return (const char*)((gconst*)sbase + slot_off(s_));
     };
     auto dst = [&](auto s_) __attribute__((always_inline)) -> char* {
         if constexpr (LBM_PTR_ARRAY) return static_cast<char*>(P.dst[decltype(s_)::value]);
-        else return dbase + slot_off(s_);
+        else return (char*)((gmut*)dbase + slot_off(s_));
     };
     // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
     auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {
