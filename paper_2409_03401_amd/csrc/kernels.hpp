@@ -176,6 +176,32 @@ __device__ __forceinline__ void st_at(char* slot, unsigned idx, float wref, floa
     }
 }
 
+// store, returning the value the slot now decodes to (16-bit moving populations:
+// the rounded value; otherwise v itself)
+template <int PREC, bool REST>
+__device__ __forceinline__ typename Stor<PREC>::C st_at_r(char* slot, unsigned idx, float wref, float scale,
+                                                           float inv_scale, typename Stor<PREC>::C v) {
+    if constexpr (PREC == P64 || PREC == P32 || REST) {
+        st_at<PREC, REST>(slot, idx, wref, scale, v);
+        return v;
+    } else {
+        const float d = (v - wref) * scale;
+        unsigned short bits;
+        float back;
+        if constexpr (PREC == P16) {
+            const __half hd = __float2half_rn(d);
+            bits = __half_as_ushort(hd);
+            back = __half2float(hd);
+        } else {
+            const __bf16 bd = __bf16(d);  // round to nearest even
+            bits = __builtin_bit_cast(unsigned short, bd);
+            back = float(bd);
+        }
+        __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short*>(slot + idx * 2u));
+        return fmaf(back, inv_scale, wref);
+    }
+}
+
 // runtime-slot variants (generic copy kernels)
 template <int PREC>
 __device__ __forceinline__ typename Stor<PREC>::C ld_pop(const void* base, int idx, bool rest,
@@ -348,6 +374,12 @@ k_lbm(const KParams P) {
     auto store = [&](auto s_, auto k_, auto lat_, unsigned idx, C v) __attribute__((always_inline)) {
         constexpr int S = decltype(s_)::value;
         st_at<PREC, SLOTS::rest(S)>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[SLOTS::field(S)], v);
+    };
+    // store and add the rounding residue (value - stored value) to res
+    auto store_r = [&](auto s_, auto k_, auto lat_, unsigned idx, C v, C& res) __attribute__((always_inline)) {
+        constexpr int S = decltype(s_)::value;
+        constexpr int F = SLOTS::field(S);
+        res += v - st_at_r<PREC, SLOTS::rest(S)>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[F], P.finv[F], v);
     };
 
     // scalar populations arriving at node idx (pull from idx - e_k)
@@ -551,9 +583,17 @@ k_lbm(const KParams P) {
                 // phi of the source state, as the stencil saw it (for the adjoint)
                 if constexpr (MODE == MODE_STEP_PHI) static_cast<C*>(P.phi_out)[idx] = phi;
 
-                // post-collision populations go to this node's own slots of the other copy
+                // post-collision populations go to this node's own slots of the other copy.
+                // 16-bit storage: the rounding residue of a field's moving populations is
+                // added to its FP32 rest population, so the stored state keeps each node's
+                // post-collision mass of every field (the rest population is stored last)
+                constexpr bool FEEDBACK = PREC == P16 || PREC == PB16;
                 auto push = [&](auto s_, auto k_, auto lat_, C v) __attribute__((always_inline)) {
                     store(s_, k_, lat_, idx, v);
+                };
+                auto push_r = [&](auto s_, auto k_, auto lat_, C v, C& res) __attribute__((always_inline)) {
+                    if constexpr (FEEDBACK) store_r(s_, k_, lat_, idx, v, res);
+                    else store(s_, k_, lat_, idx, v);
                 };
 
                 // ---- f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq ----
@@ -567,6 +607,7 @@ k_lbm(const KParams P) {
                     const C keep = C(1) - wf, half = C(1) - C(0.5) * wf;
                     const C rho0 = C(P.rho0);
                     const C g0 = C(1) - C(1.5) * uu, e0 = p_h - C(0.5) * rho0 * uu;
+                    C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
                         constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
@@ -576,8 +617,11 @@ k_lbm(const KParams P) {
                         const C gam = wk * (g0 + eu * (C(3) + C(4.5) * eu));
                         const C Fk = gam * (eF - uF);
                         const C feq = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu));
-                        push(kc, kc, FLT{}, keep * fpop[k] + wf * feq + half * Fk);
+                        const C v = keep * fpop[k] + wf * feq + half * Fk;
+                        if constexpr (k == 0 && FEEDBACK) rest = v;
+                        else push_r(kc, kc, FLT{}, v, res);
                     });
+                    if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + res);
                 }
 
                 LBM_FENCE();
@@ -588,6 +632,7 @@ k_lbm(const KParams P) {
                     const C keep = C(1) - wg;
                     const C wphi = wg * phi;
                     const C srcS = (C(1) - C(0.5) * wg) * C(m.S);
+                    C res = C(0), rest = C(0);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
                         constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
@@ -595,8 +640,11 @@ k_lbm(const KParams P) {
                         C eq = wphi;
                         if constexpr (ex != 0 || ey != 0 || ez != 0)
                             eq = wphi * (C(1) + edot<ex, ey, ez>(u[0], u[1], u[2]) * inv_cs2s);
-                        push(IC<G0 + k>{}, kc, SLT{}, keep * g[k] + wk * (eq + srcS));
+                        const C v = keep * g[k] + wk * (eq + srcS);
+                        if constexpr (k == 0 && FEEDBACK) rest = v;
+                        else push_r(IC<G0 + k>{}, kc, SLT{}, v, res);
                     });
+                    if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + res);
                 }
 
                 LBM_FENCE();
@@ -607,26 +655,31 @@ k_lbm(const KParams P) {
                     const C wA = rcp<C>(MA * inv_cs2s + C(0.5));
                     const C wB = rcp<C>(MB * inv_cs2s + C(0.5));
                     // rest populations in double: they carry the conserved composition
-                    {
-                        const double whA = double(wA), whB = double(wB);
-                        const double eqA = sA - (1.0 - SL::w(0)) * m.muA;
-                        const double eqB = sB - (1.0 - SL::w(0)) * m.muB;
-                        const double pa = double(a[0]) - whA * (double(a[0]) - eqA);
-                        const double pb = double(b[0]) - whB * (double(b[0]) - eqB);
+                    const double whA = double(wA), whB = double(wB);
+                    const double eqA = sA - (1.0 - SL::w(0)) * m.muA;
+                    const double eqB = sB - (1.0 - SL::w(0)) * m.muB;
+                    const double pa = double(a[0]) - whA * (double(a[0]) - eqA);
+                    const double pb = double(b[0]) - whB * (double(b[0]) - eqB);
+                    if constexpr (!FEEDBACK) {
                         push(IC<A0>{}, IC<0>{}, SLT{}, C(pa));
                         push(IC<B0>{}, IC<0>{}, SLT{}, C(pb));
                     }
                     const C keepA = C(1) - wA, keepB = C(1) - wB;
                     const C wmuA = wA * C(m.muA), wmuB = wB * C(m.muB);
                     const C wcA = wA * C(sA) * inv_cs2s, wcB = wB * C(sB) * inv_cs2s;
+                    C resA = C(0), resB = C(0);
                     static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
                         constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
                         const C wk = C(SL::w(k));
                         const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
-                        push(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu));
-                        push(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu));
+                        push_r(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu), resA);
+                        push_r(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu), resB);
                     });
+                    if constexpr (FEEDBACK) {
+                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(resA)));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(resB)));
+                    }
                 }
 
             } else if constexpr (MODE == MODE_MOMENTS) {
@@ -791,21 +844,31 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
     const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
     const double S0 = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
 
-    auto put = [&](auto s_, auto k_, auto lat_, double v) {
+    // returns the rounding residue (value - stored value); 16-bit storage adds the
+    // residues of a field's moving populations to its rest population, written last
+    auto put = [&](auto s_, auto k_, auto lat_, double v) -> double {
         using L = typename decltype(lat_)::type;
         constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
+        constexpr int F = SLOTS::field(S);
         char* slot = P.dst_base + slot_offset<SLOTS, S>(P);
         const unsigned t = unsigned(idx + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
-        st_at<PREC, SLOTS::rest(S)>(slot, t, float(L::w(k)) * P.fref[SLOTS::field(S)],
-                                    P.fscale[SLOTS::field(S)], C(v));
+        return v - double(st_at_r<PREC, SLOTS::rest(S)>(slot, t, float(L::w(k)) * P.fref[F], P.fscale[F],
+                                                         P.finv[F], C(v)));
     };
-    static_for<0, SL::Q>([&](auto kc) {
+    double rg = 0.0, ra = 0.0, rb = 0.0;
+    static_for<1, SL::Q>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr double wk = SL::w(k);
-        put(IC<G0 + k>{}, kc, std::common_type<SL>{}, wk * phi - 0.5 * wk * S0);
-        put(IC<A0 + k>{}, kc, std::common_type<SL>{}, k == 0 ? cA - (1.0 - wk) * muA : wk * muA);
-        put(IC<B0 + k>{}, kc, std::common_type<SL>{}, k == 0 ? cB - (1.0 - wk) * muB : wk * muB);
+        rg += put(IC<G0 + k>{}, kc, std::common_type<SL>{}, wk * phi - 0.5 * wk * S0);
+        ra += put(IC<A0 + k>{}, kc, std::common_type<SL>{}, wk * muA);
+        rb += put(IC<B0 + k>{}, kc, std::common_type<SL>{}, wk * muB);
     });
+    {
+        constexpr double w0 = SL::w(0);
+        put(IC<G0>{}, IC<0>{}, std::common_type<SL>{}, w0 * phi - 0.5 * w0 * S0 + rg);
+        put(IC<A0>{}, IC<0>{}, std::common_type<SL>{}, cA - (1.0 - w0) * muA + ra);
+        put(IC<B0>{}, IC<0>{}, std::common_type<SL>{}, cB - (1.0 - w0) * muB + rb);
+    }
     if constexpr (FL::Q > 0) {
         double grad[3] = {0.0, 0.0, 0.0}, lap = 0.0;
 #pragma unroll
@@ -824,12 +887,14 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
         const double buoy = (phi - phi_ref) * P.drho;
         const double F[3] = {buoy * P.gx + bracket * grad[0], buoy * P.gy + bracket * grad[1],
                              buoy * P.gz + bracket * grad[2]};
-        static_for<0, FL::Q>([&](auto kc) {
+        double rf = 0.0;
+        static_for<1, FL::Q>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             const double eF = FL::ex(k) * F[0] + FL::ey(k) * F[1] + FL::ez(k) * F[2];
             // f^eq at p_h = 0, u = 0 minus F_k / 2 with Gamma_k(u = 0) = w_k
-            put(kc, kc, std::common_type<FL>{}, -0.5 * FL::w(k) * eF);
+            rf += put(kc, kc, std::common_type<FL>{}, -0.5 * FL::w(k) * eF);
         });
+        put(IC<0>{}, IC<0>{}, std::common_type<FL>{}, rf);  // e_0 . F = 0
     }
 }
 
