@@ -389,8 +389,9 @@ def test_step_external_and_phase_field_match_the_handle():
         sim.step_external(a, b, phi_src)
         phi_pf = sim.phase_field(a)
         sim.step(1)
-        c = sim.save()
-        assert torch.equal(b, c)
+        pop_step = sim.populations()
+        sim.restore(b)  # checkpoints carry unwritten slot padding: compare decoded populations
+        assert torch.equal(sim.populations(), pop_step)
         assert torch.equal(phi_src, phi_pf)
         assert torch.equal(phi_pf, phi_m.to(sim.phi_dtype))
 
@@ -398,7 +399,7 @@ def test_step_external_and_phase_field_match_the_handle():
 def test_adjoint_argument_errors():
     _require_gpu()
     import ctypes
-    from paper_2409_03401_amd.lbm import LBM_EINVAL, LBMError, Simulation, lib
+    from paper_2409_03401_amd.lbm import LBM_EINVAL, Simulation, lib
     p, prec, pops, phi0, muA0, muB0, lam = step_case("d2q9_walls_y_fp64")
     sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
     work = sim.adjoint_workspace()
@@ -413,5 +414,6 @@ def test_adjoint_argument_errors():
     assert L.lbm_step_external(sim._h, ctypes.c_void_p(ck.data_ptr()), ctypes.c_void_p(ck.data_ptr()), null,
                                s) == LBM_EINVAL
     assert L.lbm_adjoint_theta(sim._h, ctypes.c_void_p(work.data_ptr()), null, s) == LBM_EINVAL
-    with pytest.raises(LBMError):
+    with pytest.raises(ValueError):
         sim.adjoint_seed(ck, torch.zeros(3, dtype=torch.float64, device="cuda"), work)
+
