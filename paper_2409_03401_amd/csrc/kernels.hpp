@@ -465,6 +465,11 @@ k_lbm(const KParams P) {
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
 
     const double phi_ref = P.mean_subtract ? *P.phi_ref : 0.0;
+    // a model constant in the compute type (the FP32 copy for FP32 arithmetic)
+    auto KC = [&](double d, float f) __attribute__((always_inline)) -> C {
+        if constexpr (std::is_same<C, float>::value) return f;
+        else return C(d);
+    };
     if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_PHI) {
         // a step between caller checkpoints carries the buffered <phi> over
         if (P.ref_copy && blockIdx.x == 0 && tid == 0) *P.ref_copy = *P.phi_ref;
@@ -558,11 +563,11 @@ k_lbm(const KParams P) {
             C F[3] = {C(0), C(0), C(0)};
             if constexpr (FLOW) {
                 // Eq. SurfaceTension_Force plus buoyancy (phi - phi_ref) drho g
-                const C bracket = C(P.cap) * (C(dwell_d(m.phi)) * C(P.inv_W2) - lap);
-                const C buoy = C((m.phi - phi_ref) * P.drho);
-                F[0] = buoy * C(P.gx) + bracket * grad[0];
-                F[1] = buoy * C(P.gy) + bracket * grad[1];
-                F[2] = buoy * C(P.gz) + bracket * grad[2];
+                const C bracket = KC(P.cap, P.f32.cap) * (C(dwell_d(m.phi)) * KC(P.inv_W2, P.f32.inv_W2) - lap);
+                const C buoy = C(m.phi - phi_ref) * KC(P.drho, P.f32.drho);
+                F[0] = buoy * KC(P.gx, P.f32.gx) + bracket * grad[0];
+                F[1] = buoy * KC(P.gy, P.f32.gy) + bracket * grad[1];
+                F[2] = buoy * KC(P.gz, P.f32.gz) + bracket * grad[2];
                 // Eqs. HydroPressure and Velocity
                 C j0 = C(0), j1 = C(0), j2 = C(0);
                 static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
@@ -572,7 +577,7 @@ k_lbm(const KParams P) {
                     if constexpr (FL::ey(k) != 0) j1 += FL::ey(k) > 0 ? fpop[k] : -fpop[k];
                     if constexpr (FL::ez(k) != 0) j2 += FL::ez(k) > 0 ? fpop[k] : -fpop[k];
                 });
-                const C inv_rho0 = C(1.0 / P.rho0);
+                const C inv_rho0 = KC(1.0 / P.rho0, P.f32.inv_rho0);
                 u[0] = (C(3) * j0 + C(0.5) * F[0]) * inv_rho0;
                 u[1] = (C(3) * j1 + C(0.5) * F[1]) * inv_rho0;
                 u[2] = (C(3) * j2 + C(0.5) * F[2]) * inv_rho0;
@@ -602,10 +607,10 @@ k_lbm(const KParams P) {
                 if constexpr (FLOW) {
                     const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
                     const C uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-                    const C nu = C(P.nu0 * (1.0 - m.phi) + P.nu1 * m.phi);
+                    const C nu = KC(P.nu0, P.f32.nu0) * (C(1) - phi) + KC(P.nu1, P.f32.nu1) * phi;
                     const C wf = rcp<C>(C(3) * nu + C(0.5));
                     const C keep = C(1) - wf, half = C(1) - C(0.5) * wf;
-                    const C rho0 = C(P.rho0);
+                    const C rho0 = KC(P.rho0, P.f32.rho0);
                     const C g0 = C(1) - C(1.5) * uu, e0 = p_h - C(0.5) * rho0 * uu;
                     C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
@@ -628,7 +633,7 @@ k_lbm(const KParams P) {
                 // ---- g: Eqs. LBE_Phi, Geq, Source_LBE_Phi ----
                 // g* = (1 - w) g + w w_k phi (1 + eu / c_s^2) + (1 - w/2) w_k S
                 {
-                    const C wg = C(P.omega_g);
+                    const C wg = KC(P.omega_g, P.f32.omega_g);
                     const C keep = C(1) - wg;
                     const C wphi = wg * phi;
                     const C srcS = (C(1) - C(0.5) * wg) * C(m.S);
@@ -650,8 +655,8 @@ k_lbm(const KParams P) {
                 LBM_FENCE();
                 // ---- h^A, h^B: Eqs. LBE_c_alpha, Heq; mobility interpolated in phi ----
                 {
-                    const C MA = C(P.MA0) * (C(1) - phi) + C(P.MA1) * phi;
-                    const C MB = C(P.MB0) * (C(1) - phi) + C(P.MB1) * phi;
+                    const C MA = KC(P.MA0, P.f32.MA0) * (C(1) - phi) + KC(P.MA1, P.f32.MA1) * phi;
+                    const C MB = KC(P.MB0, P.f32.MB0) * (C(1) - phi) + KC(P.MB1, P.f32.MB1) * phi;
                     const C wA = rcp<C>(MA * inv_cs2s + C(0.5));
                     const C wB = rcp<C>(MB * inv_cs2s + C(0.5));
                     // rest populations in double: they carry the conserved composition

@@ -222,6 +222,21 @@ void fill_params(lbm_handle* h) {
     kp.inv_W2 = 1.0 / (c.W * c.W);
     kp.dK_dW = -2.0 * c.M_phi / (c.W * c.W * c.W);
     kp.dcap_dW = 1.5 * c.sigma;
+    kp.f32.cap = float(kp.cap);
+    kp.f32.inv_W2 = float(kp.inv_W2);
+    kp.f32.drho = float(kp.drho);
+    kp.f32.gx = float(kp.gx);
+    kp.f32.gy = float(kp.gy);
+    kp.f32.gz = float(kp.gz);
+    kp.f32.inv_rho0 = float(1.0 / kp.rho0);
+    kp.f32.rho0 = float(kp.rho0);
+    kp.f32.nu0 = float(kp.nu0);
+    kp.f32.nu1 = float(kp.nu1);
+    kp.f32.omega_g = float(kp.omega_g);
+    kp.f32.MA0 = float(kp.MA0);
+    kp.f32.MA1 = float(kp.MA1);
+    kp.f32.MB0 = float(kp.MB0);
+    kp.f32.MB1 = float(kp.MB1);
     const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
     for (int f = 0; f < 4; ++f) {
         const int sh = sixteen ? c.store_shift[f] : 0;

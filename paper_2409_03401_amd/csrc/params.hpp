@@ -49,6 +49,11 @@ struct KParams {
     double cap;                  // 3/2 sigma W of Eq. SurfaceTension_Force
     double inv_W2;
     double dK_dW, dcap_dW;       // -2 M_phi / W^3 and 3/2 sigma (adjoint: d/dW)
+    // FP32 copies of the constants the FP32 collision uses (one SGPR each, no
+    // conversion in the loop)
+    struct {
+        float cap, inv_W2, drho, gx, gy, gz, inv_rho0, rho0, nu0, nu1, omega_g, MA0, MA1, MB0, MB1;
+    } f32;
     // population copies addressed by the fused kernel: slot s of a copy starts at
     // base + (#moving slots before s) * stride_m + (#rest slots before s) * stride_r
     const char* src_base;
