@@ -142,15 +142,22 @@ __device__ __forceinline__ unsigned long long slot_offset(const KParams& P) {
 }
 
 // load one population at node idx and decode it to the compute type
-template <int PREC, bool REST>
+// NT: a non-temporal load, for data no other work-group reads
+template <class T, bool NT>
+__device__ __forceinline__ T ld_raw(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <int PREC, bool REST, bool NT = false>
 __device__ __forceinline__ typename Stor<PREC>::C ld_at(const char* slot, unsigned idx, float wref,
                                                         float inv_scale) {
     if constexpr (PREC == P64) {
-        return *reinterpret_cast<const double*>(slot + idx * 8u);
+        return ld_raw<double, NT>(reinterpret_cast<const double*>(slot + idx * 8u));
     } else if constexpr (PREC == P32 || REST) {
-        return *reinterpret_cast<const float*>(slot + idx * 4u);
+        return ld_raw<float, NT>(reinterpret_cast<const float*>(slot + idx * 4u));
     } else {
-        const unsigned short bits = *reinterpret_cast<const unsigned short*>(slot + idx * 2u);
+        const unsigned short bits = ld_raw<unsigned short, NT>(reinterpret_cast<const unsigned short*>(slot + idx * 2u));
         float v;
         if constexpr (PREC == P16) v = __half2float(__ushort_as_half(bits));
         else v = float(__builtin_bit_cast(__bf16, bits));
@@ -274,6 +281,9 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #ifndef LBM_LDS_POPS
 #define LBM_LDS_POPS 1
 #endif
+#ifndef LBM_NT_FLUID
+#define LBM_NT_FLUID 1
+#endif
 #ifndef LBM_SCALAR_BASES
 #define LBM_SCALAR_BASES 1
 #endif
@@ -370,6 +380,15 @@ k_lbm(const KParams P) {
     auto load = [&](auto s_, auto k_, auto lat_, unsigned idx) __attribute__((always_inline)) -> C {
         constexpr int S = decltype(s_)::value;
         return ld_at<PREC, SLOTS::rest(S)>(src(s_), idx, wref(s_, k_, lat_), P.finv[SLOTS::field(S)]);
+    };
+    // fluid populations that arrive without an x shift are read by this work-group
+    // only (no ring, no x neighbour shares their lines): streamed past the caches.
+    // Measured: +1.7% for the 3D step, -1.7% for 2D (one row per work-group), so 3D only
+    auto load_once = [&](auto s_, auto k_, auto lat_, unsigned idx) __attribute__((always_inline)) -> C {
+        constexpr int S = decltype(s_)::value;
+        using L = typename decltype(lat_)::type;
+        constexpr bool NT = LBM_NT_FLUID && SL::DIM == 3 && L::ex(decltype(k_)::value) == 0;
+        return ld_at<PREC, SLOTS::rest(S), NT>(src(s_), idx, wref(s_, k_, lat_), P.finv[SLOTS::field(S)]);
     };
     auto store = [&](auto s_, auto k_, auto lat_, unsigned idx, C v) __attribute__((always_inline)) {
         constexpr int S = decltype(s_)::value;
@@ -499,7 +518,7 @@ k_lbm(const KParams P) {
                         constexpr int k = decltype(kc)::value;
                         const unsigned src_idx =
                             unsigned(int(idx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(nbr));
-                        fpop[k] = load(kc, kc, FLT{}, src_idx);
+                        fpop[k] = load_once(kc, kc, FLT{}, src_idx);
                     });
                 }
             }
