@@ -163,7 +163,7 @@ def cpu_baseline(budget_s=12.0):
                       f"in {el:.1f} s (single thread; host has {os.cpu_count()} logical CPUs)"}
 
 
-def adjoint_timing(n=512, steps=4096, segment=None):
+def adjoint_timing(n=512, steps=4096, segment=None, kind="single_drop_2d"):
     """Forward and backward wall time of the differentiable run on the sedimenting
     drop (n x n, D2Q9 + 3 x D2Q5, FP32 storage, T = steps, checkpoints every
     ceil(sqrt(T)) steps).  The backward pass includes the recomputation of every
@@ -172,7 +172,7 @@ def adjoint_timing(n=512, steps=4096, segment=None):
     from paper_2409_03401_amd import inputs
     from paper_2409_03401_amd.lbm import LBMConfig, Simulation, phase_field_run, theta_of
 
-    w = inputs.single_drop_2d(n=n)
+    w = inputs.single_drop_2d(n=n) if kind == "single_drop_2d" else inputs.sediment_3d(n=n, ndrops=max(4, n // 4))
     cfg = LBMConfig(**w.params, precision="fp32")
     sim = Simulation(cfg, w.phi0, w.muA0, w.muB0)
     sim.step(16)
@@ -204,7 +204,7 @@ def adjoint_timing(n=512, steps=4096, segment=None):
     torch.cuda.empty_cache()
     seg = segment or (math.isqrt(steps - 1) + 1)
     return {
-        "workload": f"single_drop_2d_{n}_fp32",
+        "workload": f"{kind}_{n}_fp32",
         "steps": steps,
         "segment": seg,
         "forward_ms": round(fwd * 1e3, 2),
@@ -229,6 +229,7 @@ def main():
     ap.add_argument("--adjoint-n", type=int, nargs="+", default=[512, 2048],
                     help="grid sizes n (n x n) for --adjoint-only")
     ap.add_argument("--adjoint-steps", type=int, default=4096)
+    ap.add_argument("--adjoint-kind", default="single_drop_2d", choices=["single_drop_2d", "sediment_3d"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale HBM counters")
     args = ap.parse_args()
@@ -259,7 +260,7 @@ def main():
         res = {}
         for n in args.adjoint_n:
             print(f"[bench] adjoint timing at {n}^2", file=sys.stderr, flush=True)
-            res[str(n)] = adjoint_timing(n=n, steps=args.adjoint_steps)
+            res[str(n)] = adjoint_timing(n=n, steps=args.adjoint_steps, kind=args.adjoint_kind)
         print(json.dumps({"adjoint": res}), flush=True)
         return
 
