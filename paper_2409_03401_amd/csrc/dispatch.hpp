@@ -18,8 +18,6 @@ struct KernelSet {
     // adjoint: nullptr when the storage precision has no adjoint (16-bit formats)
     void (*adj_step)(const KParams& kp, long long nodes, const void* phi, hipStream_t s);
     void (*adj_seed)(const KParams& kp, long long nodes, const double* dL_dphi, hipStream_t s);
-    // exchange of the wall pairs of the current adjoint before an adjoint step
-    void (*adj_walls)(const KParams& kp, int axis, hipStream_t s);
     void (*adj_gather)(const KParams& kp, long long nodes, int mode, double* grad_phi0, hipStream_t s);
     void (*adj_init_local)(const KParams& kp, long long nodes, const double* phi0, const double* muA0,
                            const double* muB0, hipStream_t s);

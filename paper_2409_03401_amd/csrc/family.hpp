@@ -56,11 +56,6 @@ struct Family {
         hipLaunchKernelGGL((k_adj_seed<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
                            nodes, dL_dphi);
     }
-    static void adj_walls(const KParams& kp, int axis, hipStream_t s) {
-        const long long n[3] = {kp.nx, kp.ny, kp.nz};
-        const long long face = n[axis == 0 ? 1 : 0] * n[axis == 2 ? 1 : 2];
-        hipLaunchKernelGGL((k_adj_walls<SL, FL>), dim3(unsigned((2 * face + 255) / 256)), dim3(256), 0, s, kp, axis);
-    }
     static void adj_gather(const KParams& kp, long long nodes, int mode, double* grad_phi0, hipStream_t s) {
         const dim3 grid(unsigned((nodes + 255) / 256));
         if (mode == 0) hipLaunchKernelGGL((k_adj_gather<SL, FL, 0>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
@@ -78,8 +73,7 @@ struct Family {
     }
     static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, &walls,
                                    kAdj ? &adj_step : nullptr, kAdj ? &adj_seed : nullptr,
-                                   kAdj ? &adj_walls : nullptr, kAdj ? &adj_gather : nullptr,
-                                   kAdj ? &adj_init_local : nullptr,
+                                   kAdj ? &adj_gather : nullptr, kAdj ? &adj_init_local : nullptr,
                                    kAdj ? &adj_copy : nullptr, TX, TY};
 };
 

@@ -973,90 +973,10 @@ __device__ __forceinline__ void theta_from_K(double K_b, const KParams& P, doubl
     th[5] += K_b * (-2.0 * P.mphi_w2 / P.W);
 }
 
-// Transposed streaming at walls.  The adjoint step needs mu_k(x) = Lambda_k(x + e_k),
-// or Lambda_opp(k)(x) when x + e_k lies across a wall (bounce-back), where Lambda =
-// lambda (+ c_F for scalar fields).  For every such pair (once, k < opp(k)) this
-// kernel exchanges the full adjoints Lambda_k(x'') and Lambda_opp(k)(x), x'' =
-// wrap(x + e_k), storing each minus the c_F of its new node, so that the step can
-// gather periodically.  Same face enumeration as k_walls.
-template <class SL, class FL>
-__global__ void __launch_bounds__(256) k_adj_walls(const KParams P, int axis) {
-    using SLOTS = Slots<FL::Q, SL::Q>;
-    const int n[3] = {P.nx, P.ny, P.nz};
-    const int ab = axis == 0 ? 1 : 0, ac = axis == 2 ? 1 : 2;
-    const long long face = (long long)n[ab] * n[ac];
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * face) return;
-    int c[3];
-    c[axis] = t < face ? 0 : n[axis] - 1;
-    const long long r = t % face;
-    c[ab] = int(r % n[ab]);
-    c[ac] = int(r / n[ab]);
-    const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
-    for (int a = 0; a < axis; ++a)
-        if (wall[a] && (c[a] == 0 || c[a] == n[a] - 1)) return;
-    if (n[axis] == 1 && t >= face) return;
-    const unsigned long long idx = (unsigned long long)((c[2] * P.ny + c[1]) * P.nx + c[0]);
-    float* lam = reinterpret_cast<float*>(const_cast<char*>(P.adj_in));
-    const unsigned long long ls = P.adj_stride / 4;
-    const float* cin = P.aux + kAuxC * P.aux_stride;
-    auto pairs = [&](auto&& fn) {
-        auto lattice = [&](auto lat_, auto base_, auto field_) {
-            using L = typename decltype(lat_)::type;
-            constexpr int B = decltype(base_)::value;
-            static_for<1, L::Q>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                constexpr int o = L::opp(k);
-                if constexpr (k < o) fn(IC<B + k>{}, IC<B + o>{}, field_, IC<L::ex(k)>{}, IC<L::ey(k)>{}, IC<L::ez(k)>{});
-            });
-        };
-        if constexpr (FL::Q > 0) lattice(std::common_type<FL>{}, IC<0>{}, IC<-1>{});
-        lattice(std::common_type<SL>{}, IC<SLOTS::G0>{}, IC<0>{});
-        lattice(std::common_type<SL>{}, IC<SLOTS::A0>{}, IC<1>{});
-        lattice(std::common_type<SL>{}, IC<SLOTS::B0>{}, IC<2>{});
-    };
-    // node wrap(x + e) and whether x + e lies across a wall
-    auto target = [&](int ex, int ey, int ez, bool& cross) {
-        const int e[3] = {ex, ey, ez};
-        int q[3];
-        cross = false;
-        for (int a = 0; a < 3; ++a) {
-            if (wall[a] && e[a] != 0 && (c[a] + e[a] < 0 || c[a] + e[a] >= n[a])) cross = true;
-            q[a] = (c[a] + e[a] + n[a]) % n[a];
-        }
-        return (unsigned long long)((q[2] * P.ny + q[1]) * P.nx + q[0]);
-    };
-    constexpr int NP = (FL::Q > 0 ? (FL::Q - 1) / 2 : 0) + 3 * ((SL::Q - 1) / 2);
-    float fa[NP], fb[NP], ca[NP], cb[NP];
-    bool cr[NP];
-    int np = 0;
-    // loads of every pair first, then the stores
-    pairs([&](auto s_, auto o_, auto f_, auto ex_, auto ey_, auto ez_) {
-        constexpr int S = decltype(s_)::value, O = decltype(o_)::value, F = decltype(f_)::value;
-        const int p = np++;
-        const unsigned long long xq = target(ex_.value, ey_.value, ez_.value, cr[p]);
-        if (cr[p]) {
-            ca[p] = F >= 0 ? cin[F * P.aux_stride + xq] : 0.0f;
-            cb[p] = F >= 0 ? cin[F * P.aux_stride + idx] : 0.0f;
-            fa[p] = lam[S * ls + xq] + ca[p];
-            fb[p] = lam[O * ls + idx] + cb[p];
-        }
-    });
-    np = 0;
-    pairs([&](auto s_, auto o_, auto f_, auto ex_, auto ey_, auto ez_) {
-        constexpr int S = decltype(s_)::value, O = decltype(o_)::value;
-        const int p = np++;
-        bool cross;
-        const unsigned long long xq = target(ex_.value, ey_.value, ez_.value, cross);
-        if (cr[p]) {
-            lam[S * ls + xq] = fb[p] - ca[p];
-            lam[O * ls + idx] = fa[p] - cb[p];
-        }
-    });
-}
-
 // Adjoint of one step, one thread per node.  mu = dL/dQ(x) is the transposed
-// streaming of the adjoint of step n + 1 (walls exchanged by k_adj_walls).  The arriving populations of state n are pulled
+// streaming of the adjoint of step n + 1: mu_k(x) = Lambda_k(x + e_k), or
+// Lambda_opp(k)(x) when x + e_k lies across a wall (bounce-back), where Lambda =
+// lambda (+ c_F for scalar fields).  The arriving populations of state n are pulled
 // as in the step; the phi stencil reads phi of state n (`phi`, written by the step
 // that left state n).  lambda^n gets the local part (P.adj_out); dL/dG, dL/dN and the
 // sensitivities of phi go to aux rows 0..6 for k_adj_gather; theta partials
@@ -1114,7 +1034,10 @@ k_adj_node(const KParams P, long long nodes, const typename Stor<PREC>::C* __res
             });
         }
         const float* cin = P.aux + kAuxC * P.aux_stride;
-        // mu_s(x) = Lambda_s(wrap(x + e_s)); wall pairs were exchanged by k_adj_walls
+        const unsigned own = voff(idx * 4u);
+        const bool lo[3] = {P.wall_x && x == 0, P.wall_y && y == 0, P.wall_z && z == 0};
+        const bool hi[3] = {P.wall_x && x == P.nx - 1, P.wall_y && y == P.ny - 1, P.wall_z && z == P.nz - 1};
+        // mu_s(x) = Lambda_s(wrap(x + e_s)), or Lambda_opp(s)(x) across a wall
         auto mu_of = [&](auto s_) __attribute__((always_inline)) -> T {
             constexpr int S = decltype(s_)::value;
             constexpr bool FLUID = S < G0;
@@ -1132,11 +1055,41 @@ k_adj_node(const KParams P, long long nodes, const typename Stor<PREC>::C* __res
             }
             return T(v);
         };
-        // adjoint of step n + 1 read once into registers
+        // bounce-back: Lambda_opp(s)(x) at the node itself when x + e_s crosses a wall
+        auto mu_wall = [&](auto s_, T& v) __attribute__((always_inline)) {
+            constexpr int S = decltype(s_)::value;
+            constexpr bool FLUID = S < G0;
+            constexpr int F = FLUID ? -1 : (S - G0) / QS;
+            constexpr int k = FLUID ? S : (S - G0) % QS;
+            using L = typename std::conditional<FLUID, FL, SL>::type;
+            constexpr int ex = L::ex(k), ey = L::ey(k), ez = L::ez(k);
+            if constexpr (ex != 0 || ey != 0 || ez != 0) {
+                bool cross = false;
+                if constexpr (ex > 0) cross = cross || hi[0];
+                if constexpr (ex < 0) cross = cross || lo[0];
+                if constexpr (ey > 0) cross = cross || hi[1];
+                if constexpr (ey < 0) cross = cross || lo[1];
+                if constexpr (ez > 0) cross = cross || hi[2];
+                if constexpr (ez < 0) cross = cross || lo[2];
+                if (cross) {
+                    constexpr int O = S - k + L::opp(k);
+                    const char* lo_ = P.adj_in + (unsigned long long)O * P.adj_stride;
+                    float w = *reinterpret_cast<const float*>(lo_ + own);
+                    if constexpr (F >= 0)
+                        w += *reinterpret_cast<const float*>(
+                            reinterpret_cast<const char*>(cin + (unsigned long long)F * P.aux_stride) + own);
+                    v = T(w);
+                }
+            }
+        };
+        // adjoint of step n + 1 read once into registers: every neighbour load first,
+        // then the wall lanes' replacements (a region that other waves skip)
         T muv[SLOTS::N];
         static_for<0, SLOTS::N>([&](auto sc) __attribute__((always_inline)) { muv[sc.value] = mu_of(sc); });
+        const bool wall_lane = lo[0] || lo[1] || lo[2] || hi[0] || hi[1] || hi[2];
+        if (wall_lane)
+            static_for<0, SLOTS::N>([&](auto sc) __attribute__((always_inline)) { mu_wall(sc, muv[sc.value]); });
         auto mu_reg = [&](auto s_) __attribute__((always_inline)) -> T { return muv[decltype(s_)::value]; };
-        const unsigned own = voff(idx * 4u);
         auto put = [&](auto s_, T v) __attribute__((always_inline)) {
             char* o = P.adj_out + (unsigned long long)decltype(s_)::value * P.adj_stride;
             __builtin_nontemporal_store(float(v), reinterpret_cast<float*>(o + own));

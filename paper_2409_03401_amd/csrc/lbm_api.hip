@@ -540,9 +540,6 @@ int lbm_adjoint_step(lbm_handle* h, const void* state, const void* phi, void* wo
     set_slots(h, kp, static_cast<const char*>(state), nullptr);
     kp.phi_ref = reinterpret_cast<const double*>(static_cast<const char*>(state) + h->L.copy_bytes);
     adjoint_params(h, kp, a, h->adj_cur, 1 - h->adj_cur);
-    const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
-    for (int ax = 0; ax < 3; ++ax)
-        if (walls[ax]) h->ks->adj_walls(kp, ax, s);
     h->ks->adj_step(kp, h->L.nodes, phi, s);
     h->ks->adj_gather(kp, h->L.nodes, 0, nullptr, s);
     h->adj_cur = 1 - h->adj_cur;
