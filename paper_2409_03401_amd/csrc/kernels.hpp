@@ -287,9 +287,6 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #ifndef LBM_SCALAR_BASES
 #define LBM_SCALAR_BASES 1
 #endif
-#ifndef LBM_PTR_ARRAY
-#define LBM_PTR_ARRAY 0
-#endif
 #ifndef LBM_PHASES
 #define LBM_PHASES 0
 #endif
@@ -365,12 +362,10 @@ k_lbm(const KParams P) {
     using gconst = __attribute__((address_space(1))) const char;
     using gmut = __attribute__((address_space(1))) char;
     auto src = [&](auto s_) __attribute__((always_inline)) -> const char* {
-        if constexpr (LBM_PTR_ARRAY) return static_cast<const char*>(P.src[decltype(s_)::value]);
-        else return (const char*)((gconst*)sbase + slot_off(s_));
+        return (const char*)((gconst*)sbase + slot_off(s_));
     };
     auto dst = [&](auto s_) __attribute__((always_inline)) -> char* {
-        if constexpr (LBM_PTR_ARRAY) return static_cast<char*>(P.dst[decltype(s_)::value]);
-        else return (char*)((gmut*)dbase + slot_off(s_));
+        return (char*)((gmut*)dbase + slot_off(s_));
     };
     // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
     auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {

@@ -30,17 +30,6 @@ int fail(int code, const std::string& msg) {
 constexpr size_t kAlign = 256;
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// weights of the paper's lattices in canonical order (for the 16-bit references)
-double lattice_w(int q, int k) {
-    switch (q) {
-        case 5: return D2Q5K::w(k);
-        case 7: return D3Q7K::w(k);
-        case 9: return D2Q9K::w(k);
-        case 19: return D3Q19K::w(k);
-    }
-    return 0.0;
-}
-
 struct Layout {
     const KernelSet* ks;
     int dim, qf, qs, nslots, prec;
@@ -83,6 +72,9 @@ int check_config(const lbm_config* c, Layout* L) {
             return fail(LBM_EINVAL, "bc must be LBM_PERIODIC or LBM_WALLS");
     const long long nodes = (long long)c->nx * c->ny * c->nz;
     if (nodes >= (1LL << 31)) return fail(LBM_EUNSUPPORTED, "more than 2^31 - 1 nodes");
+    // kernels address a slot with a 32-bit byte offset: nodes x (8 B FP64, else 4 B) < 2^32
+    if ((unsigned long long)nodes * (c->precision == LBM_FP64 ? 8ull : 4ull) > 0xFFFFFFFFull)
+        return fail(LBM_EUNSUPPORTED, "grid too large for 32-bit slot offsets (FP64: < 2^29 nodes, else < 2^30)");
     const bool flow = c->fluid != LBM_NONE;
     if (c->gravity_mean_subtract && !flow)
         return fail(LBM_EINVAL, "gravity_mean_subtract needs a fluid lattice");
@@ -185,10 +177,6 @@ namespace {
 void set_slots(const lbm_handle* h, KParams& kp, const char* src, char* dst) {
     kp.src_base = src;
     kp.dst_base = dst;
-    for (int s = 0; s < kMaxSlots; ++s) {
-        kp.src[s] = (src && s < h->L.nslots) ? src + h->L.slot_off[s] : nullptr;
-        kp.dst[s] = (dst && s < h->L.nslots) ? dst + h->L.slot_off[s] : nullptr;
-    }
 }
 
 void fill_params(lbm_handle* h) {

@@ -65,9 +65,6 @@ struct KParams {
     // device scalars
     const double* phi_ref;       // buoyancy reference <phi> (aux area)
     double* partials;            // per-work-group partial sums
-    // populations: canonical slot order f_0.., g_0.., hA_0.., hB_0..
-    const void* src[kMaxSlots];
-    void* dst[kMaxSlots];
     // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame)
     void* mout[kNumMom];
     int mout_f32;

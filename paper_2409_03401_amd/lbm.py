@@ -377,6 +377,8 @@ class PhaseFieldRun(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, phi0, theta, cfg, steps, muA0, muB0, segment=None):
+        if cfg.precision not in ("fp32", "fp64") or cfg.gravity_mean_subtract:
+            raise ValueError("the adjoint runs on fp32 or fp64 storage without gravity_mean_subtract")
         steps = int(steps)
         seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
         c = with_theta(cfg, theta.detach().double().cpu().tolist())

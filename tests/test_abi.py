@@ -62,6 +62,8 @@ def test_state_bytes_layout():
     (dict(W=-1.0), lbm.LBM_EINVAL),
     (dict(W=float("nan")), lbm.LBM_EINVAL),
     (dict(gravity_mean_subtract=True), lbm.LBM_EINVAL),   # needs a fluid
+    (dict(nx=32768, ny=32768, precision="fp32"), lbm.LBM_EUNSUPPORTED),  # 2^30 nodes x 4 B = 2^32
+    (dict(nx=32768, ny=16384, precision="fp64"), lbm.LBM_EUNSUPPORTED),  # 2^29 nodes x 8 B = 2^32
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:
