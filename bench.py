@@ -215,6 +215,38 @@ def adjoint_timing(n=512, steps=4096, segment=None, kind="single_drop_2d"):
     }
 
 
+def series_run(name, steps, every):
+    """Droplet count, mean radius and max |u| over a run (diagnostics every `every`
+    steps, recorded on the GPU), with a least-squares fit of <R>^3 = a + k t over the
+    second half of the records (coarsening law of the ripening workload)."""
+    import numpy as np
+    import torch
+    from paper_2409_03401_amd.lbm import LBMConfig, Simulation
+    w = build_workload(name)
+    cfg = LBMConfig(**w.params, precision=w.precision)
+    sim = Simulation(cfg, w.phi0, w.muA0, w.muB0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = sim.run_series(steps, every)
+    wall = time.perf_counter() - t0
+    t = d["step"].astype(float)
+    R3 = d["mean_radius"] ** 3
+    h = len(t) // 2
+    k, a = np.polyfit(t[h:], R3[h:], 1)
+    fit = a + k * t[h:]
+    r2 = 1.0 - np.sum((R3[h:] - fit) ** 2) / max(np.sum((R3[h:] - R3[h:].mean()) ** 2), 1e-300)
+    return {
+        "workload": name, "steps": steps, "every": every,
+        "MLUPS_with_diagnostics": round(cfg.nodes * steps / wall / 1e6, 1),
+        "placed_droplets": len(w.drops) if w.drops else None,
+        "step": d["step"].tolist(), "droplets": d["droplets"].tolist(),
+        "mean_radius": [round(v, 4) for v in d["mean_radius"]],
+        "max_u": [float(f"{v:.4e}") for v in d["max_u"]],
+        "nan_count": int(d["nan_count"].max()),
+        "R3_fit_second_half": {"slope_per_step": float(f"{k:.5e}"), "intercept": round(a, 3), "r2": round(r2, 5)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +262,10 @@ def main():
                     help="grid sizes n (n x n) for --adjoint-only")
     ap.add_argument("--adjoint-steps", type=int, default=4096)
     ap.add_argument("--adjoint-kind", default="single_drop_2d", choices=["single_drop_2d", "sediment_3d"])
+    ap.add_argument("--series", default=None, choices=sorted(WORKLOADS),
+                    help="only record the diagnostics time series of a workload (droplet count, <R>, max |u|)")
+    ap.add_argument("--series-steps", type=int, default=20000)
+    ap.add_argument("--series-every", type=int, default=500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale HBM counters")
     args = ap.parse_args()
@@ -255,6 +291,12 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+
+    if args.series:
+        print(f"[bench] diagnostics series of {args.series}: {args.series_steps} steps, every "
+              f"{args.series_every}", file=sys.stderr, flush=True)
+        print(json.dumps({"series": series_run(args.series, args.series_steps, args.series_every)}), flush=True)
+        return
 
     if args.adjoint_only:
         res = {}

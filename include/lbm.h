@@ -70,7 +70,17 @@ extern "C" {
 #define LBM_D_INTERFACE 5     /* sum_x (4/W) phi (1 - phi), integrand of Eq. Rmoy_2D */
 #define LBM_D_FREE_ENERGY 6   /* sum_x [W^2/2 |grad phi|^2 + omega_dw + lambda/2 |mu|^2] */
 #define LBM_D_NAN_COUNT 7     /* nodes whose phi, c^A or c^B is not finite          */
-#define LBM_NDIAG 8
+/* Section 4.2.2, geometry measurements.  LBM_D_DROPLETS is the Euler
+ * characteristic of the union of the closed unit cells of the nodes with
+ * phi >= 1/2 (vertices - edges + faces - cubes; periodic axes close on a torus,
+ * cells end at walls), which is the droplet count N for separated simply
+ * connected droplets.  The count runs over the axes of the run: 2D runs and 3D
+ * runs with nz = 1 give a planar complex.  LBM_D_MEAN_RADIUS is <R> from the
+ * interface integral I = LBM_D_INTERFACE: I / (2 pi N) in 2D (Eq. Rmoy_2D),
+ * sqrt(I / (4 pi N)) in 3D (spheres), 0 when N <= 0. */
+#define LBM_D_DROPLETS 8
+#define LBM_D_MEAN_RADIUS 9
+#define LBM_NDIAG 10
 
 /*
  * Physical parameters in lattice units (dx = dt = 1).  Section 2 of the paper
@@ -101,8 +111,9 @@ typedef struct lbm_config {
 
 typedef struct lbm_handle lbm_handle;
 
-/* Size of the state buffer lbm_init needs (two population copies plus a small
- * reduction area), and of one checkpoint written by lbm_save. */
+/* Size of the state buffer lbm_init needs (two population copies, a small
+ * reduction area and a one-byte-per-node mask of the diagnostics), and of one
+ * checkpoint written by lbm_save. */
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes);
 int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes);
 
@@ -131,6 +142,14 @@ int lbm_moments(lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtyp
 /* FP64 reductions of the current state into host_out[LBM_NDIAG].  Synchronises
  * `stream`. */
 int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream);
+
+/* Time series of the diagnostics (droplet count, mean radius and max |u| curves
+ * of Sections 4.2.2-4.2.4): records lbm_diagnostics of the current state, then
+ * advances `every` steps and records again, nsteps / every times.  host_out
+ * receives (nsteps / every + 1) rows of LBM_NDIAG doubles.  nsteps >= 0 must be a
+ * multiple of every >= 1 (LBM_EINVAL otherwise, nothing done).  Synchronises
+ * `stream` at every record. */
+int lbm_run_series(lbm_handle* h, int64_t nsteps, int64_t every, double* host_out, void* stream);
 
 /* Current populations decoded to FP64, canonical order: f_0..f_{Qf-1},
  * g_0..g_{Qs-1}, hA_0.., hB_0.. (paper's direction order), each [node].

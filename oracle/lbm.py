@@ -39,7 +39,7 @@ from typing import Optional, Tuple
 
 import numpy as np
 
-from . import model
+from . import geometry, model
 from .lattices import BY_NAME, D2Q9, D3Q19
 
 
@@ -358,7 +358,7 @@ def run(st, prm, nsteps):
 # diagnostics
 
 DIAG_NAMES = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u",
-              "interface_measure", "free_energy", "nan_count")
+              "interface_measure", "free_energy", "nan_count", "droplets", "mean_radius")
 
 
 def diagnostics(st, prm):
@@ -369,7 +369,8 @@ def diagnostics(st, prm):
     which is the functional of Eq. functional in units of H after the Legendre
     transform with the parabolic wells (bulk free energy density = |mu|^2 / 2 in
     units of K, lambda = K/H); gradient on the dimension's fluid lattice;
-    count of nodes whose phi, c^A or c^B is not finite."""
+    count of nodes whose phi, c^A or c^B is not finite; droplet count N and mean
+    radius <R> of Section 4.2.2 (geometry module, on the real part of phi)."""
     m = moments(st, prm)
     phi = m["phi"]
     u2 = m["ux"] ** 2 + m["uy"] ** 2 + m["uz"] ** 2
@@ -377,7 +378,9 @@ def diagnostics(st, prm):
     g2 = grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2
     fe = 0.5 * prm.W ** 2 * g2 + model.omega_dw(phi) + 0.5 * prm.lam * (m["muA"] ** 2 + m["muB"] ** 2)
     bad = ~(np.isfinite(phi) & np.isfinite(m["cA"]) & np.isfinite(m["cB"]))
+    n_drops = geometry.euler_characteristic(phi.real, prm.bc)
     return dict(sum_cA=m["cA"].sum(), sum_cB=m["cB"].sum(), sum_phi=phi.sum(),
                 kinetic_energy=(0.5 * prm.rho0 * u2).sum(), max_u=np.sqrt(u2.real).max(),
                 interface_measure=((4.0 / prm.W) * phi * (1.0 - phi)).sum(),
-                free_energy=fe.sum(), nan_count=int(bad.sum()))
+                free_energy=fe.sum(), nan_count=int(bad.sum()),
+                droplets=n_drops, mean_radius=geometry.mean_radius(phi.real, prm.W, n_drops))

@@ -37,5 +37,8 @@ void launch_finalize(const double* partials, int nparts, int width, int maxslot,
 // out[0..5] (+)= sum of [nparts][6] partials (parameter gradients)
 void launch_sum6(const double* partials, int nparts, double* out, bool accumulate, hipStream_t s);
 void launch_zero(double* p, long long n, hipStream_t s);
+// Euler characteristic of a node mask: partials[0 .. nblocks) receive the sums of
+// nblocks work-groups striding over the anchors
+void launch_euler(const unsigned char* mask, const EulerGeom& g, double* partials, int nblocks, hipStream_t s);
 
 }  // namespace lbm

@@ -724,6 +724,7 @@ k_lbm(const KParams P) {
                 acc[5] += (4.0 / P.W) * m.phi * (1.0 - m.phi);
                 acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) + 0.5 * P.lam * (m.muA * m.muA + m.muB * m.muB);
                 acc[7] += (isfinite(m.phi) && isfinite(sA) && isfinite(sB)) ? 0.0 : 1.0;
+                P.mask_out[idx] = m.phi >= 0.5 ? 1 : 0;
             }
         }
         if constexpr (STENCIL) {
@@ -1370,6 +1371,70 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
             else out[i] = v;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// droplet count (Section 4.2.2): Euler characteristic chi = sum over the
+// elements of the cell complex of (-1)^dim, where the complex is the union of the
+// closed unit cells of the nodes whose mask byte is set.  Every element is the
+// cell-like part S (a subset of the axes) of one anchor: along the axes in S it is
+// the cell interval j, along the others the vertex position between cells j - 1
+// and j.  It belongs to the complex when one of the 2^(d - |S|) cells containing
+// it is set, and has dimension |S|.  One thread per anchor reads the 2^d cells
+// around it (cells across a wall are empty, periodic axes wrap), so every element
+// is counted once.  The grid strides over the anchors; partials[blockIdx.x]
+// receives the work-group's sum (an integer, exact in FP64).
+
+template <int D>
+__global__ void __launch_bounds__(256) k_euler(const unsigned char* __restrict__ mask, const EulerGeom G,
+                                               double* __restrict__ partials) {
+    int acc = 0;
+    const long long step = (long long)gridDim.x * 256;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < G.nanchors; t += step) {
+        int j[D];
+        long long r = t;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const long long m = G.n[a] + G.wall[a];
+            j[a] = int(r % m);
+            r /= m;
+        }
+        // bit o set: cell (j_a - 1 + o_a)_a is in the complex (o_a = bit a of o)
+        unsigned bits = 0;
+#pragma unroll
+        for (int o = 0; o < (1 << D); ++o) {
+            long long off = 0;
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int c = j[a] - 1 + ((o >> a) & 1);
+                if (c < 0) {
+                    if (G.wall[a]) in = false;
+                    else c += G.n[a];
+                } else if (c >= G.n[a]) {
+                    if (G.wall[a]) in = false;
+                    else c -= G.n[a];
+                }
+                off += (long long)c * G.stride[a];
+            }
+            if (in && mask[off]) bits |= 1u << o;
+        }
+#pragma unroll
+        for (int S = 0; S < (1 << D); ++S) {
+            bool valid = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                if (((S >> a) & 1) && j[a] >= G.n[a]) valid = false;  // no cell j past the last one
+            // cells containing the element: o has every bit of S
+            bool present = false;
+#pragma unroll
+            for (int o = 0; o < (1 << D); ++o)
+                if ((o & S) == S && ((bits >> o) & 1u)) present = true;
+            if (valid && present) acc += (__builtin_popcount(S) & 1) ? -1 : 1;
+        }
+    }
+    double v[1] = {double(acc)};
+    block_reduce_store<1, 256>(v, -1, partials + blockIdx.x);
 }
 
 }  // namespace lbm

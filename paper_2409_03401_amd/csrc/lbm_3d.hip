@@ -35,6 +35,11 @@ void launch_sum6(const double* partials, int nparts, double* out, bool accumulat
         hipLaunchKernelGGL((k_finalize<6, false>), dim3(1), dim3(256), 0, s, partials, nparts, -1, 1.0, out);
 }
 
+void launch_euler(const unsigned char* mask, const EulerGeom& g, double* partials, int nblocks, hipStream_t s) {
+    if (g.d == 3) hipLaunchKernelGGL((k_euler<3>), dim3(nblocks), dim3(256), 0, s, mask, g, partials);
+    else hipLaunchKernelGGL((k_euler<2>), dim3(nblocks), dim3(256), 0, s, mask, g, partials);
+}
+
 void launch_zero(double* p, long long n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL((k_zero_f64<256>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, p, n);
 }

@@ -28,6 +28,9 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr size_t kAlign = 256;
+// aux area: kAuxHead doubles of scalars (0: buoyancy reference <phi>, 8..: the
+// diagnostics), then the per-work-group partial sums
+constexpr int kAuxHead = 32;
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -43,6 +46,7 @@ struct Layout {
     dim3 grid;        // 1D: one work-group per tile
     long long nparts;     // work-groups of the fused kernel
     size_t aux_bytes;
+    size_t mask_off;  // diagnostics mask (1 byte per node) after the aux area
     size_t state_bytes;
     // adjoint workspace: two FP32 lambda copies, kAuxRows FP32 rows, theta partials of
     // the adjoint kernels (6 per 256-node work-group)
@@ -146,10 +150,12 @@ int check_config(const lbm_config* c, Layout* L) {
     L->tiles[0] = int(gx); L->tiles[1] = int(gy); L->tiles[2] = int(gz);
     L->grid = dim3(unsigned(gx * gy * gz));
     L->nparts = gx * gy * gz;
-    // aux: 16 doubles of scalars, then per-work-group partials (8 per group)
+    // aux: kAuxHead doubles of scalars, then per-work-group partials (8 per group
+    // of the fused kernel, one per group of the Euler characteristic, <= 1024)
     const long long npart_doubles = std::max<long long>(8 * L->nparts, 1024);
-    L->aux_bytes = round_up(sizeof(double) * (16 + npart_doubles));
-    L->state_bytes = 2 * L->copy_bytes + L->aux_bytes;
+    L->aux_bytes = round_up(sizeof(double) * (kAuxHead + npart_doubles));
+    L->mask_off = 2 * L->copy_bytes + L->aux_bytes;
+    L->state_bytes = L->mask_off + round_up((size_t)nodes);
     L->adj_stride = round_up((size_t)nodes * 4);
     L->aux_stride_elems = round_up((size_t)nodes * 4) / 4;
     L->adj_parts = (nodes + 255) / 256;
@@ -166,6 +172,7 @@ struct lbm_handle {
     const KernelSet* ks;
     char* copy[2];
     double* aux;
+    unsigned char* mask;
     int cur;
     int64_t steps;
     int adj_cur;   // adjoint copy holding the current lambda (in the caller's workspace)
@@ -235,7 +242,7 @@ void fill_params(lbm_handle* h) {
     kp.stride_m = L.stride_m;
     kp.stride_r = L.stride_r;
     kp.phi_ref = h->aux;
-    kp.partials = h->aux + 16;
+    kp.partials = h->aux + kAuxHead;
 }
 
 int check_handle(const lbm_handle* h) {
@@ -291,6 +298,7 @@ int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const doubl
     h->copy[0] = static_cast<char*>(state);
     h->copy[1] = static_cast<char*>(state) + L.copy_bytes;
     h->aux = reinterpret_cast<double*>(static_cast<char*>(state) + 2 * L.copy_bytes);
+    h->mask = reinterpret_cast<unsigned char*>(static_cast<char*>(state) + L.mask_off);
     h->cur = 0;
     h->steps = 0;
     h->adj_cur = 0;
@@ -298,13 +306,13 @@ int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const doubl
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     auto bail = [&](int r) { delete h; return r; };
-    if (hipMemsetAsync(h->aux, 0, 16 * sizeof(double), s) != hipSuccess)
+    if (hipMemsetAsync(h->aux, 0, kAuxHead * sizeof(double), s) != hipSuccess)
         return bail(fail(LBM_EHIP, "hipMemsetAsync of the aux area failed"));
     if (cfg->gravity_mean_subtract) {
         // <phi_0> for the buoyancy reference of the first step
         const int nb = int(std::min<long long>(1024, (L.nodes + 255) / 256));
-        launch_sum_partials(phi0, L.nodes, h->aux + 16, nb, s);
-        launch_finalize(h->aux + 16, nb, 1, -1, 1.0 / double(L.nodes), h->aux, s);
+        launch_sum_partials(phi0, L.nodes, h->aux + kAuxHead, nb, s);
+        launch_finalize(h->aux + kAuxHead, nb, 1, -1, 1.0 / double(L.nodes), h->aux, s);
         if (int r = launched("phi_0 mean")) return bail(r);
     }
     KParams kp = h->base;
@@ -328,7 +336,7 @@ int lbm_step(lbm_handle* h, int64_t nsteps, void* stream) {
         for (int a = 0; a < 3; ++a)
             if (walls[a]) h->ks->walls(kp[h->cur], a, s);
         if (h->cfg.gravity_mean_subtract)
-            launch_finalize(h->aux + 16, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), h->aux, s);
+            launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), h->aux, s);
         if (int r = launched("step kernel")) return r;
         h->cur ^= 1;
         h->steps += 1;
@@ -366,17 +374,67 @@ int lbm_moments(lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtyp
     return LBM_OK;
 }
 
+namespace {
+
+EulerGeom euler_geometry(const lbm_handle* h) {
+    const Layout& L = h->L;
+    const KParams& b = h->base;
+    EulerGeom g{};
+    const long long sx = 1, sy = L.NX, sz = (long long)L.NX * L.NY;
+    auto add = [&](int n, int wall, long long stride) {
+        g.n[g.d] = n; g.wall[g.d] = wall; g.stride[g.d] = stride; ++g.d;
+    };
+    add(L.NX, b.wall_x, sx);
+    if (L.dim == 2) {
+        add(L.NZ, b.wall_z, sz);  // user y
+    } else {
+        add(L.NY, b.wall_y, sy);
+        if (L.NZ > 1) add(L.NZ, b.wall_z, sz);
+    }
+    g.nanchors = 1;
+    for (int a = 0; a < g.d; ++a) g.nanchors *= g.n[a] + g.wall[a];
+    return g;
+}
+
+}  // namespace
+
 int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream) {
     if (int r = check_handle(h)) return r;
     if (!host_out) return fail(LBM_EINVAL, "host_out is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     KParams kp = h->base;
     set_slots(h, kp, h->copy[h->cur], nullptr);
+    kp.mask_out = h->mask;
     h->ks->fused(MODE_DIAG, h->L.grid, kp, s);
-    launch_finalize(h->aux + 16, int(h->L.nparts), 8, 4, 1.0, h->aux + 8, s);
+    launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 8, 4, 1.0, h->aux + 8, s);
+    // droplet count: Euler characteristic of the cells with phi >= 1/2, over the
+    // axes of the run (2D runs: user x and y; 3D runs with nz = 1 count as 2D)
+    const EulerGeom g = euler_geometry(h);
+    const int nb = int(std::min<long long>(1024, (g.nanchors + 255) / 256));
+    launch_euler(h->mask, g, h->aux + kAuxHead, nb, s);
+    launch_finalize(h->aux + kAuxHead, nb, 1, -1, 1.0, h->aux + 8 + LBM_D_DROPLETS, s);
     if (int r = launched("diagnostics kernels")) return r;
-    LBM_HIP(hipMemcpyAsync(host_out, h->aux + 8, LBM_NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
+    LBM_HIP(hipMemcpyAsync(host_out, h->aux + 8, LBM_D_MEAN_RADIUS * sizeof(double), hipMemcpyDeviceToHost, s));
     LBM_HIP(hipStreamSynchronize(s));
+    // mean radius from the interface integral I (Eq. Rmoy_2D, I = 2 pi N <R>; in 3D
+    // spheres: I = 4 pi N <R>^2)
+    const double I = host_out[LBM_D_INTERFACE], N = host_out[LBM_D_DROPLETS];
+    const double pi = 3.14159265358979323846;
+    host_out[LBM_D_MEAN_RADIUS] = N <= 0 ? 0.0 : (g.d == 2 ? I / (2 * pi * N) : std::sqrt(I / (4 * pi * N)));
+    return LBM_OK;
+}
+
+int lbm_run_series(lbm_handle* h, int64_t nsteps, int64_t every, double* host_out, void* stream) {
+    if (int r = check_handle(h)) return r;
+    if (!host_out) return fail(LBM_EINVAL, "host_out is NULL");
+    if (every < 1 || nsteps < 0 || nsteps % every != 0)
+        return fail(LBM_EINVAL, "nsteps must be a non-negative multiple of every >= 1");
+    const int64_t rows = nsteps / every + 1;
+    for (int64_t i = 0; i < rows; ++i) {
+        if (i > 0)
+            if (int r = lbm_step(h, every, stream)) return r;
+        if (int r = lbm_diagnostics(h, host_out + i * LBM_NDIAG, stream)) return r;
+    }
     return LBM_OK;
 }
 
@@ -443,7 +501,7 @@ int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, 
     for (int a = 0; a < 3; ++a)
         if (walls[a]) h->ks->walls(kp, a, s);
     if (h->cfg.gravity_mean_subtract)
-        launch_finalize(h->aux + 16, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
+        launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
     return launched("step_external kernels");
 }
 

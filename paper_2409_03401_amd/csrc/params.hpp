@@ -68,6 +68,8 @@ struct KParams {
     // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame)
     void* mout[kNumMom];
     int mout_f32;
+    // MODE_DIAG: 1 where phi >= 1/2, else 0, one byte per node (kernel frame)
+    unsigned char* mask_out;
     // adjoint kernels.  The adjoint of the arriving
     // population X_s(x) is lambda_s(x) plus, for a scalar population of field F
     // (g, h^A, h^B), the field-wide term c_F(x) (aux rows 7..9).  lambda is FP32
@@ -86,5 +88,17 @@ struct KParams {
 
 constexpr int kAuxRows = 10;
 constexpr int kAuxC = 7;  // first row of c_F
+
+// Euler characteristic of the closed cells of a node mask (droplet count of
+// Section 4.2.2).  Only the d active axes of the run are listed: axis i has n[i]
+// cells, mask stride stride[i], wall[i] != 0 when it ends at walls.  An anchor
+// j_i in [0, n[i] + wall[i]) stands for the vertex position between cells j_i - 1
+// and j_i and for cell j_i (when j_i < n[i]); nanchors = prod(n[i] + wall[i]).
+struct EulerGeom {
+    int d;
+    int n[3], wall[3];
+    long long stride[3];
+    long long nanchors;
+};
 
 }  // namespace lbm

@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass, field, replace
 from typing import Dict, Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +27,7 @@ LBM_FP64, LBM_FP32, LBM_FP32_FP16STORE, LBM_FP32_BF16STORE = 0, 1, 2, 3
 LBM_OUT_F64, LBM_OUT_F32 = 0, 1
 MOMENTS = ("phi", "cA", "cB", "muA", "muB", "p", "ux", "uy", "uz")
 DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interface_measure",
-               "free_energy", "nan_count")
+               "free_energy", "nan_count", "droplets", "mean_radius")
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP32_FP16STORE, "bf16": LBM_FP32_BF16STORE}
 _FLUID = {None: LBM_NONE, "none": LBM_NONE, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
 _SCALAR = {"D2Q5": LBM_D2Q5, "D3Q7": LBM_D3Q7}
@@ -68,6 +69,8 @@ _SIGS = {
     "lbm_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                                    ctypes.c_int32, ctypes.c_void_p]),
     "lbm_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "lbm_run_series": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "lbm_get_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_set_populations": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -270,7 +273,27 @@ class Simulation:
     def diagnostics(self, stream=None) -> Dict[str, float]:
         out = (ctypes.c_double * len(DIAGNOSTICS))()
         _check(lib().lbm_diagnostics(self._h, out, _stream_ptr(stream)))
-        return dict(zip(DIAGNOSTICS, list(out)))
+        d = dict(zip(DIAGNOSTICS, list(out)))
+        for k in ("nan_count", "droplets"):  # integer counts (exact in FP64)
+            d[k] = int(d[k])
+        return d
+
+    def run_series(self, steps: int, every: int, stream=None) -> Dict[str, np.ndarray]:
+        """Advance `steps` steps recording the diagnostics every `every` steps (and of
+        the starting state): arrays of length steps // every + 1 per diagnostic, plus
+        "step" (time steps since init)."""
+        if every < 1 or steps < 0 or steps % every:
+            raise ValueError("steps must be a non-negative multiple of every >= 1")
+        rows = steps // every + 1
+        out = (ctypes.c_double * (rows * len(DIAGNOSTICS)))()
+        start = self.step_count
+        _check(lib().lbm_run_series(self._h, int(steps), int(every), out, _stream_ptr(stream)))
+        a = np.frombuffer(out, dtype=np.float64).reshape(rows, len(DIAGNOSTICS)).copy()
+        d = {k: a[:, i] for i, k in enumerate(DIAGNOSTICS)}
+        for k in ("nan_count", "droplets"):
+            d[k] = d[k].astype(np.int64)
+        d["step"] = start + every * np.arange(rows, dtype=np.int64)
+        return d
 
     def populations(self, stream=None) -> torch.Tensor:
         """[slot][z][y][x] FP64 decoded populations: f_0.., g_0.., hA_0.., hB_0.."""

@@ -134,9 +134,10 @@ def test_parity_fp64(name):
     assert err_p <= 1e-12, err_p
     for k in MOMENT_NAMES:
         assert max_abs(mom[k], ora_m[k]) <= 1e-12 * max(1.0, _scale(ora_m, k)), k
-    for k in ("sum_cA", "sum_cB", "sum_phi", "interface_measure", "free_energy"):
+    for k in ("sum_cA", "sum_cB", "sum_phi", "interface_measure", "free_energy", "mean_radius"):
         assert abs(diag[k] - ora_d[k]) <= 1e-11 * max(1.0, abs(ora_d[k])), k
     assert diag["nan_count"] == 0
+    assert diag["droplets"] == ora_d["droplets"]
 
 
 @pytest.mark.parametrize("name", FP32_CASES)
