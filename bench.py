@@ -31,6 +31,8 @@ WORKLOADS = {
     "spinodal_3d_512_bf16": dict(kind="spinodal_3d", n=512, precision="bf16"),
     "ostwald_2d_1024": dict(kind="ostwald_2d", n=1024, precision="fp32"),
     "single_drop_2d_512": dict(kind="single_drop_2d", n=512, precision="fp32"),
+    # the paper's own discretisation and initial condition (D2Q9 for every equation)
+    "ostwald_paper_2d_4096": dict(kind="ostwald_paper_2d", n=4096, precision="fp32"),
 }
 
 
@@ -58,6 +60,8 @@ def build_workload(name):
         return inputs.ostwald_2d(n=spec["n"], precision=spec["precision"])
     if kind == "single_drop_2d":
         return inputs.single_drop_2d(n=spec["n"], precision=spec["precision"])
+    if kind == "ostwald_paper_2d":
+        return inputs.ostwald_paper_2d(n=spec["n"], precision=spec["precision"])
     raise KeyError(name)
 
 
@@ -66,7 +70,7 @@ def time_gpu(w, steps, warmup):
     from paper_2409_03401_amd.lbm import LBMConfig, Simulation
 
     cfg = LBMConfig(**w.params, precision=w.precision)
-    sim = Simulation(cfg, w.phi0, w.muA0, w.muB0)
+    sim = Simulation(cfg, w.phi0, w.muA0, w.muB0, c0=w.c0)
     stream = torch.cuda.current_stream()
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -224,7 +228,7 @@ def series_run(name, steps, every):
     from paper_2409_03401_amd.lbm import LBMConfig, Simulation
     w = build_workload(name)
     cfg = LBMConfig(**w.params, precision=w.precision)
-    sim = Simulation(cfg, w.phi0, w.muA0, w.muB0)
+    sim = Simulation(cfg, w.phi0, w.muA0, w.muB0, c0=w.c0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     d = sim.run_series(steps, every)

@@ -33,9 +33,9 @@ extern "C" {
 
 /* ---- configuration values --------------------------------------------------- */
 #define LBM_NONE 0            /* no flow: u = 0, no f populations                  */
-#define LBM_D2Q9 9            /* fluid lattices, Tables tab:D2Q9 / tab:D3Q19       */
-#define LBM_D3Q19 19
-#define LBM_D2Q5 5            /* scalar lattices for phi, c^A, c^B                 */
+#define LBM_D2Q9 9            /* fluid lattices, Tables tab:D2Q9 / tab:D3Q19; also */
+#define LBM_D3Q19 19          /* the paper's scalar lattices (FP64 / FP32 only)    */
+#define LBM_D2Q5 5            /* reduced scalar lattices for phi, c^A, c^B         */
 #define LBM_D3Q7 7
 
 #define LBM_PERIODIC 0
@@ -90,7 +90,7 @@ extern "C" {
 typedef struct lbm_config {
     int32_t nx, ny, nz;        /* nz = 1 for 2D                                     */
     int32_t fluid;             /* LBM_NONE, LBM_D2Q9 (2D) or LBM_D3Q19 (3D)         */
-    int32_t scalar;            /* LBM_D2Q5 (2D) or LBM_D3Q7 (3D)                    */
+    int32_t scalar;            /* LBM_D2Q5 / LBM_D2Q9 (2D), LBM_D3Q7 / LBM_D3Q19 (3D) */
     int32_t bc[3];             /* per axis x, y, z: LBM_PERIODIC or LBM_WALLS       */
     int32_t precision;         /* LBM_FP64 ... LBM_FP32_BF16STORE                   */
     int32_t gravity_mean_subtract; /* 1: buoyancy uses phi - <phi> of the previous
@@ -128,6 +128,16 @@ int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes);
 int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes,
              const double* phi0, const double* muA0, const double* muB0,
              void* stream, lbm_handle** out);
+
+/* As lbm_init, but with the compositions given instead of derived from the
+ * closure: the device fields cA0, cB0 ([node], FP64) set the zeroth moments of
+ * h^A, h^B while muA0, muB0 enter the equilibria and the source S.  This is the
+ * initial condition of Section 4.2.1 (Eq. Compos_Init: c stepped at phi = 1/2,
+ * mu = 0 everywhere), which is not in equilibrium with the closure.  NULL cA0 or
+ * cB0: LBM_EINVAL. */
+int lbm_init_composition(const lbm_config* cfg, void* state, size_t state_bytes,
+                         const double* phi0, const double* cA0, const double* cB0,
+                         const double* muA0, const double* muB0, void* stream, lbm_handle** out);
 
 /* Advance nsteps >= 0 time steps (Section 3: moments, forces, BGK collision of
  * f, g, h^A, h^B, streaming with periodic or bounce-back boundaries). */
@@ -179,8 +189,9 @@ int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
  * field.  The adjoint of a state is dL/dX_k(x) for its arriving populations
  * (Section 3); it lives in the caller's device workspace `work` of
  * lbm_adjoint_bytes (FP32 adjoint populations, scratch rows and FP64 parameter
- * partials).  Supported for LBM_FP32 and LBM_FP64 storage without
- * gravity_mean_subtract; other configurations return LBM_EUNSUPPORTED.
+ * partials).  Supported for LBM_FP32 and LBM_FP64 storage with the D2Q5 / D3Q7
+ * scalar lattices, without gravity_mean_subtract; other configurations return
+ * LBM_EUNSUPPORTED.
  * Calls that share one workspace must not overlap.
  *
  *   lbm_adjoint_seed  : start from dL/dphi_T (FP64 device [node]) at the final

@@ -49,7 +49,7 @@ class Params:
     ny: int
     nz: int = 1
     fluid: Optional[str] = None          # None, "D2Q9" or "D3Q19"
-    scalar: str = "D2Q5"                 # "D2Q5" or "D3Q7"
+    scalar: str = "D2Q5"                 # "D2Q5", "D3Q7" or the paper's "D2Q9", "D3Q19"
     bc: Tuple[str, str, str] = ("periodic", "periodic", "periodic")   # per axis x, y, z
     W: float = 4.0
     lam: float = 1.0
@@ -281,16 +281,21 @@ def moments(st, prm):
 # ----------------------------------------------------------------------------------------
 # init and step
 
-def init(phi0, muA0, muB0, prm, phi_ref=None):
+def init(phi0, muA0, muB0, prm, phi_ref=None, c0=None):
     """Populations at rest from (phi_0, mu_0), with u = 0 and p_h = 0 (Section 4.2.1):
     c from the closure Eq. species_closure, every population set to its equilibrium
     including the -G_k/2 and -F_k/2 shifts, so that the moments of Eqs. Moment0_Phi
-    and Velocity give back phi_0 + O(S) and u = 0."""
+    and Velocity give back phi_0 + O(S) and u = 0.  c0 = (c^A, c^B) gives the
+    compositions instead of the closure (the paper's own initial condition, Eq.
+    Compos_Init with mu = 0, is not in equilibrium with the closure)."""
     phi0 = np.asarray(phi0)
     shape = prm.shape
     phi0 = phi0.reshape(shape)
     mu0 = (np.asarray(muA0).reshape(shape), np.asarray(muB0).reshape(shape))
-    c = model.closure_c(mu0, phi0, prm.c_eq)
+    if c0 is None:
+        c = model.closure_c(mu0, phi0, prm.c_eq)
+    else:
+        c = (np.asarray(c0[0]).reshape(shape), np.asarray(c0[1]).reshape(shape))
     S0 = model.source_phi(phi0, mu0, prm)
     zero = np.zeros_like(phi0 * S0)
     u0 = [zero, zero, zero]

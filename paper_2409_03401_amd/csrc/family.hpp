@@ -1,5 +1,6 @@
 // Instantiation helper: the launchers of one (scalar lattice, fluid lattice)
-// family for the four storage precisions.
+// family for the four storage precisions (FP64 and FP32 only for the paper's
+// scalar lattices, family_fp_only).
 #pragma once
 
 #include "dispatch.hpp"
@@ -7,7 +8,7 @@
 
 namespace lbm {
 
-template <class SL, class FL, int PREC, int TX, int TY>
+template <class SL, class FL, int PREC, int TX, int TY, bool ADJ = true>
 struct Family {
     static void fused(int mode, dim3 grid, const KParams& kp, hipStream_t s) {
         const dim3 block(TX, TY);
@@ -46,30 +47,36 @@ struct Family {
         const dim3 grid(unsigned((2 * face + 255) / 256));
         hipLaunchKernelGGL((k_walls<SL, FL, PREC>), grid, dim3(256), 0, s, kp, axis);
     }
-    static constexpr bool kAdj = PREC == P32 || PREC == P64;
+    static constexpr bool kAdj = ADJ && (PREC == P32 || PREC == P64);
     static void adj_step(const KParams& kp, long long nodes, const void* phi, hipStream_t s) {
         if constexpr (kAdj)
             hipLaunchKernelGGL((k_adj_node<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
                                nodes, static_cast<const typename Stor<PREC>::C*>(phi));
     }
     static void adj_seed(const KParams& kp, long long nodes, const double* dL_dphi, hipStream_t s) {
-        hipLaunchKernelGGL((k_adj_seed<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
-                           nodes, dL_dphi);
+        if constexpr (kAdj)
+            hipLaunchKernelGGL((k_adj_seed<SL, FL, PREC>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
+                               kp, nodes, dL_dphi);
     }
     static void adj_gather(const KParams& kp, long long nodes, int mode, double* grad_phi0, hipStream_t s) {
         const dim3 grid(unsigned((nodes + 255) / 256));
-        if (mode == 0) hipLaunchKernelGGL((k_adj_gather<SL, FL, 0>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
-        else hipLaunchKernelGGL((k_adj_gather<SL, FL, 1>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
+        if constexpr (kAdj) {
+            if (mode == 0) hipLaunchKernelGGL((k_adj_gather<SL, FL, 0>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
+            else hipLaunchKernelGGL((k_adj_gather<SL, FL, 1>), grid, dim3(256), 0, s, kp, nodes, grad_phi0);
+        }
     }
     static void adj_init_local(const KParams& kp, long long nodes, const double* phi0, const double* muA0,
                                const double* muB0, hipStream_t s) {
-        hipLaunchKernelGGL((k_adj_init_local<SL, FL>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s, kp,
-                           nodes, phi0, muA0, muB0);
+        if constexpr (kAdj)
+            hipLaunchKernelGGL((k_adj_init_local<SL, FL>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
+                               kp, nodes, phi0, muA0, muB0);
     }
     static void adj_copy(const KParams& kp, int nslots, long long nodes, double* buf, bool set_, hipStream_t s) {
         const dim3 grid(unsigned((nodes + 255) / 256), nslots);
-        if (set_) hipLaunchKernelGGL((k_adj_copy<SL, FL, true>), grid, dim3(256), 0, s, kp, nodes, buf);
-        else hipLaunchKernelGGL((k_adj_copy<SL, FL, false>), grid, dim3(256), 0, s, kp, nodes, buf);
+        if constexpr (kAdj) {
+            if (set_) hipLaunchKernelGGL((k_adj_copy<SL, FL, true>), grid, dim3(256), 0, s, kp, nodes, buf);
+            else hipLaunchKernelGGL((k_adj_copy<SL, FL, false>), grid, dim3(256), 0, s, kp, nodes, buf);
+        }
     }
     static constexpr KernelSet set{&fused, &init, &get_pops, &set_pops, &walls,
                                    kAdj ? &adj_step : nullptr, kAdj ? &adj_seed : nullptr,
@@ -84,6 +91,16 @@ const KernelSet* family_for_prec(int prec) {
         case P32: return &Family<SL, FL, P32, TX, TY>::set;
         case P16: return &Family<SL, FL, P16, TX, TY>::set;
         case PB16: return &Family<SL, FL, PB16, TX, TY>::set;
+        default: return nullptr;
+    }
+}
+
+// the paper's scalar lattices: FP64 and FP32 storage, no adjoint
+template <class SL, class FL, int TX, int TY>
+const KernelSet* family_fp_only(int prec) {
+    switch (prec) {
+        case P64: return &Family<SL, FL, P64, TX, TY, false>::set;
+        case P32: return &Family<SL, FL, P32, TX, TY, false>::set;
         default: return nullptr;
     }
 }

@@ -315,12 +315,15 @@ k_lbm(const KParams P) {
     constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
     constexpr C inv_cs2s = C(1.0 / SL::cs2);
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
+    // the private LDS ring of scalar populations, unless it would not leave room for
+    // a second work-group per compute unit (the paper's D3Q19 scalar lattice)
+    constexpr bool LDS_POPS = LBM_LDS_POPS && 2 * 3 * QS * NT * sizeof(C) <= 96 * 1024;
 
     __shared__ C sphi[NSLOT][LY][LX];
     // this thread's own scalar populations of the current and the next plane
     // (thread-private ring of two planes, [plane][slot][thread], no barriers needed)
-    __shared__ C spop[(STENCIL && LBM_LDS_POPS) ? 2 : 1][(STENCIL && LBM_LDS_POPS) ? 3 * QS : 1]
-                     [(STENCIL && LBM_LDS_POPS) ? NT : 1];
+    __shared__ C spop[(STENCIL && LDS_POPS) ? 2 : 1][(STENCIL && LDS_POPS) ? 3 * QS : 1]
+                     [(STENCIL && LDS_POPS) ? NT : 1];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
@@ -435,7 +438,7 @@ k_lbm(const KParams P) {
                           __attribute__((always_inline)) {
         const int zm = map_coord(zz, P.nz, P.wall_z);
         if (active) {
-            if constexpr (LBM_LDS_POPS) {
+            if constexpr (LDS_POPS) {
                 C gg[QS], aa[QS], bb[QS];
                 load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), gg, aa, bb, ps, cA, cB);
 #pragma unroll
@@ -493,7 +496,7 @@ k_lbm(const KParams P) {
         if (z0 < z1) {
             fill_plane(z0 - 1, 0, 1, n_ps, n_cA, n_cB);  // ring only; own entries overwritten next
             fill_plane(z0, 1, 0, c_ps, c_cA, c_cB);
-            if constexpr (!LBM_LDS_POPS) {
+            if constexpr (!LDS_POPS) {
 #pragma unroll
                 for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
             }
@@ -527,7 +530,7 @@ k_lbm(const KParams P) {
             sp = (z - z0 + 2) % 3;
             fill_plane(z + 1, sp, (z - z0 + 1) & 1, n_ps, n_cA, n_cB);
             __syncthreads();
-            if constexpr (LBM_LDS_POPS) {
+            if constexpr (LDS_POPS) {
                 if (active) {
                     const int pb = (z - z0) & 1;
 #pragma unroll
@@ -729,7 +732,7 @@ k_lbm(const KParams P) {
         }
         if constexpr (STENCIL) {
             // the next plane becomes the current one
-            if constexpr (!LBM_LDS_POPS) {
+            if constexpr (!LDS_POPS) {
 #pragma unroll
                 for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
             }
@@ -859,8 +862,10 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
     const Nbr nb = neighbours(x, y, z, P);
     const double phi = phi0[idx], muA = muA0[idx], muB = muB0[idx];
     const double pp = interp_p(phi);
-    const double cA = muA + P.c0A + pp * (P.c1A - P.c0A);  // Eq. species_closure
-    const double cB = muB + P.c0B + pp * (P.c1B - P.c0B);
+    // Eq. species_closure, unless the compositions are given (initial condition of
+    // Section 4.2.1: c stepped at phi = 1/2 with mu = 0)
+    const double cA = P.init_c[0] ? P.init_c[0][idx] : muA + P.c0A + pp * (P.c1A - P.c0A);
+    const double cB = P.init_c[1] ? P.init_c[1][idx] : muB + P.c0B + pp * (P.c1B - P.c0B);
     const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
     const double S0 = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
 

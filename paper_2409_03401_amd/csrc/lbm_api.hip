@@ -57,18 +57,19 @@ struct Layout {
 int check_config(const lbm_config* c, Layout* L) {
     if (!c) return fail(LBM_EINVAL, "config is NULL");
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(LBM_EINVAL, "grid sizes must be >= 1");
-    if (c->scalar == LBM_D2Q5) {
-        if (c->nz != 1) return fail(LBM_EINVAL, "D2Q5 needs nz = 1");
+    if (c->scalar == LBM_D2Q5 || c->scalar == LBM_D2Q9) {
+        if (c->nz != 1) return fail(LBM_EINVAL, "2D scalar lattices need nz = 1");
         if (c->fluid != LBM_NONE && c->fluid != LBM_D2Q9)
             return fail(LBM_EUNSUPPORTED, "2D runs take LBM_NONE or LBM_D2Q9 for the fluid");
         L->dim = 2;
-    } else if (c->scalar == LBM_D3Q7) {
+    } else if (c->scalar == LBM_D3Q7 || c->scalar == LBM_D3Q19) {
         if (c->fluid != LBM_NONE && c->fluid != LBM_D3Q19)
             return fail(LBM_EUNSUPPORTED, "3D runs take LBM_NONE or LBM_D3Q19 for the fluid");
         L->dim = 3;
     } else {
-        return fail(LBM_EUNSUPPORTED, "scalar lattice must be LBM_D2Q5 or LBM_D3Q7");
+        return fail(LBM_EUNSUPPORTED, "scalar lattice must be LBM_D2Q5, LBM_D2Q9, LBM_D3Q7 or LBM_D3Q19");
     }
+    const bool paper_scalar = c->scalar == LBM_D2Q9 || c->scalar == LBM_D3Q19;
     if (c->precision < LBM_FP64 || c->precision > LBM_FP32_BF16STORE)
         return fail(LBM_EUNSUPPORTED, "unknown precision");
     for (int a = 0; a < 3; ++a)
@@ -134,7 +135,12 @@ int check_config(const lbm_config* c, Layout* L) {
     // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
     int want_tx = 0, want_ty = 0;
     if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
-    L->ks = L->dim == 2 ? kernels_2d(L->qf, L->prec, want_tx) : kernels_3d(L->qf, L->prec, want_tx, want_ty);
+    if (paper_scalar) {
+        L->ks = L->dim == 2 ? kernels_paper_2d(L->qf, L->prec) : kernels_paper_3d(L->qf, L->prec);
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "D2Q9 / D3Q19 scalar lattices run with FP64 or FP32 storage");
+    } else {
+        L->ks = L->dim == 2 ? kernels_2d(L->qf, L->prec, want_tx) : kernels_3d(L->qf, L->prec, want_tx, want_ty);
+    }
     if (!L->ks) return fail(LBM_EUNSUPPORTED, "no kernel for this lattice / precision");
     L->tx = L->ks->tx;
     L->ty = L->ks->ty;
@@ -207,7 +213,8 @@ void fill_params(lbm_handle* h) {
     kp.mphi_w2 = c.M_phi / (c.W * c.W);
     kp.c0A = c.c_eq[0][0]; kp.c0B = c.c_eq[0][1];
     kp.c1A = c.c_eq[1][0]; kp.c1B = c.c_eq[1][1];
-    const double cs2s = L.qs == 5 ? D2Q5K::cs2 : D3Q7K::cs2;
+    // c_s^2 of the scalar lattice
+    const double cs2s = L.qs == 5 ? D2Q5K::cs2 : L.qs == 7 ? D3Q7K::cs2 : L.qs == 9 ? D2Q9K::cs2 : D3Q19K::cs2;
     kp.omega_g = 1.0 / (c.M_phi / cs2s + 0.5);
     kp.MA0 = c.M_A[0]; kp.MA1 = c.M_A[1]; kp.MB0 = c.M_B[0]; kp.MB1 = c.M_B[1];
     kp.nu0 = c.nu[0]; kp.nu1 = c.nu[1];
@@ -278,13 +285,17 @@ int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes) {
     return LBM_OK;
 }
 
-int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
-             const double* muA0, const double* muB0, void* stream, lbm_handle** out) {
+namespace {
+
+int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
+              const double* cA0, const double* cB0, const double* muA0, const double* muB0, void* stream,
+              lbm_handle** out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     Layout L;
     if (int r = check_config(cfg, &L)) return r;
     if (!state || !phi0 || !muA0 || !muB0) return fail(LBM_EINVAL, "NULL device pointer");
+    if ((cA0 == nullptr) != (cB0 == nullptr)) return fail(LBM_EINVAL, "give both compositions or neither");
     if ((reinterpret_cast<uintptr_t>(state) % kAlign) != 0)
         return fail(LBM_EINVAL, "state must be 256-byte aligned");
     if (state_bytes < L.state_bytes)
@@ -317,10 +328,29 @@ int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const doubl
     }
     KParams kp = h->base;
     set_slots(h, kp, nullptr, h->copy[0]);
+    kp.init_c[0] = cA0;
+    kp.init_c[1] = cB0;
     ks->init(kp, phi0, muA0, muB0, s);
     if (int r = launched("init kernel")) return bail(r);
     *out = h;
     return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
+             const double* muA0, const double* muB0, void* stream, lbm_handle** out) {
+    return init_impl(cfg, state, state_bytes, phi0, nullptr, nullptr, muA0, muB0, stream, out);
+}
+
+int lbm_init_composition(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
+                         const double* cA0, const double* cB0, const double* muA0, const double* muB0,
+                         void* stream, lbm_handle** out) {
+    if (!cA0 || !cB0) {
+        if (out) *out = nullptr;
+        return fail(LBM_EINVAL, "NULL device pointer");
+    }
+    return init_impl(cfg, state, state_bytes, phi0, cA0, cB0, muA0, muB0, stream, out);
 }
 
 int lbm_step(lbm_handle* h, int64_t nsteps, void* stream) {
@@ -523,7 +553,8 @@ namespace {
 int adjoint_ready(const lbm_handle* h, const void* work) {
     if (int r = check_handle(h)) return r;
     if (!work) return fail(LBM_EINVAL, "work is NULL");
-    if (!h->ks->adj_step) return fail(LBM_EUNSUPPORTED, "the adjoint runs on FP32 or FP64 storage");
+    if (!h->ks->adj_step)
+        return fail(LBM_EUNSUPPORTED, "the adjoint runs on FP32 or FP64 storage with D2Q5 / D3Q7 scalars");
     if (h->cfg.gravity_mean_subtract)
         return fail(LBM_EUNSUPPORTED, "the adjoint does not support gravity_mean_subtract");
     return LBM_OK;

@@ -9,7 +9,7 @@
 
 namespace lbm {
 
-constexpr int kMaxSlots = 19 + 3 * 7;  // D3Q19 + 3 x D3Q7
+constexpr int kMaxSlots = 19 + 3 * 19;  // D3Q19 fluid + 3 x D3Q19 scalars
 constexpr int kNumMom = 9;
 constexpr int kNumDiag = 8;
 
@@ -70,6 +70,8 @@ struct KParams {
     int mout_f32;
     // MODE_DIAG: 1 where phi >= 1/2, else 0, one byte per node (kernel frame)
     unsigned char* mask_out;
+    // initialisation: given compositions c^A, c^B ([node]) instead of the closure, or null
+    const double* init_c[2];
     // adjoint kernels.  The adjoint of the arriving
     // population X_s(x) is lambda_s(x) plus, for a scalar population of field F
     // (g, h^A, h^B), the field-wide term c_F(x) (aux rows 7..9).  lambda is FP32

@@ -3,8 +3,12 @@
 This module only draws initial fields and holds the workload recipes (grid,
 lattices, boundaries, parameters, step counts).  It contains none of the
 method's arithmetic: the compositions, sources and populations are derived from
-(phi_0, mu_0) inside each implementation.  Both the GPU library's callers and
-the oracle-based tests take their inputs from here.
+(phi_0, mu_0) inside each implementation.  The one exception is an input by
+definition: the paper's own initial condition (Section 4.2.1) prescribes the
+compositions directly (Eq. Compos_Init, with mu_0 = 0), and its recipe (droplet
+placement by phase fraction, lever rule, supersaturation offset) lives here.
+Both the GPU library's callers and the oracle-based tests take their inputs
+from here.
 
 Initial phase field: circular / spherical droplets with the equilibrium
 profile of Eq. tanh, phi = (1 + tanh(2 (R - r) / W)) / 2, r the minimum-image
@@ -111,6 +115,67 @@ def droplet_field(shape, drops, W, wall_axes=()):
     return phi
 
 
+# ----------------------------------------------------------------------------------------
+# the paper's initial condition (Section 4.2.1)
+
+def lever_rule_fraction(cg, c0, c1):
+    """Eq. phi_glob_eq: equilibrium phase fraction of the inventory cg on the tie line
+    from c0 (phase 0) to c1 (phase 1)."""
+    return float(np.linalg.norm(np.subtract(c0, cg)) / np.linalg.norm(np.subtract(c0, c1)))
+
+
+def supersaturation_offset(phi_eq, phi_frac):
+    """Eq. Delta-1: delta = (Phi_eq - Phi) / (1 - Phi)."""
+    return (phi_eq - phi_frac) / (1.0 - phi_frac)
+
+
+def stepped_composition(phi, c_eq, cg):
+    """Eq. Compos_Init: c = c_1 where phi >= 1/2, c = (1 - delta) c_0 + delta c_1
+    elsewhere, delta from Eqs. phi_glob_eq and Delta-1.  Readings: Phi is the fraction
+    of nodes with phi >= 1/2, so that the mean composition is cg exactly; the matrix
+    offset is + delta (c_1 - c_0), as in Eq. Compos_Init and the inventory balance
+    (Eq. Init_c0 prints the opposite sign).  Returns (cA, cB) and the recipe values."""
+    phi = np.asarray(phi)
+    c0, c1 = np.asarray(c_eq[0], float), np.asarray(c_eq[1], float)
+    inside = phi >= 0.5
+    frac = float(inside.mean())
+    phi_eq = lever_rule_fraction(cg, c0, c1)
+    delta = supersaturation_offset(phi_eq, frac)
+    matrix = (1.0 - delta) * c0 + delta * c1
+    cA = np.where(inside, c1[0], matrix[0])
+    cB = np.where(inside, c1[1], matrix[1])
+    return (cA, cB), dict(phase_fraction=frac, phi_eq=phi_eq, delta=delta, matrix=tuple(matrix))
+
+
+def place_droplets_by_fraction(shape, s, vmin, vmax, W, rng, max_tries=2_000_000):
+    """Droplet ensemble of Fig. initialization_flowchart: volume (area in 2D) V ~ U[vmin,
+    vmax], centre uniform in the box.  A candidate is discarded when its centre lies
+    within R_max + W/2 of a domain bound or within 2 (R_max + W/2) of an accepted
+    centre, R_max the radius of volume vmax.  Droplets are added until their volumes
+    reach s times the domain volume (reading: the last accepted droplet may pass it).
+    Returns [(centre_xyz, R)]."""
+    nz, ny, nx = shape
+    dims = np.array([nx, ny, nz], float)
+    ndim = 3 if nz > 1 else 2
+    radius = (lambda V: math.sqrt(V / math.pi)) if ndim == 2 else (lambda V: (3.0 * V / (4.0 * math.pi)) ** (1 / 3))
+    clear = radius(vmax) + W / 2
+    target = s * float(np.prod(dims[:ndim]))
+    centres = np.zeros((0, ndim))
+    drops, total, tries = [], 0.0, 0
+    while total < target and tries < max_tries:
+        tries += 1
+        V = rng.uniform(vmin, vmax)
+        c = rng.uniform(0.0, 1.0, ndim) * dims[:ndim]
+        if np.any(c < clear) or np.any(c > dims[:ndim] - clear):
+            continue
+        if len(centres) and np.min(np.sum((centres - c) ** 2, axis=1)) < (2 * clear) ** 2:
+            continue
+        centres = np.vstack([centres, c])
+        drops.append((tuple(c) + (0.0,) * (3 - ndim), radius(V)))
+        total += V
+    return drops
+
+
 @dataclass
 class Workload:
     name: str
@@ -122,6 +187,7 @@ class Workload:
     muB0: np.ndarray
     note: str = ""
     drops: Optional[List] = None
+    c0: Optional[Tuple[np.ndarray, np.ndarray]] = None   # given compositions (paper's initial condition)
 
     @property
     def nodes(self):
@@ -202,3 +268,32 @@ def spinodal_3d(n=512, precision="bf16", rng_index=4):
     phi0 = 0.5 + rng.uniform(-0.05, 0.05, (n, n, n))
     z = np.zeros((n, n, n))
     return Workload(f"spinodal_3d_{n}_{precision}", p, precision, 50000, phi0, z, z.copy())
+
+
+# the paper's 2D ripening run (Table tab:Parameters_Ostwald-Ripening) in lattice units
+OSTWALD_PAPER_DX = 4.882e-4
+OSTWALD_PAPER_DT = 2.5e-8
+
+
+def ostwald_paper_2d(n=4096, precision="fp32", rng_index=5):
+    """E2 of the paper in lattice units, with the paper's discretisation (D2Q9 for every
+    equation) and initial condition (Section 4.2.1).  Mobilities M dt / dx^2 from the
+    table (collision rates 0.8776, 0.8146, 0.7517), W = 3, lambda = 155.95, tie line
+    (0.3, 0.3) - (0.4, 0.4); droplet areas U[S_avg - dS, S_avg + dS] / dx^2 placed to the
+    phase fraction 0.08; compositions stepped at phi = 1/2 for the inventory (0.31, 0.31)
+    with mu_0 = 0.  n = 4096 is the paper's box; smaller n keep dx (a crop)."""
+    k = OSTWALD_PAPER_DT / OSTWALD_PAPER_DX ** 2
+    c_eq = ((0.3, 0.3), (0.4, 0.4))
+    p = _base(n, n, 1, W=3.0, lam=155.95, M_phi=1.2 * k, M_A=(1.0 * k, 1.0 * k), M_B=(0.8 * k, 0.8 * k),
+              c_eq=c_eq, scalar="D2Q9")
+    rng = rng_for(rng_index)
+    a2 = OSTWALD_PAPER_DX ** 2
+    drops = place_droplets_by_fraction((1, n, n), 0.08, (1.02e-4 - 0.957e-4) / a2, (1.02e-4 + 0.957e-4) / a2,
+                                       p["W"], rng)
+    phi0 = droplet_field((1, n, n), drops, p["W"])
+    c0, info = stepped_composition(phi0, c_eq, (0.31, 0.31))
+    z = np.zeros((1, n, n))
+    return Workload(f"ostwald_paper_2d_{n}_{precision}", p, precision, 20000, phi0, z, z.copy(), drops=drops,
+                    c0=c0, note=f"{len(drops)} droplets, phase fraction {info['phase_fraction']:.4f}, "
+                                f"delta {info['delta']:.5f}")
+

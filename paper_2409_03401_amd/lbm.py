@@ -30,7 +30,8 @@ DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interf
                "free_energy", "nan_count", "droplets", "mean_radius")
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP32_FP16STORE, "bf16": LBM_FP32_BF16STORE}
 _FLUID = {None: LBM_NONE, "none": LBM_NONE, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
-_SCALAR = {"D2Q5": LBM_D2Q5, "D3Q7": LBM_D3Q7}
+# D2Q5 / D3Q7: reduced scalar lattices; D2Q9 / D3Q19: the paper's (FP64 / FP32 only)
+_SCALAR = {"D2Q5": LBM_D2Q5, "D3Q7": LBM_D3Q7, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
 _BC = {"periodic": LBM_PERIODIC, "walls": LBM_WALLS}
 _ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ESIZE: "LBM_ESIZE", LBM_EUNSTABLE: "LBM_EUNSTABLE",
              LBM_EUNSUPPORTED: "LBM_EUNSUPPORTED", LBM_EHIP: "LBM_EHIP"}
@@ -65,6 +66,9 @@ _SIGS = {
     "lbm_init": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "lbm_init_composition": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "lbm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "lbm_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                                    ctypes.c_int32, ctypes.c_void_p]),
@@ -217,7 +221,9 @@ def _dev_f64(a, n, device):
 class Simulation:
     """One domain on one GPU: state buffer (torch uint8 tensor) plus the library handle."""
 
-    def __init__(self, cfg: LBMConfig, phi0, muA0, muB0, device="cuda", stream=None):
+    def __init__(self, cfg: LBMConfig, phi0, muA0, muB0, device="cuda", stream=None, c0=None):
+        """c0 = (cA0, cB0) gives the compositions instead of the closure
+        (lbm_init_composition: the initial condition of Section 4.2.1)."""
         if not torch.cuda.is_available():
             raise RuntimeError("liblbm needs a GPU; none is visible")
         L = lib()
@@ -228,10 +234,17 @@ class Simulation:
         self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         n = cfg.nodes
         self._inputs = [_dev_f64(a, n, self.device) for a in (phi0, muA0, muB0)]
+        ptrs = [ctypes.c_void_p(t.data_ptr()) for t in self._inputs]
         h = ctypes.c_void_p()
-        _check(L.lbm_init(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
-                          *[ctypes.c_void_p(t.data_ptr()) for t in self._inputs], _stream_ptr(stream),
-                          ctypes.byref(h)))
+        if c0 is None:
+            _check(L.lbm_init(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
+                              *ptrs, _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            self._c_inputs = [_dev_f64(a, n, self.device) for a in c0]
+            cp = [ctypes.c_void_p(t.data_ptr()) for t in self._c_inputs]
+            _check(L.lbm_init_composition(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
+                                          ptrs[0], cp[0], cp[1], ptrs[1], ptrs[2], _stream_ptr(stream),
+                                          ctypes.byref(h)))
         self._h = h
 
     def close(self):

@@ -64,9 +64,37 @@ def test_state_bytes_layout():
     (dict(gravity_mean_subtract=True), lbm.LBM_EINVAL),   # needs a fluid
     (dict(nx=32768, ny=32768, precision="fp32"), lbm.LBM_EUNSUPPORTED),  # 2^30 nodes x 4 B = 2^32
     (dict(nx=32768, ny=16384, precision="fp64"), lbm.LBM_EUNSUPPORTED),  # 2^29 nodes x 8 B = 2^32
+    (dict(scalar="D2Q9", precision="bf16"), lbm.LBM_EUNSUPPORTED),  # paper's scalar lattices: FP64 / FP32
+    (dict(scalar="D3Q19", nz=4, precision="fp16"), lbm.LBM_EUNSUPPORTED),
+    (dict(scalar="D2Q9", nz=4), lbm.LBM_EINVAL),              # a 2D lattice with nz > 1
+    (dict(scalar="D3Q19", nz=4, fluid="D2Q9"), lbm.LBM_EUNSUPPORTED),
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:
         lbm.state_bytes(_cfg(**kw))
     assert e.value.code == code
     assert lbm.lib().lbm_last_error().decode()
+
+
+def test_paper_scalar_lattices_accepted():
+    """D2Q9 / D3Q19 for phi and the compositions (the paper's discretisation): FP64 and
+    FP32 layouts of Q_f + 3 Q_s slots."""
+    for kw, q in ((dict(scalar="D2Q9"), 27), (dict(scalar="D2Q9", fluid="D2Q9"), 36),
+                  (dict(scalar="D3Q19", nz=5), 57), (dict(scalar="D3Q19", nz=5, fluid="D3Q19"), 76)):
+        for prec in ("fp32", "fp64"):
+            c = _cfg(precision=prec, **kw)
+            per_slot = (c.nodes * (8 if prec == "fp64" else 4) + 255) // 256 * 256
+            assert lbm.state_bytes(c) >= 2 * q * per_slot
+            assert lbm.checkpoint_bytes(c) >= q * per_slot
+
+
+def test_init_composition_rejects_null_compositions():
+    c = _cfg()
+    n = lbm.state_bytes(c)
+    h = ctypes.c_void_p()
+    cfg = c.to_c()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the call fails before any device work
+    r = lbm.lib().lbm_init_composition(ctypes.byref(cfg), fake, n, fake, None, fake, fake, fake, None,
+                                       ctypes.byref(h))
+    assert r == lbm.LBM_EINVAL and not h.value
+

@@ -1,0 +1,171 @@
+"""The paper's own discretisation on the GPU: D2Q9 / D3Q19 for phi and both
+compositions (Section 3), and the paper's initial condition (Section 4.2.1, Eq.
+Compos_Init: c stepped at phi = 1/2 with mu = 0, lbm_init_composition).
+
+Parity with the FP64 oracle on the same seeded inputs, bars as for the reduced
+lattices: FP64 populations within 1e-12, FP32 relative L2 within 1e-5 on phi, c^A,
+c^B.  The full-size ripening box of the paper (4096^2) is checked on sampled nodes
+against exact oracle windows.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from helpers import (MOMENT_NAMES, field_errors, gpu_config, max_abs, oracle_moments, oracle_params,
+                     oracle_populations, rel_l2)
+from oracle import lbm as olbm
+from paper_2409_03401_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _drops(shape, n, rmin, rmax, W, seed, wall_axes=()):
+    rng = np.random.default_rng(seed)
+    drops = inputs.place_droplets(shape, n, rmin, rmax, W, rng, wall_axes=wall_axes)
+    phi = inputs.droplet_field(shape, drops, W, wall_axes=wall_axes)
+    mu = rng.normal(0.0, 1e-3, (2,) + shape)
+    return phi, mu[0], mu[1]
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    """(params, phi0, muA0, muB0, c0 or None, steps) of a small case; sizes ragged."""
+    if name == "2d_noflow_periodic":
+        p = inputs._base(77, 45, 1, W=3.0, scalar="D2Q9")
+        return (p, *_drops((1, 45, 77), 5, 4.0, 8.0, 3.0, 41), None, 40)
+    if name == "2d_flow_walls":
+        p = inputs._base(70, 52, 1, W=4.0, scalar="D2Q9", fluid="D2Q9", bc=("periodic", "walls", "periodic"),
+                         drho=0.5, g=(0.0, -1e-4, 0.0), sigma=1e-3, nu=(0.1, 0.05))
+        return (p, *_drops((1, 52, 70), 3, 5.0, 9.0, 4.0, 42, (1,)), None, 30)
+    if name == "3d_noflow_walls":
+        p = inputs._base(22, 18, 20, W=3.0, scalar="D3Q19", bc=("periodic", "periodic", "walls"))
+        return (p, *_drops((20, 18, 22), 2, 3.0, 5.0, 3.0, 43, (2,)), None, 12)
+    if name == "3d_flow_walls":
+        p = inputs._base(21, 19, 18, W=4.0, scalar="D3Q19", fluid="D3Q19", bc=("walls", "periodic", "walls"),
+                         drho=0.5, g=(0.0, 0.0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
+        return (p, *_drops((18, 19, 21), 1, 4.0, 5.0, 4.0, 44, (0, 2)), None, 10)
+    if name == "2d_paper_initial_condition":
+        w = inputs.ostwald_paper_2d(n=96)
+        z = np.zeros_like(w.phi0)
+        return (w.params, w.phi0, z, z.copy(), w.c0, 40)
+    raise KeyError(name)
+
+
+CASES = ["2d_noflow_periodic", "2d_flow_walls", "3d_noflow_walls", "3d_flow_walls", "2d_paper_initial_condition"]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name):
+    p, phi0, muA0, muB0, c0, steps = case(name)
+    prm = oracle_params(p)
+    st = olbm.run(olbm.init(phi0, muA0, muB0, prm, c0=c0), prm, steps)
+    return oracle_moments(prm, st), oracle_populations(prm, st)
+
+
+def _gpu(name, precision):
+    from paper_2409_03401_amd.lbm import Simulation
+    p, phi0, muA0, muB0, c0, steps = case(name)
+    print(f"[paper lattice] {name} {p['scalar']}/{p['fluid']} shape={phi0.shape} {precision} steps={steps}",
+          flush=True)
+    sim = Simulation(gpu_config(p, precision), phi0, muA0, muB0, c0=c0)
+    sim.step(steps)
+    mom = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+    pops = sim.populations().cpu().numpy()
+    return sim, mom, pops
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_parity_fp64(name):
+    _require_gpu()
+    _, mom, pops = _gpu(name, "fp64")
+    ora_m, ora_p = oracle_case(name)
+    assert pops.shape == ora_p.shape
+    err = max_abs(pops, ora_p)
+    assert err <= 1e-12, err
+    for k in MOMENT_NAMES:
+        assert max_abs(mom[k], ora_m[k]) <= 1e-12 * max(1.0, np.abs(ora_m[k]).max()), k
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_parity_fp32(name):
+    _require_gpu()
+    _, mom, pops = _gpu(name, "fp32")
+    ora_m, ora_p = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("phi", "cA", "cB"):
+        assert errs[k][0] <= 1e-5, (k, errs[k])
+    assert rel_l2(pops, ora_p) <= 1e-5
+
+
+def test_paper_initial_condition_moments():
+    """Right after lbm_init_composition the compositions are the given step field
+    exactly (FP64) and the mean composition is the inventory (0.31, 0.31)."""
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    w = inputs.ostwald_paper_2d(n=256)
+    z = np.zeros_like(w.phi0)
+    sim = Simulation(gpu_config(w.params, "fp64"), w.phi0, z, z.copy(), c0=w.c0)
+    m = sim.moments(("cA", "cB"))
+    assert np.array_equal(m["cA"].cpu().numpy(), w.c0[0])
+    assert np.array_equal(m["cB"].cpu().numpy(), w.c0[1])
+    d = sim.diagnostics()
+    assert abs(d["sum_cA"] / w.nodes - 0.31) < 1e-13
+    assert d["droplets"] == len(w.drops)
+
+
+def test_unsupported_combinations():
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import LBM_EUNSUPPORTED, LBMError, Simulation
+    p, phi0, muA0, muB0, _, _ = case("2d_noflow_periodic")
+    with pytest.raises(LBMError) as e:
+        Simulation(gpu_config(p, "bf16"), phi0, muA0, muB0)
+    assert e.value.code == LBM_EUNSUPPORTED
+    sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
+    work = sim.adjoint_workspace()
+    with pytest.raises(LBMError) as e:
+        sim.adjoint_seed(sim.save(), np.zeros(phi0.size), work)
+    assert e.value.code == LBM_EUNSUPPORTED
+
+
+def test_fullsize_paper_ripening_sampled():
+    """The paper's 4096^2 ripening box (FP32, D2Q9 everywhere, paper's initial
+    condition) for 3 steps, sampled nodes against exact FP64 oracle windows of
+    half-width 3K + 3."""
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    w = inputs.ostwald_paper_2d()
+    steps = 3
+    sim = Simulation(gpu_config(w.params, "fp32"), w.phi0, w.muA0, w.muB0, c0=w.c0)
+    sim.step(steps)
+    rng = inputs.rng_for(61)
+    flat = w.phi0.reshape(-1)
+    near = np.flatnonzero(np.abs(flat - 0.5) < 0.25)
+    picks = list(rng.choice(near, 6, replace=False)) + list(rng.integers(0, flat.size, 4))
+    nodes = [np.unravel_index(int(i), w.phi0.shape) for i in picks]
+    idx = torch.tensor([int(i) for i in picks], device="cuda")
+    mom = sim.moments()
+    gpu = {k: v.reshape(-1).index_select(0, idx).cpu().numpy() for k, v in mom.items()}
+    R = 3 * steps + 3
+    n = w.phi0.shape[1]
+    for i, (_, y, x) in enumerate(nodes):
+        iy, ix = np.arange(y - R, y + R + 1) % n, np.arange(x - R, x + R + 1) % n
+        sub = np.ix_([0], iy, ix)
+        q = dict(w.params, nx=2 * R + 1, ny=2 * R + 1)
+        prm = oracle_params(q)
+        st = olbm.run(olbm.init(w.phi0[sub], w.muA0[sub], w.muB0[sub], prm,
+                                c0=(w.c0[0][sub], w.c0[1][sub])), prm, steps)
+        m = olbm.moments(st, prm)
+        for k in ("phi", "cA", "cB", "muA", "muB"):
+            win = np.asarray(m[k])
+            scale = max(np.abs(win).max(), np.abs(np.asarray(m["cA"])).max() if k.startswith("mu") else 0.0)
+            assert abs(gpu[k][i] - win[0, R, R]) <= 1e-5 * scale + 1e-12, (k, (y, x), gpu[k][i], win[0, R, R])

@@ -158,8 +158,9 @@ def test_ostwald_collision_rates_printed():
 # ----------------------------------------------------------------------------------------
 # equilibrium moments stated in Section 3
 
-@pytest.mark.parametrize("slat,flat", [(lattices.D2Q5, lattices.D2Q9), (lattices.D3Q7, lattices.D3Q19)],
-                         ids=["2D", "3D"])
+@pytest.mark.parametrize("slat,flat", [(lattices.D2Q5, lattices.D2Q9), (lattices.D3Q7, lattices.D3Q19),
+                                       (lattices.D2Q9, lattices.D2Q9), (lattices.D3Q19, lattices.D3Q19)],
+                         ids=["2D", "3D", "2D-paper-scalars", "3D-paper-scalars"])
 def test_equilibrium_moments(slat, flat):
     rng = np.random.default_rng(7)
     n = 17
@@ -213,7 +214,8 @@ def _droplet_fields(shape, centres, radii, W, rng, noise=1e-3):
     return phi, mu[0], mu[1]
 
 
-@pytest.mark.parametrize("case", ["2d_noflow_walls", "2d_flow_walls", "3d_flow_walls", "3d_flow_periodic_g"])
+@pytest.mark.parametrize("case", ["2d_noflow_walls", "2d_flow_walls", "3d_flow_walls", "3d_flow_periodic_g",
+                                  "2d_paper_scalars_flow_walls", "3d_paper_scalars_flow_walls"])
 def test_mass_conservation_exact(case):
     rng = np.random.default_rng(3)
     if case == "2d_noflow_walls":
@@ -230,6 +232,16 @@ def test_mass_conservation_exact(case):
                          W=4.0, lam=21.05, drho=0.5, g=(0, 0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
         fields = _droplet_fields(prm.shape, [(7, 6, 8)], [4.5], 4.0, rng)
         nsteps = 30
+    elif case == "2d_paper_scalars_flow_walls":
+        prm = lbm.Params(nx=30, ny=26, fluid="D2Q9", scalar="D2Q9", bc=("walls", "walls", "periodic"), W=4.0,
+                         lam=21.05, drho=0.5, g=(0, -1e-4, 0), sigma=1e-3, nu=(0.1, 0.05))
+        fields = _droplet_fields(prm.shape, [(15, 13, 0)], [6], 4.0, rng)
+        nsteps = 80
+    elif case == "3d_paper_scalars_flow_walls":
+        prm = lbm.Params(nx=12, ny=10, nz=14, fluid="D3Q19", scalar="D3Q19", bc=("periodic", "walls", "walls"),
+                         W=4.0, lam=21.05, drho=0.5, g=(0, 0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
+        fields = _droplet_fields(prm.shape, [(6, 5, 7)], [4.0], 4.0, rng)
+        nsteps = 20
     else:
         prm = lbm.Params(nx=12, ny=12, nz=12, fluid="D3Q19", scalar="D3Q7", W=4.0, lam=21.05,
                          drho=0.5, g=(0, 0, -1e-4), sigma=1e-3, nu=(0.1, 0.05), gravity_mean_subtract=True)
@@ -269,7 +281,8 @@ def test_momentum_balance_periodic():
 # ----------------------------------------------------------------------------------------
 # diffusion of the composition lattice: Fourier-mode decay against exp(-M k^2 t)
 
-@pytest.mark.parametrize("scalar,axis", [("D2Q5", 0), ("D2Q5", 1), ("D3Q7", 2)])
+@pytest.mark.parametrize("scalar,axis", [("D2Q5", 0), ("D2Q5", 1), ("D3Q7", 2), ("D2Q9", 0), ("D2Q9", 1),
+                                         ("D3Q19", 2)])
 def test_fourier_mode_diffusivity(scalar, axis):
     """phi = 0 everywhere stays 0 (omega_dw'(0) = p'(0) = 0), so c^A obeys
     dc/dt = M lap mu with mu = c - c_0 (Eq. Compos, bulk phase 0).  A sine mode decays
@@ -299,6 +312,51 @@ def test_fourier_mode_diffusivity(scalar, axis):
         errs.append(abs(rate_meas / (M * kw * kw) - 1.0))
     assert errs[1] < 0.02
     assert errs[0] / errs[1] > 3.0   # O(k^2) relative error
+
+
+@pytest.mark.parametrize("scalar", ["D2Q5", "D2Q9", "D3Q7", "D3Q19"])
+def test_fourier_mode_diagonal(scalar):
+    """Isotropy of the composition lattice: a mode along a lattice diagonal decays at
+    M |k|^2 as well (to O(k^2) relative error)."""
+    N = 24
+    three = scalar in ("D3Q7", "D3Q19")
+    nz, ny, nx = (1, N, N) if not three else (N, N, 1)
+    M = 0.15
+    prm = lbm.Params(nx=nx, ny=ny, nz=nz, scalar=scalar, W=4.0, lam=10.0, M_phi=0.1,
+                     M_A=(M, M), M_B=(M, M), c_eq=((0.2, 0.1), (0.6, 0.3)))
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    kw = 2 * math.pi / N
+    arg = kw * (y + z) if three else kw * (x + y)
+    mu0 = 1e-3 * np.sin(arg)
+    st = lbm.run(lbm.init(np.zeros(prm.shape), mu0, 0 * mu0, prm), prm, 30)
+    a0 = (lbm.moments(st, prm)["muA"] * np.sin(arg)).sum()
+    T = int(1.0 / (M * 2 * kw * kw))
+    st = lbm.run(st, prm, T)
+    a1 = (lbm.moments(st, prm)["muA"] * np.sin(arg)).sum()
+    rate = -math.log(a1 / a0) / T
+    assert abs(rate / (M * 2 * kw * kw) - 1.0) < 0.03
+
+
+def test_init_given_compositions():
+    """The paper's initial condition gives c and mu separately.  With c equal to the
+    closure the populations equal those of the ordinary initialisation; with mu = 0
+    the h populations are c at rest (h_0 = c, h_k = 0) and g does not depend on c."""
+    rng = np.random.default_rng(21)
+    prm = lbm.Params(nx=18, ny=14, fluid="D2Q9", scalar="D2Q9", W=3.0, lam=21.05, drho=0.5,
+                     g=(0, -1e-4, 0), sigma=1e-3, nu=(0.1, 0.05))
+    phi, muA, muB = _droplet_fields(prm.shape, [(9, 7, 0)], [4.0], 3.0, rng)
+    a = lbm.init(phi, muA, muB, prm)
+    c = model.closure_c((muA, muB), phi, prm.c_eq)
+    b = lbm.init(phi, muA, muB, prm, c0=c)
+    for k in ("g", "hA", "hB", "f"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+    cA = np.where(phi >= 0.5, 0.6, 0.21)
+    cB = np.where(phi >= 0.5, 0.3, 0.11)
+    z = np.zeros_like(phi)
+    st = lbm.init(phi, z, z, prm, c0=(cA, cB))
+    assert np.array_equal(st.hA[0], cA) and np.array_equal(st.hB[0], cB)
+    assert np.abs(st.hA[1:]).max() == 0.0 and np.abs(st.hB[1:]).max() == 0.0
+    assert np.array_equal(st.g, lbm.init(phi, z, z, prm).g)
 
 
 # ----------------------------------------------------------------------------------------
