@@ -53,6 +53,11 @@ def case(name):
         p = inputs._base(21, 19, 18, W=4.0, scalar="D3Q19", fluid="D3Q19", bc=("walls", "periodic", "walls"),
                          drho=0.5, g=(0.0, 0.0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
         return (p, *_drops((18, 19, 21), 1, 4.0, 5.0, 4.0, 44, (0, 2)), None, 10)
+    if name == "c1b_couple_paper_d2q9":
+        # the diffusion couple of Table tab:Parameters_Diffusion-Couple on the paper's D2Q9
+        w = inputs.diffusion_couple_paper(nx=256)
+        p = dict(w.params, scalar="D2Q9")
+        return (p, w.phi0, w.muA0, w.muB0, None, 600)
     if name == "2d_paper_initial_condition":
         w = inputs.ostwald_paper_2d(n=96)
         z = np.zeros_like(w.phi0)
@@ -60,7 +65,8 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["2d_noflow_periodic", "2d_flow_walls", "3d_noflow_walls", "3d_flow_walls", "2d_paper_initial_condition"]
+CASES = ["2d_noflow_periodic", "2d_flow_walls", "3d_noflow_walls", "3d_flow_walls", "2d_paper_initial_condition",
+         "c1b_couple_paper_d2q9"]
 
 
 @functools.lru_cache(maxsize=None)
