@@ -63,6 +63,8 @@ class Params:
     sigma: float = 0.0
     nu: Tuple[float, float] = (0.1, 0.1)       # (phase 0, phase 1)
     gravity_mean_subtract: bool = False
+    collision: str = "BGK"                      # "BGK" (the paper's) or "TRT"
+    trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)   # TRT Lambda of (f, the scalar lattices)
 
     @property
     def shape(self):
@@ -224,6 +226,28 @@ def rate(D, cs2):
     return 1.0 / (D / cs2 + 0.5)
 
 
+def trt_partner_rate(w, magic):
+    """Two-relaxation-time collision (the TRT operator the paper names as an alternative
+    to BGK in Section 3; Ginzburg's form): the rate that the transport coefficient does
+    not fix follows from the magic parameter Lambda = (1/w+ - 1/2)(1/w- - 1/2)."""
+    return 1.0 / (0.5 + magic / (1.0 / w - 0.5))
+
+
+def trt_collide(X, eqs, src, lat, w_sym, w_anti):
+    """Post-collision populations of a TRT collision: the non-equilibrium part
+    n_k = X_k - eqs_k (eqs: the shifted equilibrium of the BGK form) is split into its
+    symmetric and antisymmetric parts over the pair (k, opp(k)), relaxed at w_sym and
+    w_anti, and the source src_k is added:
+        X*_k = X_k - w_sym (n_k + n_opp)/2 - w_anti (n_k - n_opp)/2 + src_k.
+    With w_sym = w_anti this is the BGK collision X_k - w n_k + src_k."""
+    n = [X[k] - eqs[k] for k in range(lat.Q)]
+    out = []
+    for k in range(lat.Q):
+        o = lat.opp[k]
+        out.append(X[k] - w_sym * 0.5 * (n[k] + n[o]) - w_anti * 0.5 * (n[k] - n[o]) + src[k])
+    return np.stack(out)
+
+
 # ----------------------------------------------------------------------------------------
 # moments
 
@@ -327,25 +351,41 @@ def step(st, prm):
     else:
         u = [zero, zero, zero]
 
+    trt = prm.collision == "TRT"
+    lam_f, lam_s = prm.trt_magic
+
     # g: Eqs. LBE_Phi, Geq, Source_LBE_Phi
     wg = rate(prm.M_phi, slat.cs2)
-    g_post = np.stack([st.g[k] - wg * (st.g[k] - g_equilibrium_k(slat, k, phi, u, slat.w[k] * S))
-                       + slat.w[k] * S for k in range(slat.Q)])
+    if not trt:
+        g_post = np.stack([st.g[k] - wg * (st.g[k] - g_equilibrium_k(slat, k, phi, u, slat.w[k] * S))
+                           + slat.w[k] * S for k in range(slat.Q)])
+    else:  # the diffusive flux is the antisymmetric part: M_phi sets w-
+        Gk = [slat.w[k] * S for k in range(slat.Q)]
+        g_post = trt_collide(st.g, [g_equilibrium_k(slat, k, phi, u, Gk[k]) for k in range(slat.Q)], Gk, slat,
+                             trt_partner_rate(wg, lam_s), wg)
 
     # h^alpha: Eqs. LBE_c_alpha, Heq with the phase-dependent mobility
     h_post = []
     for h, c, mu, Mpair in ((st.hA, m["cA"], m["muA"], prm.M_A), (st.hB, m["cB"], m["muB"], prm.M_B)):
         wh = rate(model.mobility(phi, Mpair), slat.cs2)
-        h_post.append(np.stack([h[k] - wh * (h[k] - h_equilibrium_k(slat, k, c, mu, u))
-                                for k in range(slat.Q)]))
+        if not trt:
+            h_post.append(np.stack([h[k] - wh * (h[k] - h_equilibrium_k(slat, k, c, mu, u))
+                                    for k in range(slat.Q)]))
+        else:
+            h_post.append(trt_collide(h, [h_equilibrium_k(slat, k, c, mu, u) for k in range(slat.Q)],
+                                      [0.0] * slat.Q, slat, trt_partner_rate(wh, lam_s), wh))
 
     f_new = None
     if prm.fluid:
         # f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq
         wf = rate(model.viscosity(phi, prm.nu), flat.cs2)
         Fk = [forcing_k(flat, k, u, F) for k in range(flat.Q)]
-        f_post = np.stack([st.f[k] - wf * (st.f[k] - f_equilibrium_k(flat, k, p_h, u, prm.rho0, Fk[k]))
-                           + Fk[k] for k in range(flat.Q)])
+        if not trt:
+            f_post = np.stack([st.f[k] - wf * (st.f[k] - f_equilibrium_k(flat, k, p_h, u, prm.rho0, Fk[k]))
+                               + Fk[k] for k in range(flat.Q)])
+        else:  # the viscous stress is the symmetric part: nu sets w+
+            f_post = trt_collide(st.f, [f_equilibrium_k(flat, k, p_h, u, prm.rho0, Fk[k]) for k in range(flat.Q)],
+                                 Fk, flat, wf, trt_partner_rate(wf, lam_f))
         f_new = stream(f_post, flat, prm.bc)
 
     phi_ref = phi.mean() if prm.gravity_mean_subtract else st.phi_ref

@@ -495,6 +495,86 @@ def test_poiseuille_between_walls():
     assert np.abs(ux - ref).max() < 0.01 * ref.max()
 
 
+# ----------------------------------------------------------------------------------------
+# TRT collision (the two-relaxation-time alternative to BGK named in Section 3)
+
+@pytest.mark.parametrize("nu,steps", [(0.5, 1000), (0.2, 2200)])
+def test_trt_poiseuille_exact(nu, steps):
+    """With the magic parameter 3/16 the half-way bounce-back wall sits exactly at
+    -1/2 and N - 1/2 for any viscosity: the steady TRT profile is the parabola to
+    rounding, where BGK leaves a viscosity-dependent slip."""
+    N = 12
+    ref = analytic.poiseuille(np.arange(N), N, 1e-6, 1.0, nu)
+    errs = {}
+    for coll in ("TRT", "BGK"):
+        prm = lbm.Params(nx=2, ny=N, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05,
+                         drho=1.0, g=(1e-6, 0, 0), sigma=1e-3, nu=(nu, nu), collision=coll,
+                         trt_magic=(3.0 / 16.0, 0.25))
+        if coll == "BGK" and nu != 0.5:
+            continue
+        phi0 = np.ones(prm.shape)
+        st = lbm.run(lbm.init(phi0, 0 * phi0, 0 * phi0, prm), prm, steps)
+        ux = lbm.moments(st, prm)["ux"][0, :, 0]
+        errs[coll] = np.abs(ux - ref).max() / ref.max()
+    assert errs["TRT"] < 1e-9, errs
+    if "BGK" in errs:
+        assert errs["BGK"] > 1e-2, errs
+
+
+def test_trt_equals_bgk_when_rates_coincide():
+    """With one rate per lattice and Lambda = tau^2 (tau = 1/w - 1/2) both TRT rates are
+    the BGK rate: the two collisions agree to rounding, flow, walls and sources included."""
+    rng = np.random.default_rng(8)
+    M, nu = 0.1, 0.08
+    cs2 = 1.0 / 3.0
+    common = dict(nx=26, ny=22, fluid="D2Q9", scalar="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0,
+                  lam=21.05, M_phi=M, M_A=(M, M), M_B=(M, M), drho=0.5, g=(0, -1e-4, 0), sigma=1e-3,
+                  nu=(nu, nu))
+    fields = _droplet_fields((1, 22, 26), [(13, 11, 0)], [5], 4.0, rng)
+    a = lbm.run(lbm.init(*fields, lbm.Params(**common)), lbm.Params(**common), 25)
+    trt = lbm.Params(**common, collision="TRT", trt_magic=((nu / cs2) ** 2, (M / cs2) ** 2))
+    b = lbm.run(lbm.init(*fields, trt), trt, 25)
+    for k in ("f", "g", "hA", "hB"):
+        assert np.abs(getattr(a, k) - getattr(b, k)).max() < 1e-14, k
+
+
+@pytest.mark.parametrize("magic", [0.25, 1.0 / 12.0])
+def test_trt_fourier_mode_diffusivity(magic):
+    """The TRT diffusivity is set by the antisymmetric rate alone: D = c_s^2 (1/w- - 1/2)
+    whatever Lambda (to the O(k^2) error of the scheme)."""
+    errs = []
+    for N in (16, 32):
+        M = 0.15
+        prm = lbm.Params(nx=N, ny=1, scalar="D2Q9", W=4.0, lam=10.0, M_phi=0.1, M_A=(M, M), M_B=(M, M),
+                         c_eq=((0.2, 0.1), (0.6, 0.3)), collision="TRT", trt_magic=(0.25, magic))
+        x = np.arange(N)[None, None, :] * np.ones(prm.shape)
+        kw = 2 * math.pi / N
+        mu0 = 1e-3 * np.sin(kw * x)
+        st = lbm.run(lbm.init(np.zeros(prm.shape), mu0, 0 * mu0, prm), prm, 40)
+        a0 = (lbm.moments(st, prm)["muA"] * np.sin(kw * x)).sum()
+        T = int(2.0 / (M * kw * kw))
+        st = lbm.run(st, prm, T)
+        a1 = (lbm.moments(st, prm)["muA"] * np.sin(kw * x)).sum()
+        errs.append(abs(-math.log(a1 / a0) / T / (M * kw * kw) - 1.0))
+    assert errs[1] < 0.02
+    assert errs[0] / errs[1] > 3.0
+
+
+def test_trt_conserves_mass_and_pressure_sum():
+    rng = np.random.default_rng(9)
+    prm = lbm.Params(nx=24, ny=20, fluid="D2Q9", bc=("walls", "walls", "periodic"), W=4.0, lam=21.05,
+                     M_A=(0.1, 0.05), M_B=(0.08, 0.12), drho=0.5, g=(0, -1e-4, 0), sigma=1e-3, nu=(0.1, 0.05),
+                     collision="TRT", trt_magic=(3.0 / 16.0, 0.25))
+    st = lbm.init(*_droplet_fields(prm.shape, [(12, 10, 0)], [5], 4.0, rng), prm)
+    d0, p0 = lbm.diagnostics(st, prm), st.f.sum()
+    st = lbm.run(st, prm, 60)
+    d1 = lbm.diagnostics(st, prm)
+    for key in ("sum_cA", "sum_cB"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * abs(d0[key]), key
+    assert abs(st.f.sum() - p0) <= 1e-12 * max(1.0, abs(d0["sum_phi"]))
+    assert d1["nan_count"] == 0
+
+
 @pytest.mark.slow
 def test_laplace_pressure_jump():
     """Static 2D drop with no driving force: p_in - p_out = sigma / R (within the spurious
