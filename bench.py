@@ -33,6 +33,8 @@ WORKLOADS = {
     "single_drop_2d_512": dict(kind="single_drop_2d", n=512, precision="fp32"),
     # the paper's own discretisation and initial condition (D2Q9 for every equation)
     "ostwald_paper_2d_4096": dict(kind="ostwald_paper_2d", n=4096, precision="fp32"),
+    # the two-relaxation-time collision on the sedimentation workload
+    "sediment_3d_256_trt": dict(kind="sediment_3d", n=256, precision="fp32", collision="TRT"),
 }
 
 
@@ -49,6 +51,13 @@ def bytes_per_update(cfg):
 
 
 def build_workload(name):
+    w = _build_workload(name)
+    if WORKLOADS[name].get("collision"):
+        w.params = dict(w.params, collision=WORKLOADS[name]["collision"], trt_magic=(3.0 / 16.0, 0.25))
+    return w
+
+
+def _build_workload(name):
     from paper_2409_03401_amd import inputs
     spec = WORKLOADS[name]
     kind = spec["kind"]

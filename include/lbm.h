@@ -38,6 +38,18 @@ extern "C" {
 #define LBM_D2Q5 5            /* reduced scalar lattices for phi, c^A, c^B         */
 #define LBM_D3Q7 7
 
+/* collision operators (Section 3).  LBM_BGK is the paper's single-rate collision.
+ * LBM_TRT, the two-relaxation-time alternative Section 3 names, relaxes the part
+ * of X_k - X_k^eq that is symmetric over (k, opp(k)) at w+ and the antisymmetric
+ * part at w- (the equilibria keep their -F_k/2, -G_k/2 shifts and the sources are
+ * added as in BGK).  The transport coefficient sets one rate as in BGK: the
+ * viscosity sets w+ of f, the mobilities set w- of g, h^A, h^B; the other follows
+ * from the magic parameter Lambda = (1/w+ - 1/2)(1/w- - 1/2) (trt_magic; 3/16
+ * puts half-way bounce-back walls exactly at the half link).  FP64 and FP32
+ * storage, no adjoint. */
+#define LBM_BGK 0
+#define LBM_TRT 1
+
 #define LBM_PERIODIC 0
 #define LBM_WALLS 1           /* half-way bounce-back walls at both ends of an axis */
 
@@ -107,6 +119,9 @@ typedef struct lbm_config {
     double nu[2];              /* kinematic viscosity per phase                     */
     double store_ref[4];       /* 16-bit storage: reference per field f, g, hA, hB  */
     int32_t store_shift[4];    /* 16-bit storage: power-of-two scale per field      */
+    int32_t collision;         /* LBM_BGK (the paper's, 0) or LBM_TRT               */
+    int32_t reserved;          /* 0                                                 */
+    double trt_magic[2];       /* LBM_TRT: Lambda of f and of g, h^A, h^B (> 0)     */
 } lbm_config;
 
 typedef struct lbm_handle lbm_handle;

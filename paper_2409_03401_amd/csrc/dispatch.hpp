@@ -33,6 +33,9 @@ const KernelSet* kernels_3d(int fluid, int prec, int tx, int ty);
 // the paper's scalar lattices (D2Q9 / D3Q19 for g, h^A, h^B): FP64 / FP32, no adjoint
 const KernelSet* kernels_paper_2d(int fluid, int prec);
 const KernelSet* kernels_paper_3d(int fluid, int prec);
+// the two-relaxation-time collision (scalar lattice 5 / 9 in 2D, 7 / 19 in 3D): FP64 / FP32, no adjoint
+const KernelSet* kernels_trt_2d(int scalar, int fluid, int prec);
+const KernelSet* kernels_trt_3d(int scalar, int fluid, int prec);
 
 void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
 void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,

@@ -8,16 +8,16 @@
 
 namespace lbm {
 
-template <class SL, class FL, int PREC, int TX, int TY, bool ADJ = true>
+template <class SL, class FL, int PREC, int TX, int TY, bool ADJ = true, int COLL = COLL_BGK>
 struct Family {
     static void fused(int mode, dim3 grid, const KParams& kp, hipStream_t s) {
         const dim3 block(TX, TY);
         switch (mode) {
             case MODE_STEP:
-                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP, PREC, TX, TY>), grid, block, 0, s, kp);
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP, PREC, TX, TY, COLL>), grid, block, 0, s, kp);
                 break;
             case MODE_STEP_PHI:
-                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP_PHI, PREC, TX, TY>), grid, block, 0, s, kp);
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP_PHI, PREC, TX, TY, COLL>), grid, block, 0, s, kp);
                 break;
             case MODE_MOMENTS:
                 hipLaunchKernelGGL((k_lbm<SL, FL, MODE_MOMENTS, PREC, TX, TY>), grid, block, 0, s, kp);
@@ -95,12 +95,12 @@ const KernelSet* family_for_prec(int prec) {
     }
 }
 
-// the paper's scalar lattices: FP64 and FP32 storage, no adjoint
-template <class SL, class FL, int TX, int TY>
+// the paper's scalar lattices and the TRT collision: FP64 and FP32 storage, no adjoint
+template <class SL, class FL, int TX, int TY, int COLL = COLL_BGK>
 const KernelSet* family_fp_only(int prec) {
     switch (prec) {
-        case P64: return &Family<SL, FL, P64, TX, TY, false>::set;
-        case P32: return &Family<SL, FL, P32, TX, TY, false>::set;
+        case P64: return &Family<SL, FL, P64, TX, TY, false, COLL>::set;
+        case P32: return &Family<SL, FL, P32, TX, TY, false, COLL>::set;
         default: return nullptr;
     }
 }

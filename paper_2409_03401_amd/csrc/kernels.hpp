@@ -296,7 +296,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
         if constexpr (LBM_PHASES) __builtin_amdgcn_sched_barrier(0); \
     } while (0)
 
-template <class SL, class FL, int MODE, int PREC, int TX, int TY>
+template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
 k_lbm(const KParams P) {
     using C = typename Stor<PREC>::C;
@@ -629,6 +629,7 @@ k_lbm(const KParams P) {
                     const C keep = C(1) - wf, half = C(1) - C(0.5) * wf;
                     const C rho0 = KC(P.rho0, P.f32.rho0);
                     const C g0 = C(1) - C(1.5) * uu, e0 = p_h - C(0.5) * rho0 * uu;
+                    if constexpr (COLL == COLL_BGK) {
                     C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
@@ -644,6 +645,38 @@ k_lbm(const KParams P) {
                         else push_r(kc, kc, FLT{}, v, res);
                     });
                     if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + res);
+                    } else {
+                        // TRT: the viscosity sets the symmetric rate w+ = wf; w- from the
+                        // magic parameter, 1/w- - 1/2 = Lambda_f / (1/wf - 1/2) = Lambda_f / (3 nu)
+                        const C wm = rcp<C>(C(0.5) + KC(P.trt_lf, P.f32.trt_lf) * rcp<C>(C(3) * nu));
+                        // shifted equilibrium (feq - F_k/2) and source F_k of direction k
+                        auto eqsrc = [&](auto kc, C& eqs, C& Fk) __attribute__((always_inline)) {
+                            constexpr int k = decltype(kc)::value;
+                            constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
+                            const C wk = C(FL::w(k));
+                            const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
+                            const C eF = edot<ex, ey, ez>(F[0], F[1], F[2]);
+                            Fk = wk * (g0 + eu * (C(3) + C(4.5) * eu)) * (eF - uF);
+                            eqs = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu)) - C(0.5) * Fk;
+                        };
+                        static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                            constexpr int k = decltype(kc)::value;
+                            constexpr int o = FL::opp(k);
+                            if constexpr (k == 0) {
+                                C eqs, Fk;
+                                eqsrc(kc, eqs, Fk);
+                                push(kc, kc, FLT{}, fpop[0] - wf * (fpop[0] - eqs) + Fk);
+                            } else if constexpr (k < o) {
+                                C eqk, Fk, eqo, Fo;
+                                eqsrc(kc, eqk, Fk);
+                                eqsrc(IC<o>{}, eqo, Fo);
+                                const C nk = fpop[k] - eqk, no = fpop[o] - eqo;
+                                const C sp = wf * C(0.5) * (nk + no), sm = wm * C(0.5) * (nk - no);
+                                push(kc, kc, FLT{}, fpop[k] - sp - sm + Fk);
+                                push(IC<o>{}, IC<o>{}, FLT{}, fpop[o] - sp + sm + Fo);
+                            }
+                        });
+                    }
                 }
 
                 LBM_FENCE();
@@ -654,6 +687,7 @@ k_lbm(const KParams P) {
                     const C keep = C(1) - wg;
                     const C wphi = wg * phi;
                     const C srcS = (C(1) - C(0.5) * wg) * C(m.S);
+                    if constexpr (COLL == COLL_BGK) {
                     C res = C(0), rest = C(0);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
@@ -667,6 +701,34 @@ k_lbm(const KParams P) {
                         else push_r(IC<G0 + k>{}, kc, SLT{}, v, res);
                     });
                     if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + res);
+                    } else {
+                        // TRT: M_phi sets the antisymmetric rate w- = wg; w+ (uniform) from
+                        // the magic parameter on the host.  Shifted equilibrium
+                        // w_k phi (1 + eu / c_s^2) - w_k S / 2, source w_k S.
+                        const C wp = KC(P.omega_gp, P.f32.omega_gp);
+                        const C S = C(m.S), hS = C(0.5) * C(m.S);
+                        auto eqs = [&](auto kc) __attribute__((always_inline)) -> C {
+                            constexpr int k = decltype(kc)::value;
+                            constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                            const C wk = C(SL::w(k));
+                            if constexpr (ex != 0 || ey != 0 || ez != 0)
+                                return wk * (phi * (C(1) + edot<ex, ey, ez>(u[0], u[1], u[2]) * inv_cs2s) - hS);
+                            else
+                                return wk * (phi - hS);
+                        };
+                        static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
+                            constexpr int k = decltype(kc)::value;
+                            constexpr int o = SL::opp(k);
+                            if constexpr (k == 0) {
+                                push(IC<G0>{}, kc, SLT{}, g[0] - wp * (g[0] - eqs(kc)) + C(SL::w(0)) * S);
+                            } else if constexpr (k < o) {
+                                const C nk = g[k] - eqs(kc), no = g[o] - eqs(IC<o>{});
+                                const C sp = wp * C(0.5) * (nk + no), sm = wg * C(0.5) * (nk - no);
+                                push(IC<G0 + k>{}, kc, SLT{}, g[k] - sp - sm + C(SL::w(k)) * S);
+                                push(IC<G0 + o>{}, IC<o>{}, SLT{}, g[o] - sp + sm + C(SL::w(o)) * S);
+                            }
+                        });
+                    }
                 }
 
                 LBM_FENCE();
@@ -676,6 +738,36 @@ k_lbm(const KParams P) {
                     const C MB = KC(P.MB0, P.f32.MB0) * (C(1) - phi) + KC(P.MB1, P.f32.MB1) * phi;
                     const C wA = rcp<C>(MA * inv_cs2s + C(0.5));
                     const C wB = rcp<C>(MB * inv_cs2s + C(0.5));
+                    if constexpr (COLL == COLL_TRT) {
+                        // TRT: the mobility sets the antisymmetric rate w- = wA (wB); w+ from
+                        // the magic parameter, 1/w+ - 1/2 = Lambda_s / (M / c_s^2)
+                        const C ls = KC(P.trt_ls, P.f32.trt_ls);
+                        const C wpA = rcp<C>(C(0.5) + ls * rcp<C>(MA * inv_cs2s));
+                        const C wpB = rcp<C>(C(0.5) + ls * rcp<C>(MB * inv_cs2s));
+                        // rest populations (symmetric) in double, as in BGK
+                        push(IC<A0>{}, IC<0>{}, SLT{},
+                             C(double(a[0]) - double(wpA) * (double(a[0]) - (sA - (1.0 - SL::w(0)) * m.muA))));
+                        push(IC<B0>{}, IC<0>{}, SLT{},
+                             C(double(b[0]) - double(wpB) * (double(b[0]) - (sB - (1.0 - SL::w(0)) * m.muB))));
+                        const C muA = C(m.muA), muB = C(m.muB);
+                        const C cuA = C(sA) * inv_cs2s, cuB = C(sB) * inv_cs2s;
+                        static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
+                            constexpr int k = decltype(kc)::value;
+                            constexpr int o = SL::opp(k);
+                            if constexpr (k < o) {
+                                constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                                const C wk = C(SL::w(k));  // w_opp(k) = w_k
+                                const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);  // e_opp . u = -eu
+                                // h^eq_k = w_k (mu + c eu / c_s^2): symmetric part w_k mu, antisymmetric w_k c eu / c_s^2
+                                const C npA = C(0.5) * (a[k] + a[o]) - wk * muA, nmA = C(0.5) * (a[k] - a[o]) - wk * cuA * eu;
+                                const C npB = C(0.5) * (b[k] + b[o]) - wk * muB, nmB = C(0.5) * (b[k] - b[o]) - wk * cuB * eu;
+                                push(IC<A0 + k>{}, kc, SLT{}, a[k] - wpA * npA - wA * nmA);
+                                push(IC<A0 + o>{}, IC<o>{}, SLT{}, a[o] - wpA * npA + wA * nmA);
+                                push(IC<B0 + k>{}, kc, SLT{}, b[k] - wpB * npB - wB * nmB);
+                                push(IC<B0 + o>{}, IC<o>{}, SLT{}, b[o] - wpB * npB + wB * nmB);
+                            }
+                        });
+                    } else {
                     // rest populations in double: they carry the conserved composition
                     const double whA = double(wA), whB = double(wB);
                     const double eqA = sA - (1.0 - SL::w(0)) * m.muA;
@@ -701,6 +793,7 @@ k_lbm(const KParams P) {
                     if constexpr (FEEDBACK) {
                         push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(resA)));
                         push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(resB)));
+                    }
                     }
                 }
 

@@ -70,6 +70,12 @@ int check_config(const lbm_config* c, Layout* L) {
         return fail(LBM_EUNSUPPORTED, "scalar lattice must be LBM_D2Q5, LBM_D2Q9, LBM_D3Q7 or LBM_D3Q19");
     }
     const bool paper_scalar = c->scalar == LBM_D2Q9 || c->scalar == LBM_D3Q19;
+    if (c->collision != LBM_BGK && c->collision != LBM_TRT)
+        return fail(LBM_EINVAL, "collision must be LBM_BGK or LBM_TRT");
+    const bool trt = c->collision == LBM_TRT;
+    if (trt)
+        for (double m : {c->trt_magic[0], c->trt_magic[1]})
+            if (!(std::isfinite(m) && m > 0)) return fail(LBM_EINVAL, "trt_magic must be finite and > 0");
     if (c->precision < LBM_FP64 || c->precision > LBM_FP32_BF16STORE)
         return fail(LBM_EUNSUPPORTED, "unknown precision");
     for (int a = 0; a < 3; ++a)
@@ -135,7 +141,10 @@ int check_config(const lbm_config* c, Layout* L) {
     // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
     int want_tx = 0, want_ty = 0;
     if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
-    if (paper_scalar) {
+    if (trt) {
+        L->ks = L->dim == 2 ? kernels_trt_2d(L->qs, L->qf, L->prec) : kernels_trt_3d(L->qs, L->qf, L->prec);
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "the TRT collision runs with FP64 or FP32 storage");
+    } else if (paper_scalar) {
         L->ks = L->dim == 2 ? kernels_paper_2d(L->qf, L->prec) : kernels_paper_3d(L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "D2Q9 / D3Q19 scalar lattices run with FP64 or FP32 storage");
     } else {
@@ -216,6 +225,13 @@ void fill_params(lbm_handle* h) {
     // c_s^2 of the scalar lattice
     const double cs2s = L.qs == 5 ? D2Q5K::cs2 : L.qs == 7 ? D3Q7K::cs2 : L.qs == 9 ? D2Q9K::cs2 : D3Q19K::cs2;
     kp.omega_g = 1.0 / (c.M_phi / cs2s + 0.5);
+    // TRT: the symmetric rate of g from Lambda_s = (1/w+ - 1/2)(1/w- - 1/2), w- = omega_g
+    kp.trt_lf = c.trt_magic[0];
+    kp.trt_ls = c.trt_magic[1];
+    kp.omega_gp = c.collision == LBM_TRT ? 1.0 / (0.5 + c.trt_magic[1] / (c.M_phi / cs2s)) : kp.omega_g;
+    kp.f32.trt_lf = float(kp.trt_lf);
+    kp.f32.trt_ls = float(kp.trt_ls);
+    kp.f32.omega_gp = float(kp.omega_gp);
     kp.MA0 = c.M_A[0]; kp.MA1 = c.M_A[1]; kp.MB0 = c.M_B[0]; kp.MB1 = c.M_B[1];
     kp.nu0 = c.nu[0]; kp.nu1 = c.nu[1];
     kp.rho0 = L.qf ? c.rho0 : 1.0;

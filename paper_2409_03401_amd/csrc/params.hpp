@@ -16,6 +16,8 @@ constexpr int kNumDiag = 8;
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
 // MODE_STEP_PHI: a step that also writes phi of its source state (P.phi_out)
 enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_STEP_PHI = 3 };
+// collision operator of the fused step: the paper's BGK, or two relaxation times
+enum Coll : int { COLL_BGK = 0, COLL_TRT = 1 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -43,6 +45,8 @@ struct KParams {
     double W, lam, mphi_w2;      // mphi_w2 = M_phi / W^2 = 1 / tau_phi
     double c0A, c0B, c1A, c1B;   // equilibrium compositions of phases 0 and 1
     double omega_g;              // g-lattice rate 1 / (M_phi / c_s^2 + 1/2)
+    // TRT (COLL_TRT): magic parameters of f and of the scalar lattices; symmetric rate of g
+    double trt_lf, trt_ls, omega_gp;
     double MA0, MA1, MB0, MB1;   // species mobilities per phase
     double nu0, nu1, rho0, drho;
     double gx, gy, gz;           // gravity in the kernel frame
@@ -53,6 +57,7 @@ struct KParams {
     // conversion in the loop)
     struct {
         float cap, inv_W2, drho, gx, gy, gz, inv_rho0, rho0, nu0, nu1, omega_g, MA0, MA1, MB0, MB1;
+        float trt_lf, trt_ls, omega_gp;
     } f32;
     // population copies addressed by the fused kernel: slot s of a copy starts at
     // base + (#moving slots before s) * stride_m + (#rest slots before s) * stride_r

@@ -25,6 +25,8 @@ LBM_NONE, LBM_D2Q9, LBM_D3Q19, LBM_D2Q5, LBM_D3Q7 = 0, 9, 19, 5, 7
 LBM_PERIODIC, LBM_WALLS = 0, 1
 LBM_FP64, LBM_FP32, LBM_FP32_FP16STORE, LBM_FP32_BF16STORE = 0, 1, 2, 3
 LBM_OUT_F64, LBM_OUT_F32 = 0, 1
+LBM_BGK, LBM_TRT = 0, 1
+_COLLISION = {"BGK": LBM_BGK, "TRT": LBM_TRT}
 MOMENTS = ("phi", "cA", "cB", "muA", "muB", "p", "ux", "uy", "uz")
 DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interface_measure",
                "free_energy", "nan_count", "droplets", "mean_radius")
@@ -54,6 +56,7 @@ class _Config(ctypes.Structure):
         ("rho0", ctypes.c_double), ("drho", ctypes.c_double), ("g", ctypes.c_double * 3),
         ("sigma", ctypes.c_double), ("nu", ctypes.c_double * 2),
         ("store_ref", ctypes.c_double * 4), ("store_shift", ctypes.c_int32 * 4),
+        ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32), ("trt_magic", ctypes.c_double * 2),
     ]
 
 
@@ -144,6 +147,9 @@ class LBMConfig:
     # (x - w_k store_ref[F]) * 2^store_shift[F]
     store_ref: Tuple[float, float, float, float] = (0.0, 0.5, 0.0, 0.0)
     store_shift: Tuple[int, int, int, int] = (8, 0, 6, 6)
+    # "BGK" (the paper's) or "TRT"; TRT magic parameters of (f, the scalar lattices)
+    collision: str = "BGK"
+    trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)
 
     @property
     def nodes(self):
@@ -181,6 +187,8 @@ class LBMConfig:
         for i in range(4):
             c.store_ref[i] = self.store_ref[i]
             c.store_shift[i] = int(self.store_shift[i])
+        c.collision = _COLLISION[self.collision]
+        c.trt_magic[0], c.trt_magic[1] = float(self.trt_magic[0]), float(self.trt_magic[1])
         return c
 
 

@@ -31,9 +31,12 @@ def test_binding_covers_header():
 
 
 def test_struct_layout_matches_header():
-    # 10 int32 fields, then doubles; store_shift closes the struct
+    # 10 int32 fields, then doubles; store_shift, the collision fields and the TRT
+    # magic parameters close the struct
     assert lbm._Config.W.offset == 40
-    assert ctypes.sizeof(lbm._Config) == lbm._Config.store_shift.offset + 16
+    assert lbm._Config.collision.offset == lbm._Config.store_shift.offset + 16
+    assert lbm._Config.trt_magic.offset == lbm._Config.collision.offset + 8
+    assert ctypes.sizeof(lbm._Config) == lbm._Config.trt_magic.offset + 16
 
 
 def _cfg(**kw):
@@ -68,6 +71,9 @@ def test_state_bytes_layout():
     (dict(scalar="D3Q19", nz=4, precision="fp16"), lbm.LBM_EUNSUPPORTED),
     (dict(scalar="D2Q9", nz=4), lbm.LBM_EINVAL),              # a 2D lattice with nz > 1
     (dict(scalar="D3Q19", nz=4, fluid="D2Q9"), lbm.LBM_EUNSUPPORTED),
+    (dict(collision="TRT", precision="bf16"), lbm.LBM_EUNSUPPORTED),   # TRT: FP64 / FP32
+    (dict(collision="TRT", trt_magic=(0.0, 0.25)), lbm.LBM_EINVAL),
+    (dict(collision="TRT", trt_magic=(0.25, float("inf"))), lbm.LBM_EINVAL),
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:
