@@ -64,6 +64,7 @@ class Params:
     nu: Tuple[float, float] = (0.1, 0.1)       # (phase 0, phase 1)
     gravity_mean_subtract: bool = False
     collision: str = "BGK"                      # "BGK" (the paper's) or "TRT"
+    variable_density: bool = False              # False: Boussinesq (the paper's); True: rho(phi)
     trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)   # TRT Lambda of (f, the scalar lattices)
 
     @property
@@ -288,13 +289,74 @@ def flow_moments(f, F, prm):
     return p_h, u
 
 
+def density(phi, prm):
+    """rho(phi) of the variable-density model: rho0 in phase 0, rho0 + drho in phase 1,
+    interpolated linearly like the viscosity (the paper interpolates the bulk densities
+    without giving the law)."""
+    return prm.rho0 + prm.drho * phi
+
+
+def flow_moments_variable(f, phi, F_sb, prm):
+    """Variable-density flow moments (the alternative of Section 3 after Eq. Velocity:
+    the equilibrium carries the dimensionless pressure p* = p_h / (rho(phi) c_s^2), and
+    the pressure and viscous forces join the total force).  Reading:
+    f holds dimensionless populations, p* = sum_k f_k, p_h = rho c_s^2 p*;
+    F_p = -p* c_s^2 grad rho;
+    u* = sum_k f_k c_k + (F_sb + F_p) / (2 rho);
+    F_mu,i = -(nu w+ / c_s^2) Pi_ij d_j rho, Pi = sum_k c_k c_k (f_k - f^eq_k(p*, u*)) with
+    the unshifted equilibrium, w+ the rate of the viscous stress (nu(phi) / c_s^2 + 1/2)^-1;
+    u = u* + F_mu / (2 rho).  Returns p_h, u and the total force."""
+    lat = prm.flat
+    cs2 = lat.cs2
+    rho = density(phi, prm)
+    grad = gradient(phi, prm.bc, prm.stencil_lattice)
+    grho = [prm.drho * g for g in grad]
+    p_star = f.sum(axis=0)
+    F_p = [-p_star * cs2 * grho[a] for a in range(3)]
+    u_star = []
+    for a in range(3):
+        m = np.zeros_like(p_star)
+        for k in range(lat.Q):
+            if lat.e[k][a] != 0:
+                m = m + f[k] * lat.e[k][a]
+        u_star.append(m + 0.5 * (F_sb[a] + F_p[a]) / rho)
+    zero = np.zeros_like(p_star)
+    Pi = [[zero, zero, zero], [zero, zero, zero], [zero, zero, zero]]
+    for k in range(lat.Q):
+        n = f[k] - f_equilibrium_k(lat, k, p_star, u_star, 1.0 / cs2, 0.0)
+        e = lat.e[k]
+        for i in range(3):
+            for j in range(3):
+                if e[i] != 0 and e[j] != 0:
+                    Pi[i][j] = Pi[i][j] + e[i] * e[j] * n
+    w_plus = rate(model.viscosity(phi, prm.nu), cs2)
+    F_mu = [-(model.viscosity(phi, prm.nu) * w_plus / cs2) * sum(Pi[i][j] * grho[j] for j in range(3))
+            for i in range(3)]
+    u = [u_star[a] + 0.5 * F_mu[a] / rho for a in range(3)]
+    F = [F_sb[a] + F_p[a] + F_mu[a] for a in range(3)]
+    return rho * cs2 * p_star, u, F
+
+
+def _flow(f, phi, prm, phi_ref):
+    """p_h, u, total force and the forcing populations of the current state (either
+    density model).  The forcing populations are in the units of f: F_k for the
+    Boussinesq model, F_k / (rho c_s^2) for the variable-density one."""
+    F = force(phi, prm, phi_ref)
+    flat = prm.flat
+    if not prm.variable_density:
+        p_h, u = flow_moments(f, F, prm)
+        return p_h, u, F, [forcing_k(flat, k, u, F) for k in range(flat.Q)]
+    p_h, u, F = flow_moments_variable(f, phi, F, prm)
+    scale = 1.0 / (density(phi, prm) * flat.cs2)
+    return p_h, u, F, [forcing_k(flat, k, u, F) * scale for k in range(flat.Q)]
+
+
 def moments(st, prm):
     """All macroscopic fields of the current state: phi, c, mu, S, p_h, u, F."""
     m = scalar_moments(st, prm)
     zero = np.zeros_like(m["phi"])
     if prm.fluid:
-        F = force(m["phi"], prm, st.phi_ref)
-        p_h, u = flow_moments(st.f, F, prm)
+        p_h, u, F, _ = _flow(st.f, m["phi"], prm, st.phi_ref)
     else:
         F = [zero, zero, zero]
         p_h, u = zero, [zero, zero, zero]
@@ -333,8 +395,13 @@ def init(phi0, muA0, muB0, prm, phi_ref=None, c0=None):
     if prm.fluid:
         flat = prm.flat
         F0 = force(phi0, prm, phi_ref)
-        f = np.stack([f_equilibrium_k(flat, k, zero, u0, prm.rho0, forcing_k(flat, k, u0, F0))
-                      for k in range(flat.Q)])
+        if not prm.variable_density:
+            f = np.stack([f_equilibrium_k(flat, k, zero, u0, prm.rho0, forcing_k(flat, k, u0, F0))
+                          for k in range(flat.Q)])
+        else:  # dimensionless populations; at rest with p* = 0 the pressure and viscous forces vanish
+            scale = 1.0 / (density(phi0, prm) * flat.cs2)
+            f = np.stack([f_equilibrium_k(flat, k, zero, u0, 1.0 / flat.cs2, forcing_k(flat, k, u0, F0) * scale)
+                          for k in range(flat.Q)])
     return State(g=g, hA=hA, hB=hB, f=f, phi_ref=phi_ref, step=0)
 
 
@@ -346,8 +413,9 @@ def step(st, prm):
     zero = np.zeros_like(phi)
     if prm.fluid:
         flat = prm.flat
-        F = force(phi, prm, st.phi_ref)
-        p_h, u = flow_moments(st.f, F, prm)
+        p_h, u, F, Fk = _flow(st.f, phi, prm, st.phi_ref)
+        # pressure variable and inertia of the equilibrium (Eq. Feq, or its dimensionless form)
+        p_eq, rho_eq = (p_h, prm.rho0) if not prm.variable_density else (st.f.sum(axis=0), 1.0 / flat.cs2)
     else:
         u = [zero, zero, zero]
 
@@ -379,12 +447,11 @@ def step(st, prm):
     if prm.fluid:
         # f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq
         wf = rate(model.viscosity(phi, prm.nu), flat.cs2)
-        Fk = [forcing_k(flat, k, u, F) for k in range(flat.Q)]
         if not trt:
-            f_post = np.stack([st.f[k] - wf * (st.f[k] - f_equilibrium_k(flat, k, p_h, u, prm.rho0, Fk[k]))
+            f_post = np.stack([st.f[k] - wf * (st.f[k] - f_equilibrium_k(flat, k, p_eq, u, rho_eq, Fk[k]))
                                + Fk[k] for k in range(flat.Q)])
         else:  # the viscous stress is the symmetric part: nu sets w+
-            f_post = trt_collide(st.f, [f_equilibrium_k(flat, k, p_h, u, prm.rho0, Fk[k]) for k in range(flat.Q)],
+            f_post = trt_collide(st.f, [f_equilibrium_k(flat, k, p_eq, u, rho_eq, Fk[k]) for k in range(flat.Q)],
                                  Fk, flat, wf, trt_partner_rate(wf, lam_f))
         f_new = stream(f_post, flat, prm.bc)
 

@@ -575,6 +575,76 @@ def test_trt_conserves_mass_and_pressure_sum():
     assert d1["nan_count"] == 0
 
 
+# ----------------------------------------------------------------------------------------
+# variable-density flow (the rho(phi) alternative to Boussinesq named after Eq. Velocity)
+
+def test_variable_density_reduces_to_boussinesq():
+    """With equal densities the pressure and viscous forces vanish and the dimensionless
+    populations are the Boussinesq ones divided by rho0 c_s^2: same state to rounding."""
+    rng = np.random.default_rng(12)
+    common = dict(nx=30, ny=24, fluid="D2Q9", bc=("walls", "walls", "periodic"), W=4.0, lam=21.05,
+                  rho0=1.7, drho=0.0, g=(0, -1e-4, 0), sigma=2e-3, nu=(0.1, 0.05))
+    fields = _droplet_fields((1, 24, 30), [(15, 12, 0)], [6], 4.0, rng)
+    pb, pv = lbm.Params(**common), lbm.Params(**common, variable_density=True)
+    a = lbm.run(lbm.init(*fields, pb), pb, 40)
+    b = lbm.run(lbm.init(*fields, pv), pv, 40)
+    assert np.abs(b.f * (1.7 / 3.0) - a.f).max() < 1e-14
+    for k in ("g", "hA", "hB"):
+        assert np.abs(getattr(a, k) - getattr(b, k)).max() < 1e-14, k
+    ma, mb = lbm.moments(a, pb), lbm.moments(b, pv)
+    for k in ("p", "ux", "uy"):
+        assert np.abs(ma[k] - mb[k]).max() < 1e-14, k
+    assert np.abs(ma["ux"]).max() > 1e-6   # the capillary force drives a flow
+
+
+def _layered_channel_ode(N, W, phi_of, b_of, mu_of):
+    """Steady u_x(y) of d/dy (mu(y) du/dy) = -b(y) between walls at -1/2 and N - 1/2
+    (trapezoidal quadrature of the closed form on a fine grid)."""
+    ys = np.linspace(-0.5, N - 0.5, 100001)
+    ph = phi_of(ys)
+    b, inv = b_of(ph), 1.0 / mu_of(ph)
+    cum = lambda v: np.concatenate([[0.0], np.cumsum(0.5 * (v[1:] + v[:-1]) * np.diff(ys))])
+    B = cum(b)
+    I1, I2 = cum(inv), cum(B * inv)
+    u = I2[-1] / I1[-1] * I1 - I2
+    return np.interp(np.arange(N), ys, u)
+
+
+def test_variable_density_layered_channel():
+    """Two layers (density ratio 4, viscosity ratio 1/2) between walls, driven along the
+    layers by the buoyancy of the dense one: the steady profile solves
+    d/dy (rho nu du/dy) = -b with the dynamic viscosity rho(phi) nu(phi), which needs the
+    viscous force; the Boussinesq model's rho0 nu(phi) profile is far off."""
+    N, W, drho, nu, g = 24, 4.0, 3.0, (0.2, 0.1), 1e-6
+    y0 = N / 2 - 0.5
+    phi_of = lambda y: 0.5 * (1.0 + np.tanh(2.0 * (y0 - y) / W))
+    prm = lbm.Params(nx=2, ny=N, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=W, lam=21.05,
+                     drho=drho, g=(g, 0, 0), sigma=1e-3, nu=nu, variable_density=True)
+    phi0 = np.repeat(phi_of(np.arange(N))[None, :, None], 2, axis=2)
+    z = np.zeros_like(phi0)
+    st = lbm.run(lbm.init(phi0, z, z, prm), prm, 3000)
+    ux = lbm.moments(st, prm)["ux"][0, :, 0]
+    visc = lambda p: nu[0] * (1 - p) + nu[1] * p
+    ref = _layered_channel_ode(N, W, phi_of, lambda p: p * drho * g, lambda p: (1.0 + drho * p) * visc(p))
+    bous = _layered_channel_ode(N, W, phi_of, lambda p: p * drho * g, lambda p: 1.0 * visc(p))
+    assert np.abs(ux - ref).max() < 0.02 * ref.max()
+    assert np.abs(ux - bous).max() > 0.3 * bous.max()
+
+
+def test_variable_density_conserves_mass():
+    rng = np.random.default_rng(13)
+    prm = lbm.Params(nx=26, ny=22, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05,
+                     drho=2.0, g=(0, -1e-5, 0), sigma=1e-3, nu=(0.1, 0.05), variable_density=True,
+                     collision="TRT")
+    st = lbm.init(*_droplet_fields(prm.shape, [(13, 11, 0)], [5], 4.0, rng), prm)
+    d0 = lbm.diagnostics(st, prm)
+    st = lbm.run(st, prm, 60)
+    d1 = lbm.diagnostics(st, prm)
+    for key in ("sum_cA", "sum_cB"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * abs(d0[key]), key
+    assert d1["nan_count"] == 0 and d1["max_u"] > 0
+
+
 @pytest.mark.slow
 def test_laplace_pressure_jump():
     """Static 2D drop with no driving force: p_in - p_out = sigma / R (within the spurious
