@@ -35,6 +35,8 @@ WORKLOADS = {
     "ostwald_paper_2d_4096": dict(kind="ostwald_paper_2d", n=4096, precision="fp32"),
     # the two-relaxation-time collision on the sedimentation workload
     "sediment_3d_256_trt": dict(kind="sediment_3d", n=256, precision="fp32", collision="TRT"),
+    # the variable-density flow model (density ratio 1.5) on the sedimentation workload
+    "sediment_3d_256_vd": dict(kind="sediment_3d", n=256, precision="fp32", variable_density=True),
 }
 
 
@@ -52,8 +54,11 @@ def bytes_per_update(cfg):
 
 def build_workload(name):
     w = _build_workload(name)
-    if WORKLOADS[name].get("collision"):
-        w.params = dict(w.params, collision=WORKLOADS[name]["collision"], trt_magic=(3.0 / 16.0, 0.25))
+    spec = WORKLOADS[name]
+    if spec.get("collision"):
+        w.params = dict(w.params, collision=spec["collision"], trt_magic=(3.0 / 16.0, 0.25))
+    if spec.get("variable_density"):
+        w.params = dict(w.params, variable_density=True)
     return w
 
 

@@ -50,6 +50,16 @@ extern "C" {
 #define LBM_BGK 0
 #define LBM_TRT 1
 
+/* variable_density = 1 (needs a fluid lattice; FP64 / FP32 storage, no adjoint):
+ * the high-density-ratio form Section 3 names after Eq. Velocity.  rho(phi) =
+ * rho0 + drho phi enters the inertia; f holds dimensionless populations with
+ * zeroth moment p* = p_h / (rho c_s^2) and equilibrium w_k [p* + c_k.u / c_s^2 +
+ * (c_k.u)^2 / (2 c_s^4) - u.u / (2 c_s^2)] - F_k / 2, F_k the forcing population
+ * divided by rho c_s^2; the pressure force -p* c_s^2 grad rho and the viscous
+ * force -(nu w+ / c_s^2) Pi . grad rho (Pi the second moment of f - f^eq at the
+ * predictor velocity sum_k f_k c_k + (F_s + F_b + F_p) / (2 rho)) join the total
+ * force.  Buoyancy stays (phi - phi_ref) drho g.  lbm_moments reports p_h. */
+
 #define LBM_PERIODIC 0
 #define LBM_WALLS 1           /* half-way bounce-back walls at both ends of an axis */
 
@@ -120,7 +130,7 @@ typedef struct lbm_config {
     double store_ref[4];       /* 16-bit storage: reference per field f, g, hA, hB  */
     int32_t store_shift[4];    /* 16-bit storage: power-of-two scale per field      */
     int32_t collision;         /* LBM_BGK (the paper's, 0) or LBM_TRT               */
-    int32_t reserved;          /* 0                                                 */
+    int32_t variable_density;  /* 0: Boussinesq (the paper's); 1: rho(phi) model    */
     double trt_magic[2];       /* LBM_TRT: Lambda of f and of g, h^A, h^B (> 0)     */
 } lbm_config;
 

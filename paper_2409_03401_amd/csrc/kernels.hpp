@@ -314,6 +314,8 @@ k_lbm(const KParams P) {
     constexpr int NT = TX * TY;
     constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
     constexpr C inv_cs2s = C(1.0 / SL::cs2);
+    constexpr bool TRTC = (COLL & COLL_TRT) != 0;
+    constexpr bool VD = FLOW && (COLL & COLL_VD) != 0;
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
     // the private LDS ring of scalar populations, unless it would not leave room for
     // a second work-group per compute unit (the paper's D3Q19 scalar lattice)
@@ -576,8 +578,9 @@ k_lbm(const KParams P) {
             }
 
             C u[3] = {C(0), C(0), C(0)};
-            C p_h = C(0);
+            C p_h = C(0);  // pressure variable of f: p_h, or p* with variable density
             C F[3] = {C(0), C(0), C(0)};
+            C irho = C(1);  // 1 / rho(phi) (variable density)
             if constexpr (FLOW) {
                 // Eq. SurfaceTension_Force plus buoyancy (phi - phi_ref) drho g
                 const C bracket = KC(P.cap, P.f32.cap) * (C(dwell_d(m.phi)) * KC(P.inv_W2, P.f32.inv_W2) - lap);
@@ -594,10 +597,49 @@ k_lbm(const KParams P) {
                     if constexpr (FL::ey(k) != 0) j1 += FL::ey(k) > 0 ? fpop[k] : -fpop[k];
                     if constexpr (FL::ez(k) != 0) j2 += FL::ez(k) > 0 ? fpop[k] : -fpop[k];
                 });
-                const C inv_rho0 = KC(1.0 / P.rho0, P.f32.inv_rho0);
-                u[0] = (C(3) * j0 + C(0.5) * F[0]) * inv_rho0;
-                u[1] = (C(3) * j1 + C(0.5) * F[1]) * inv_rho0;
-                u[2] = (C(3) * j2 + C(0.5) * F[2]) * inv_rho0;
+                if constexpr (!VD) {
+                    const C inv_rho0 = KC(1.0 / P.rho0, P.f32.inv_rho0);
+                    u[0] = (C(3) * j0 + C(0.5) * F[0]) * inv_rho0;
+                    u[1] = (C(3) * j1 + C(0.5) * F[1]) * inv_rho0;
+                    u[2] = (C(3) * j2 + C(0.5) * F[2]) * inv_rho0;
+                } else {
+                    // variable density: f is dimensionless, p_h holds p* = sum f; rho(phi)
+                    // interpolated; pressure force -p* c_s^2 grad rho; predictor velocity;
+                    // viscous force -(nu w+ / c_s^2) Pi . grad rho from the non-equilibrium
+                    // second moment at the predictor; final velocity
+                    const C drho = KC(P.drho, P.f32.drho);
+                    irho = rcp<C>(KC(P.rho0, P.f32.rho0) + drho * phi);
+                    const C fp = -p_h * C(1.0 / 3.0) * drho;
+                    C us[3];
+                    us[0] = j0 + C(0.5) * (F[0] + fp * grad[0]) * irho;
+                    us[1] = j1 + C(0.5) * (F[1] + fp * grad[1]) * irho;
+                    us[2] = j2 + C(0.5) * (F[2] + fp * grad[2]) * irho;
+                    const C uus = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+                    const C e0s = p_h - C(1.5) * uus;
+                    C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+                    static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                        constexpr int k = decltype(kc)::value;
+                        constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
+                        const C eu = edot<ex, ey, ez>(us[0], us[1], us[2]);
+                        const C n = fpop[k] - C(FL::w(k)) * (e0s + eu * (C(3) + C(4.5) * eu));
+                        if constexpr (ex != 0) pxx += n;
+                        if constexpr (ey != 0) pyy += n;
+                        if constexpr (ez != 0) pzz += n;
+                        if constexpr (ex != 0 && ey != 0) pxy += ex * ey > 0 ? n : -n;
+                        if constexpr (ex != 0 && ez != 0) pxz += ex * ez > 0 ? n : -n;
+                        if constexpr (ey != 0 && ez != 0) pyz += ey * ez > 0 ? n : -n;
+                    });
+                    const C nuv = KC(P.nu0, P.f32.nu0) * (C(1) - phi) + KC(P.nu1, P.f32.nu1) * phi;
+                    const C coef = -C(3) * nuv * rcp<C>(C(3) * nuv + C(0.5)) * drho;
+                    const C Fm[3] = {coef * (pxx * grad[0] + pxy * grad[1] + pxz * grad[2]),
+                                     coef * (pxy * grad[0] + pyy * grad[1] + pyz * grad[2]),
+                                     coef * (pxz * grad[0] + pyz * grad[1] + pzz * grad[2])};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        u[a] = us[a] + C(0.5) * Fm[a] * irho;
+                        F[a] += fp * grad[a] + Fm[a];
+                    }
+                }
             }
 
             if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_PHI) {
@@ -627,9 +669,13 @@ k_lbm(const KParams P) {
                     const C nu = KC(P.nu0, P.f32.nu0) * (C(1) - phi) + KC(P.nu1, P.f32.nu1) * phi;
                     const C wf = rcp<C>(C(3) * nu + C(0.5));
                     const C keep = C(1) - wf, half = C(1) - C(0.5) * wf;
-                    const C rho0 = KC(P.rho0, P.f32.rho0);
+                    // inertia of the equilibrium: rho0 (Eq. Feq), or 1 / c_s^2 for the
+                    // dimensionless populations of the variable-density model, whose
+                    // forcing populations are divided by rho c_s^2
+                    const C rho0 = VD ? C(3) : KC(P.rho0, P.f32.rho0);
                     const C g0 = C(1) - C(1.5) * uu, e0 = p_h - C(0.5) * rho0 * uu;
-                    if constexpr (COLL == COLL_BGK) {
+                    const C fsc = VD ? C(3) * irho : C(1);
+                    if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
@@ -638,7 +684,7 @@ k_lbm(const KParams P) {
                         const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
                         const C eF = edot<ex, ey, ez>(F[0], F[1], F[2]);
                         const C gam = wk * (g0 + eu * (C(3) + C(4.5) * eu));
-                        const C Fk = gam * (eF - uF);
+                        const C Fk = VD ? gam * (eF - uF) * fsc : gam * (eF - uF);
                         const C feq = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu));
                         const C v = keep * fpop[k] + wf * feq + half * Fk;
                         if constexpr (k == 0 && FEEDBACK) rest = v;
@@ -657,6 +703,7 @@ k_lbm(const KParams P) {
                             const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
                             const C eF = edot<ex, ey, ez>(F[0], F[1], F[2]);
                             Fk = wk * (g0 + eu * (C(3) + C(4.5) * eu)) * (eF - uF);
+                            if constexpr (VD) Fk *= fsc;
                             eqs = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu)) - C(0.5) * Fk;
                         };
                         static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
@@ -687,7 +734,7 @@ k_lbm(const KParams P) {
                     const C keep = C(1) - wg;
                     const C wphi = wg * phi;
                     const C srcS = (C(1) - C(0.5) * wg) * C(m.S);
-                    if constexpr (COLL == COLL_BGK) {
+                    if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
@@ -738,7 +785,7 @@ k_lbm(const KParams P) {
                     const C MB = KC(P.MB0, P.f32.MB0) * (C(1) - phi) + KC(P.MB1, P.f32.MB1) * phi;
                     const C wA = rcp<C>(MA * inv_cs2s + C(0.5));
                     const C wB = rcp<C>(MB * inv_cs2s + C(0.5));
-                    if constexpr (COLL == COLL_TRT) {
+                    if constexpr (TRTC) {
                         // TRT: the mobility sets the antisymmetric rate w- = wA (wB); w+ from
                         // the magic parameter, 1/w+ - 1/2 = Lambda_s / (M / c_s^2)
                         const C ls = KC(P.trt_ls, P.f32.trt_ls);
@@ -798,7 +845,9 @@ k_lbm(const KParams P) {
                 }
 
             } else if constexpr (MODE == MODE_MOMENTS) {
-                const double vals[kNumMom] = {m.phi, sA, sB, m.muA, m.muB, double(p_h),
+                // hydrodynamic pressure: p_h, or rho c_s^2 p* with variable density
+                const double p_out = VD ? double(p_h) / (3.0 * double(irho)) : double(p_h);
+                const double vals[kNumMom] = {m.phi, sA, sB, m.muA, m.muB, p_out,
                                               double(u[0]), double(u[1]), double(u[2])};
 #pragma unroll
                 for (int i = 0; i < kNumMom; ++i) {
@@ -1006,9 +1055,11 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
         const double F[3] = {buoy * P.gx + bracket * grad[0], buoy * P.gy + bracket * grad[1],
                              buoy * P.gz + bracket * grad[2]};
         double rf = 0.0;
+        // variable density: dimensionless populations, forcing divided by rho(phi) c_s^2
+        const double fsc = P.variable_density ? 3.0 / (P.rho0 + P.drho * phi) : 1.0;
         static_for<1, FL::Q>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const double eF = FL::ex(k) * F[0] + FL::ey(k) * F[1] + FL::ez(k) * F[2];
+            const double eF = (FL::ex(k) * F[0] + FL::ey(k) * F[1] + FL::ez(k) * F[2]) * fsc;
             // f^eq at p_h = 0, u = 0 minus F_k / 2 with Gamma_k(u = 0) = w_k
             rf += put(kc, kc, std::common_type<FL>{}, -0.5 * FL::w(k) * eF);
         });

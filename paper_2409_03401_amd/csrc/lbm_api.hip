@@ -73,6 +73,11 @@ int check_config(const lbm_config* c, Layout* L) {
     if (c->collision != LBM_BGK && c->collision != LBM_TRT)
         return fail(LBM_EINVAL, "collision must be LBM_BGK or LBM_TRT");
     const bool trt = c->collision == LBM_TRT;
+    if (c->variable_density != 0 && c->variable_density != 1)
+        return fail(LBM_EINVAL, "variable_density must be 0 or 1");
+    const bool vd = c->variable_density == 1;
+    if (vd && c->fluid == LBM_NONE) return fail(LBM_EINVAL, "variable_density needs a fluid lattice");
+    if (vd && !(c->rho0 + c->drho > 0)) return fail(LBM_EINVAL, "variable_density needs rho0 + drho > 0");
     if (trt)
         for (double m : {c->trt_magic[0], c->trt_magic[1]})
             if (!(std::isfinite(m) && m > 0)) return fail(LBM_EINVAL, "trt_magic must be finite and > 0");
@@ -141,7 +146,10 @@ int check_config(const lbm_config* c, Layout* L) {
     // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
     int want_tx = 0, want_ty = 0;
     if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
-    if (trt) {
+    if (vd) {
+        L->ks = L->dim == 2 ? kernels_vd_2d(L->qs, trt, L->prec) : kernels_vd_3d(L->qs, trt, L->prec);
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with FP64 or FP32 storage");
+    } else if (trt) {
         L->ks = L->dim == 2 ? kernels_trt_2d(L->qs, L->qf, L->prec) : kernels_trt_3d(L->qs, L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "the TRT collision runs with FP64 or FP32 storage");
     } else if (paper_scalar) {
@@ -232,6 +240,7 @@ void fill_params(lbm_handle* h) {
     kp.f32.trt_lf = float(kp.trt_lf);
     kp.f32.trt_ls = float(kp.trt_ls);
     kp.f32.omega_gp = float(kp.omega_gp);
+    kp.variable_density = c.variable_density;
     kp.MA0 = c.M_A[0]; kp.MA1 = c.M_A[1]; kp.MB0 = c.M_B[0]; kp.MB1 = c.M_B[1];
     kp.nu0 = c.nu[0]; kp.nu1 = c.nu[1];
     kp.rho0 = L.qf ? c.rho0 : 1.0;

@@ -17,7 +17,8 @@ enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
 // MODE_STEP_PHI: a step that also writes phi of its source state (P.phi_out)
 enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_STEP_PHI = 3 };
 // collision operator of the fused step: the paper's BGK, or two relaxation times
-enum Coll : int { COLL_BGK = 0, COLL_TRT = 1 };
+// (flags): COLL_TRT two relaxation times, COLL_VD the variable-density flow model
+enum Coll : int { COLL_BGK = 0, COLL_TRT = 1, COLL_VD = 2 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -47,6 +48,7 @@ struct KParams {
     double omega_g;              // g-lattice rate 1 / (M_phi / c_s^2 + 1/2)
     // TRT (COLL_TRT): magic parameters of f and of the scalar lattices; symmetric rate of g
     double trt_lf, trt_ls, omega_gp;
+    int variable_density;        // 1: f holds dimensionless populations (rho(phi) model)
     double MA0, MA1, MB0, MB1;   // species mobilities per phase
     double nu0, nu1, rho0, drho;
     double gx, gy, gz;           // gravity in the kernel frame

@@ -56,7 +56,7 @@ class _Config(ctypes.Structure):
         ("rho0", ctypes.c_double), ("drho", ctypes.c_double), ("g", ctypes.c_double * 3),
         ("sigma", ctypes.c_double), ("nu", ctypes.c_double * 2),
         ("store_ref", ctypes.c_double * 4), ("store_shift", ctypes.c_int32 * 4),
-        ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32), ("trt_magic", ctypes.c_double * 2),
+        ("collision", ctypes.c_int32), ("variable_density", ctypes.c_int32), ("trt_magic", ctypes.c_double * 2),
     ]
 
 
@@ -150,6 +150,8 @@ class LBMConfig:
     # "BGK" (the paper's) or "TRT"; TRT magic parameters of (f, the scalar lattices)
     collision: str = "BGK"
     trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)
+    # False: Boussinesq (the paper's); True: rho(phi) model with pressure and viscous forces
+    variable_density: bool = False
 
     @property
     def nodes(self):
@@ -188,6 +190,7 @@ class LBMConfig:
             c.store_ref[i] = self.store_ref[i]
             c.store_shift[i] = int(self.store_shift[i])
         c.collision = _COLLISION[self.collision]
+        c.variable_density = int(bool(self.variable_density))
         c.trt_magic[0], c.trt_magic[1] = float(self.trt_magic[0]), float(self.trt_magic[1])
         return c
 

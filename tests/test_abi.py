@@ -74,6 +74,9 @@ def test_state_bytes_layout():
     (dict(collision="TRT", precision="bf16"), lbm.LBM_EUNSUPPORTED),   # TRT: FP64 / FP32
     (dict(collision="TRT", trt_magic=(0.0, 0.25)), lbm.LBM_EINVAL),
     (dict(collision="TRT", trt_magic=(0.25, float("inf"))), lbm.LBM_EINVAL),
+    (dict(variable_density=True), lbm.LBM_EINVAL),                     # needs a fluid lattice
+    (dict(variable_density=True, fluid="D2Q9", drho=-1.0), lbm.LBM_EINVAL),  # rho(1) = 0
+    (dict(variable_density=True, fluid="D2Q9", precision="fp16"), lbm.LBM_EUNSUPPORTED),
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:

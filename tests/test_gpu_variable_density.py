@@ -1,0 +1,157 @@
+"""The variable-density flow model on the GPU (variable_density = 1), against the
+FP64 oracle's model (oracle/lbm.py, flow_moments_variable) on the same seeded inputs.
+
+Bars as for the Boussinesq model: FP64 populations within 1e-12, FP32 relative L2
+within 1e-5 on phi, c^A, c^B and the populations.  Properties at sizes of their own:
+equal densities reproduce the Boussinesq state (f scaled by rho0 c_s^2), and a layered
+channel with density ratio 4 follows d/dy (rho(phi) nu(phi) du/dy) = -b.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from helpers import (MOMENT_NAMES, field_errors, gpu_config, max_abs, oracle_moments, oracle_params,
+                     oracle_populations, rel_l2)
+from oracle import lbm as olbm
+from paper_2409_03401_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _drops(shape, n, rmin, rmax, W, seed, wall_axes=()):
+    rng = np.random.default_rng(seed)
+    drops = inputs.place_droplets(shape, n, rmin, rmax, W, rng, wall_axes=wall_axes)
+    phi = inputs.droplet_field(shape, drops, W, wall_axes=wall_axes)
+    mu = rng.normal(0.0, 1e-3, (2,) + shape)
+    return phi, mu[0], mu[1]
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    """(params, phi0, muA0, muB0, steps): density ratio 4, viscosity ratio 1/2."""
+    vd2 = dict(fluid="D2Q9", drho=3.0, g=(0.0, -2e-5, 0.0), sigma=1e-3, nu=(0.1, 0.05), variable_density=True)
+    vd3 = dict(fluid="D3Q19", drho=3.0, g=(0.0, 0.0, -2e-5), sigma=1e-3, nu=(0.1, 0.05), variable_density=True)
+    if name == "2d_bgk_walls":
+        p = inputs._base(70, 48, 1, W=4.0, bc=("periodic", "walls", "periodic"), **vd2)
+        return (p, *_drops((1, 48, 70), 3, 5.0, 9.0, 4.0, 61, (1,)), 60)
+    if name == "2d_trt_d2q9":
+        p = inputs._base(64, 50, 1, W=4.0, scalar="D2Q9", bc=("walls", "walls", "periodic"), collision="TRT",
+                         trt_magic=(3.0 / 16.0, 0.25), **vd2)
+        return (p, *_drops((1, 50, 64), 2, 5.0, 8.0, 4.0, 62, (0, 1)), 50)
+    if name == "3d_bgk_walls":
+        p = inputs._base(21, 19, 20, W=4.0, bc=("periodic", "periodic", "walls"), **vd3)
+        return (p, *_drops((20, 19, 21), 1, 4.0, 5.0, 4.0, 63, (2,)), 12)
+    if name == "3d_trt_d3q19":
+        p = inputs._base(18, 20, 19, W=4.0, scalar="D3Q19", bc=("walls", "periodic", "walls"), collision="TRT",
+                         trt_magic=(3.0 / 16.0, 0.25), **vd3)
+        return (p, *_drops((19, 20, 18), 1, 4.0, 5.0, 4.0, 64, (0, 2)), 10)
+    raise KeyError(name)
+
+
+CASES = ["2d_bgk_walls", "2d_trt_d2q9", "3d_bgk_walls", "3d_trt_d3q19"]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name):
+    p, phi0, muA0, muB0, steps = case(name)
+    prm = oracle_params(p)
+    st = olbm.run(olbm.init(phi0, muA0, muB0, prm), prm, steps)
+    return oracle_moments(prm, st), oracle_populations(prm, st)
+
+
+def _gpu(name, precision):
+    from paper_2409_03401_amd.lbm import Simulation
+    p, phi0, muA0, muB0, steps = case(name)
+    print(f"[variable density] {name} shape={phi0.shape} {precision} steps={steps}", flush=True)
+    sim = Simulation(gpu_config(p, precision), phi0, muA0, muB0)
+    sim.step(steps)
+    return {k: v.cpu().numpy() for k, v in sim.moments().items()}, sim.populations().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_vd_parity_fp64(name):
+    _require_gpu()
+    mom, pops = _gpu(name, "fp64")
+    ora_m, ora_p = oracle_case(name)
+    err = max_abs(pops, ora_p)
+    assert err <= 1e-12, err
+    for k in MOMENT_NAMES:
+        assert max_abs(mom[k], ora_m[k]) <= 1e-12 * max(1.0, np.abs(ora_m[k]).max()), k
+    assert np.abs(ora_m["ux"]).max() > 1e-7   # a flow develops
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_vd_parity_fp32(name):
+    _require_gpu()
+    mom, pops = _gpu(name, "fp32")
+    ora_m, ora_p = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("phi", "cA", "cB"):
+        assert errs[k][0] <= 1e-5, (k, errs[k])
+    assert rel_l2(pops, ora_p) <= 1e-5
+
+
+def test_vd_equal_densities_is_boussinesq():
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    p, phi0, muA0, muB0, _ = case("2d_bgk_walls")
+    base = dict(p, drho=0.0, rho0=1.7, sigma=3e-3)
+    a = Simulation(gpu_config(dict(base, variable_density=False), "fp64"), phi0, muA0, muB0)
+    b = Simulation(gpu_config(base, "fp64"), phi0, muA0, muB0)
+    a.step(40)
+    b.step(40)
+    pa, pb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+    assert np.abs(pb[:9] * (1.7 / 3.0) - pa[:9]).max() < 1e-13
+    assert np.abs(pb[9:] - pa[9:]).max() < 1e-13
+    ma, mb = a.moments(("p", "ux", "uy")), b.moments(("p", "ux", "uy"))
+    for k in ("p", "ux", "uy"):
+        assert torch.allclose(ma[k], mb[k], rtol=0, atol=1e-13), k
+
+
+@pytest.mark.parametrize("N,steps,bar", [(24, 3000, 0.02), (48, 12000, 0.01)])
+def test_vd_layered_channel(N, steps, bar):
+    """Two layers, density ratio 4, viscosity ratio 1/2, driven along the layers by the
+    buoyancy of the dense one: steady profile of d/dy (rho nu du/dy) = -b."""
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    W, drho, nu, g = 4.0, 3.0, (0.2, 0.1), 1e-6
+    y0 = N / 2 - 0.5
+    phi_of = lambda y: 0.5 * (1.0 + np.tanh(2.0 * (y0 - y) / W))
+    p = inputs._base(64, N, 1, W=W, fluid="D2Q9", bc=("periodic", "walls", "periodic"), drho=drho,
+                     g=(g, 0.0, 0.0), sigma=1e-3, nu=nu, variable_density=True)
+    phi0 = np.repeat(phi_of(np.arange(N))[None, :, None], 64, axis=2)
+    z = np.zeros_like(phi0)
+    sim = Simulation(gpu_config(p, "fp64"), phi0, z, z.copy())
+    sim.step(steps)
+    ux = sim.moments(("ux",))["ux"].cpu().numpy()[0]
+    ys = np.linspace(-0.5, N - 0.5, 100001)
+    ph = phi_of(ys)
+    cum = lambda v: np.concatenate([[0.0], np.cumsum(0.5 * (v[1:] + v[:-1]) * np.diff(ys))])
+    inv = 1.0 / ((1.0 + drho * ph) * (nu[0] * (1 - ph) + nu[1] * ph))
+    B = cum(ph * drho * g)
+    I1, I2 = cum(inv), cum(B * inv)
+    ref = np.interp(np.arange(N), ys, I2[-1] / I1[-1] * I1 - I2)
+    err = np.abs(ux - ref[:, None]).max() / ref.max()
+    print(f"  layered channel N={N}: max relative error {err:.2e}", flush=True)
+    assert err < bar
+
+
+def test_vd_unsupported():
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import LBM_EUNSUPPORTED, LBMError, Simulation
+    p, phi0, muA0, muB0, _ = case("2d_bgk_walls")
+    sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
+    work = sim.adjoint_workspace()
+    with pytest.raises(LBMError) as e:
+        sim.adjoint_seed(sim.save(), np.zeros(phi0.size), work)
+    assert e.value.code == LBM_EUNSUPPORTED
