@@ -65,6 +65,9 @@ class Params:
     gravity_mean_subtract: bool = False
     collision: str = "BGK"                      # "BGK" (the paper's) or "TRT"
     variable_density: bool = False              # False: Boussinesq (the paper's); True: rho(phi)
+    # general curvatures: ((k_AA, k_AB, k_BB) of phase 0, same of phase 1) = K (K_pi)^-1;
+    # None is the paper's K_pi = K identity
+    kappa: Optional[Tuple[Tuple[float, float, float], Tuple[float, float, float]]] = None
     trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)   # TRT Lambda of (f, the scalar lattices)
 
     @property
@@ -257,10 +260,10 @@ def scalar_moments(st, prm):
     cA = st.hA.sum(axis=0)                               # Eq. Moment0_c_alpha
     cB = st.hB.sum(axis=0)
     phi_star = st.g.sum(axis=0)                          # sum_k g_k
-    mu_star = model.closure_mu((cA, cB), phi_star, prm.c_eq)
+    mu_star = model.closure_mu((cA, cB), phi_star, prm.c_eq, prm.kappa)
     S_star = model.source_phi(phi_star, mu_star, prm)
     phi = phi_star + 0.5 * S_star                        # Eq. Moment0_Phi (predictor)
-    mu = model.closure_mu((cA, cB), phi, prm.c_eq)       # Eq. PotChem
+    mu = model.closure_mu((cA, cB), phi, prm.c_eq, prm.kappa)   # Eq. PotChem
     S = model.source_phi(phi, mu, prm)                   # Eq. SourceTerm_Phi
     return dict(phi=phi, phi_star=phi_star, cA=cA, cB=cB, muA=mu[0], muB=mu[1], S=S)
 
@@ -379,7 +382,7 @@ def init(phi0, muA0, muB0, prm, phi_ref=None, c0=None):
     phi0 = phi0.reshape(shape)
     mu0 = (np.asarray(muA0).reshape(shape), np.asarray(muB0).reshape(shape))
     if c0 is None:
-        c = model.closure_c(mu0, phi0, prm.c_eq)
+        c = model.closure_c(mu0, phi0, prm.c_eq, prm.kappa)
     else:
         c = (np.asarray(c0[0]).reshape(shape), np.asarray(c0[1]).reshape(shape))
     S0 = model.source_phi(phi0, mu0, prm)
@@ -488,7 +491,8 @@ def diagnostics(st, prm):
     u2 = m["ux"] ** 2 + m["uy"] ** 2 + m["uz"] ** 2
     grad = gradient(phi, prm.bc, prm.stencil_lattice)
     g2 = grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2
-    fe = 0.5 * prm.W ** 2 * g2 + model.omega_dw(phi) + 0.5 * prm.lam * (m["muA"] ** 2 + m["muB"] ** 2)
+    fe = 0.5 * prm.W ** 2 * g2 + model.omega_dw(phi) + prm.lam * model.bulk_free_energy((m["muA"], m["muB"]), phi,
+                                                                                          prm.kappa)
     bad = ~(np.isfinite(phi) & np.isfinite(m["cA"]) & np.isfinite(m["cB"]))
     n_drops = geometry.euler_characteristic(phi.real, prm.bc)
     return dict(sum_cA=m["cA"].sum(), sum_cB=m["cB"].sum(), sum_phi=phi.sum(),

@@ -645,6 +645,105 @@ def test_variable_density_conserves_mass():
     assert d1["nan_count"] == 0 and d1["max_u"] > 0
 
 
+# ----------------------------------------------------------------------------------------
+# general curvature matrices K_pi (Eq. Taylor with a full matrix; the paper's model has
+# K_pi = K identity)
+
+KAPPA = ((1.0, 0.2, 0.8), (0.6, -0.1, 1.3))   # (k_AA, k_AB, k_BB) of phases 0 and 1
+C_EQ = ((0.2, 0.1), (0.6, 0.3))
+
+
+def _legendre_numeric(mu, c_eq_pi, kappa_pi):
+    """omega(mu) = min_c [f(c) - mu . c] with f(c) = 1/2 (c - c_eq) . K^-1 (c - c_eq),
+    by numerical minimisation (independent of the closed form)."""
+    from scipy.optimize import minimize
+    kAA, kAB, kBB = kappa_pi
+    Kinv = np.linalg.inv(np.array([[kAA, kAB], [kAB, kBB]]))
+    ce = np.array(c_eq_pi)
+    fun = lambda c: 0.5 * (c - ce) @ Kinv @ (c - ce) - np.dot(mu, c)
+    r = minimize(fun, ce, method="BFGS", options=dict(gtol=1e-13))
+    return r.fun, r.x
+
+
+def test_general_curvature_grand_potential_is_the_legendre_transform():
+    rng = np.random.default_rng(14)
+    for _ in range(5):
+        mu = rng.uniform(-0.1, 0.1, 2)
+        for pi in range(2):
+            w_num, c_num = _legendre_numeric(mu, C_EQ[pi], KAPPA[pi])
+            assert abs(model.grand_potential(tuple(mu), C_EQ[pi], KAPPA[pi]) - w_num) < 1e-12
+            c = model.closure_c(tuple(mu), float(pi), C_EQ, KAPPA)  # phi = 0 or 1: the pure phase
+            np.testing.assert_allclose(c, c_num, atol=1e-7)
+
+
+def test_general_curvature_closure():
+    """c = -d omega / d mu of the interpolated grand potential (complex step), and
+    closure_mu inverts closure_c; identity curvatures give the paper's closure."""
+    rng = np.random.default_rng(15)
+    phi = rng.uniform(0, 1, 6)
+    mu = (rng.uniform(-0.1, 0.1, 6), rng.uniform(-0.1, 0.1, 6))
+    c = model.closure_c(mu, phi, C_EQ, KAPPA)
+    h = 1e-30
+    for a in range(2):
+        mp = [mu[0] + 0j, mu[1] + 0j]
+        mp[a] = mp[a] + 1j * h
+        om = (1 - model.p(phi)) * model.grand_potential(mp, C_EQ[0], KAPPA[0]) + \
+            model.p(phi) * model.grand_potential(mp, C_EQ[1], KAPPA[1])
+        np.testing.assert_allclose(-om.imag / h, c[a], rtol=1e-13)
+    back = model.closure_mu(c, phi, C_EQ, KAPPA)
+    np.testing.assert_allclose(back[0], mu[0], atol=1e-15)
+    np.testing.assert_allclose(back[1], mu[1], atol=1e-15)
+    ident = ((1.0, 0.0, 1.0), (1.0, 0.0, 1.0))
+    np.testing.assert_allclose(model.closure_mu(c, phi, C_EQ, ident), model.closure_mu(c, phi, C_EQ), atol=1e-15)
+    np.testing.assert_allclose(model.delta_omega(mu, C_EQ, ident), model.delta_omega(mu, C_EQ), atol=1e-16)
+
+
+def test_general_curvature_flat_interface_coexistence():
+    """A flat interface with uniform mu on the coexistence line Delta omega(mu) = 0 stays
+    put; shifted off it, phase 1 grows when Delta omega > 0 and shrinks when < 0."""
+    from scipy.optimize import brentq
+    muB = 0.02
+    muA = brentq(lambda a: model.delta_omega((a, muB), C_EQ, KAPPA), -0.2, 0.2)
+    nx = 48
+    x = np.arange(nx) - (nx - 1) / 2.0
+    phi0 = (0.5 * (1.0 + np.tanh(2.0 * x / 4.0))).reshape(1, 1, nx)
+    prm = lbm.Params(nx=nx, ny=1, bc=("walls", "periodic", "periodic"), W=4.0, lam=2.0, M_phi=0.1,
+                     M_A=(0.1, 0.1), M_B=(0.1, 0.1), c_eq=C_EQ, kappa=KAPPA)
+    moved = {}
+    for shift in (0.0, 0.01, -0.01):
+        m0 = np.full_like(phi0, muA + shift)
+        st = lbm.init(phi0, m0, np.full_like(phi0, muB), prm)
+        s0 = lbm.diagnostics(st, prm)["sum_phi"]
+        st = lbm.run(st, prm, 300)
+        moved[shift] = lbm.diagnostics(st, prm)["sum_phi"] - s0
+    d_plus = model.delta_omega((muA + 0.01, muB), C_EQ, KAPPA)
+    # at coexistence only the start-up transient moves the interface (unequal
+    # curvatures make it asymmetric): 2% of the motion off coexistence
+    assert abs(moved[0.0]) < 5e-3
+    assert np.sign(moved[0.01]) == np.sign(d_plus) and abs(moved[0.01]) > 20 * abs(moved[0.0])
+    assert np.sign(moved[-0.01]) == -np.sign(d_plus) and abs(moved[-0.01]) > 20 * abs(moved[0.0])
+
+
+def test_general_curvature_run_conserves_and_matches_identity():
+    rng = np.random.default_rng(16)
+    common = dict(nx=28, ny=22, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05,
+                  drho=0.5, g=(0, -1e-4, 0), sigma=1e-3, nu=(0.1, 0.05))
+    fields = _droplet_fields((1, 22, 28), [(14, 11, 0)], [6], 4.0, rng)
+    a = lbm.Params(**common)
+    b = lbm.Params(**common, kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0)))
+    sa = lbm.run(lbm.init(*fields, a), a, 30)
+    sb = lbm.run(lbm.init(*fields, b), b, 30)
+    for k in ("f", "g", "hA", "hB"):
+        assert np.abs(getattr(sa, k) - getattr(sb, k)).max() < 1e-13, k
+    c = lbm.Params(**common, kappa=KAPPA)
+    st = lbm.init(*fields, c)
+    d0 = lbm.diagnostics(st, c)
+    st = lbm.run(st, c, 40)
+    d1 = lbm.diagnostics(st, c)
+    for key in ("sum_cA", "sum_cB"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * abs(d0[key]), key
+
+
 @pytest.mark.slow
 def test_laplace_pressure_jump():
     """Static 2D drop with no driving force: p_in - p_out = sigma / R (within the spurious
