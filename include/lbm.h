@@ -50,6 +50,15 @@ extern "C" {
 #define LBM_BGK 0
 #define LBM_TRT 1
 
+/* general_kappa = 1 (FP64 / FP32 storage, BGK, Boussinesq, no adjoint): the
+ * quadratic free energies of Eq. Taylor with full curvature matrices K_pi, given
+ * as kappa_pi = K (K_pi)^-1 (symmetric positive definite; the identity is the
+ * paper's model).  The grand potentials become -1/2 mu.kappa_pi mu - mu.c_pi^eq,
+ * so the closure is c = c^eq(phi) + kappa(phi) mu with kappa(phi) = kappa_0 +
+ * p(phi) (kappa_1 - kappa_0), solved for mu per node (2 x 2), Delta omega gains
+ * -1/2 mu.(kappa_0 - kappa_1) mu, and the free-energy diagnostic uses
+ * 1/2 mu.kappa(phi) mu.  lbm_init takes mu_0 and derives c from this closure. */
+
 /* variable_density = 1 (needs a fluid lattice; FP64 / FP32 storage, no adjoint):
  * the high-density-ratio form Section 3 names after Eq. Velocity.  rho(phi) =
  * rho0 + drho phi enters the inertia; f holds dimensionless populations with
@@ -132,6 +141,9 @@ typedef struct lbm_config {
     int32_t collision;         /* LBM_BGK (the paper's, 0) or LBM_TRT               */
     int32_t variable_density;  /* 0: Boussinesq (the paper's); 1: rho(phi) model    */
     double trt_magic[2];       /* LBM_TRT: Lambda of f and of g, h^A, h^B (> 0)     */
+    int32_t general_kappa;     /* 0: the paper's K_pi = K identity; 1: kappa below  */
+    int32_t reserved;          /* 0                                                 */
+    double kappa[2][3];        /* per phase (k_AA, k_AB, k_BB) = K (K_pi)^-1        */
 } lbm_config;
 
 typedef struct lbm_handle lbm_handle;

@@ -39,6 +39,9 @@ const KernelSet* kernels_trt_3d(int scalar, int fluid, int prec);
 // the variable-density flow model (needs the fluid lattice): FP64 / FP32, no adjoint
 const KernelSet* kernels_vd_2d(int scalar, bool trt, int prec);
 const KernelSet* kernels_vd_3d(int scalar, bool trt, int prec);
+// general curvature matrices of the free energies (BGK, Boussinesq): FP64 / FP32, no adjoint
+const KernelSet* kernels_gk_2d(int scalar, int fluid, int prec);
+const KernelSet* kernels_gk_3d(int scalar, int fluid, int prec);
 
 void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
 void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,

@@ -20,10 +20,10 @@ struct Family {
                 hipLaunchKernelGGL((k_lbm<SL, FL, MODE_STEP_PHI, PREC, TX, TY, COLL>), grid, block, 0, s, kp);
                 break;
             case MODE_MOMENTS:
-                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_MOMENTS, PREC, TX, TY, (COLL & COLL_VD)>), grid, block, 0, s, kp);
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_MOMENTS, PREC, TX, TY, (COLL & (COLL_VD | COLL_GK))>), grid, block, 0, s, kp);
                 break;
             default:
-                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_DIAG, PREC, TX, TY, (COLL & COLL_VD)>), grid, block, 0, s, kp);
+                hipLaunchKernelGGL((k_lbm<SL, FL, MODE_DIAG, PREC, TX, TY, (COLL & (COLL_VD | COLL_GK))>), grid, block, 0, s, kp);
                 break;
         }
     }

@@ -316,6 +316,7 @@ k_lbm(const KParams P) {
     constexpr C inv_cs2s = C(1.0 / SL::cs2);
     constexpr bool TRTC = (COLL & COLL_TRT) != 0;
     constexpr bool VD = FLOW && (COLL & COLL_VD) != 0;
+    constexpr bool GK = (COLL & COLL_GK) != 0;
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
     // the private LDS ring of scalar populations, unless it would not leave room for
     // a second work-group per compute unit (the paper's D3Q19 scalar lattice)
@@ -427,7 +428,7 @@ k_lbm(const KParams P) {
         C tg[QS], ta[QS], tb[QS];
         double ps, ca, cb;
         load_scalars(unsigned((zz * P.ny + yy) * P.nx + xx), neighbours(xx, yy, zz, P), tg, ta, tb, ps, ca, cb);
-        return C(node_scalars(ps, ca, cb, P).phi);
+        return C(node_scalars<GK>(ps, ca, cb, P).phi);
     };
 
     // scalar populations and sums of this thread's node: current plane (c*) and next plane (n*)
@@ -452,7 +453,7 @@ k_lbm(const KParams P) {
             } else {
                 load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), ng, na, nb, ps, cA, cB);
             }
-            sphi[slot][ty + OY][tx + 1] = C(node_scalars(ps, cA, cB, P).phi);
+            sphi[slot][ty + OY][tx + 1] = C(node_scalars<GK>(ps, cA, cB, P).phi);
         } else if (x <= P.nx && y <= P.ny) {
             // ghost column / row just beyond the domain edge
             sphi[slot][ty + OY][tx + 1] = node_phi(map_coord(x, P.nx, P.wall_x),
@@ -553,7 +554,7 @@ k_lbm(const KParams P) {
         const double sA = c_cA, sB = c_cB;
 
         if (active) {
-            const Scalars m = node_scalars(c_ps, sA, sB, P);
+            const Scalars m = node_scalars<GK>(c_ps, sA, sB, P);
             const C phi = C(m.phi);
 
             // isotropic gradient and Laplacian, Eqs. Grad and Laplacian (fluid lattice)
@@ -867,7 +868,7 @@ k_lbm(const KParams P) {
                 acc[3] += 0.5 * P.rho0 * u2;
                 acc[4] = fmax(acc[4], sqrt(u2));
                 acc[5] += (4.0 / P.W) * m.phi * (1.0 - m.phi);
-                acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) + 0.5 * P.lam * (m.muA * m.muA + m.muB * m.muB);
+                acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) + P.lam * bulk_free_energy<GK>(m.phi, m.muA, m.muB, P);
                 acc[7] += (isfinite(m.phi) && isfinite(sA) && isfinite(sB)) ? 0.0 : 1.0;
                 P.mask_out[idx] = m.phi >= 0.5 ? 1 : 0;
             }
@@ -1004,11 +1005,22 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
     const Nbr nb = neighbours(x, y, z, P);
     const double phi = phi0[idx], muA = muA0[idx], muB = muB0[idx];
     const double pp = interp_p(phi);
-    // Eq. species_closure, unless the compositions are given (initial condition of
-    // Section 4.2.1: c stepped at phi = 1/2 with mu = 0)
-    const double cA = P.init_c[0] ? P.init_c[0][idx] : muA + P.c0A + pp * (P.c1A - P.c0A);
-    const double cB = P.init_c[1] ? P.init_c[1][idx] : muB + P.c0B + pp * (P.c1B - P.c0B);
-    const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
+    // Eq. species_closure (general curvatures: c = c^eq(phi) + kappa(phi) mu), unless the
+    // compositions are given (initial condition of Section 4.2.1: c stepped at phi = 1/2
+    // with mu = 0)
+    double kA = muA, kB = muB;  // kappa(phi) mu
+    double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
+    if (P.general_k) {
+        const double kAA = P.kap0[0] + pp * (P.kap1[0] - P.kap0[0]);
+        const double kAB = P.kap0[1] + pp * (P.kap1[1] - P.kap0[1]);
+        const double kBB = P.kap0[2] + pp * (P.kap1[2] - P.kap0[2]);
+        kA = kAA * muA + kAB * muB;
+        kB = kAB * muA + kBB * muB;
+        const double dAA = P.kap0[0] - P.kap1[0], dAB = P.kap0[1] - P.kap1[1], dBB = P.kap0[2] - P.kap1[2];
+        domega -= 0.5 * (dAA * muA * muA + 2.0 * dAB * muA * muB + dBB * muB * muB);
+    }
+    const double cA = P.init_c[0] ? P.init_c[0][idx] : kA + P.c0A + pp * (P.c1A - P.c0A);
+    const double cB = P.init_c[1] ? P.init_c[1][idx] : kB + P.c0B + pp * (P.c1B - P.c0B);
     const double S0 = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
 
     // returns the rounding residue (value - stored value); 16-bit storage adds the

@@ -76,6 +76,24 @@ int check_config(const lbm_config* c, Layout* L) {
     if (c->variable_density != 0 && c->variable_density != 1)
         return fail(LBM_EINVAL, "variable_density must be 0 or 1");
     const bool vd = c->variable_density == 1;
+    if (c->general_kappa != 0 && c->general_kappa != 1) return fail(LBM_EINVAL, "general_kappa must be 0 or 1");
+    const bool gk = c->general_kappa == 1;
+    if (gk) {
+        for (int pi = 0; pi < 2; ++pi) {
+            const double* k = c->kappa[pi];
+            if (!(std::isfinite(k[0]) && std::isfinite(k[1]) && std::isfinite(k[2])))
+                return fail(LBM_EINVAL, "kappa must be finite");
+            if (!(k[0] > 0 && k[0] * k[2] - k[1] * k[1] > 0))
+                return fail(LBM_EINVAL, "kappa must be symmetric positive definite");
+            // the reduced composition lattices grow a checkerboard mode once
+            // (1 - w_0) exceeds the smallest eigenvalue of kappa (D2Q5: 2/3, D3Q7: 3/4)
+            const double lmin = 0.5 * (k[0] + k[2]) - std::sqrt(0.25 * (k[0] - k[2]) * (k[0] - k[2]) + k[1] * k[1]);
+            const double one_minus_w0 = c->scalar == LBM_D2Q5 ? 2.0 / 3.0 : c->scalar == LBM_D3Q7 ? 0.75 : 0.0;
+            if (lmin < one_minus_w0)
+                return fail(LBM_EUNSTABLE, "kappa's smallest eigenvalue is below 1 - w_0 of the D2Q5 / D3Q7 lattice");
+        }
+        if (trt || vd) return fail(LBM_EUNSUPPORTED, "general_kappa runs with the BGK Boussinesq step");
+    }
     if (vd && c->fluid == LBM_NONE) return fail(LBM_EINVAL, "variable_density needs a fluid lattice");
     if (vd && !(c->rho0 + c->drho > 0)) return fail(LBM_EINVAL, "variable_density needs rho0 + drho > 0");
     if (trt)
@@ -146,7 +164,10 @@ int check_config(const lbm_config* c, Layout* L) {
     // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
     int want_tx = 0, want_ty = 0;
     if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
-    if (vd) {
+    if (gk) {
+        L->ks = L->dim == 2 ? kernels_gk_2d(L->qs, L->qf, L->prec) : kernels_gk_3d(L->qs, L->qf, L->prec);
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "general_kappa runs with FP64 or FP32 storage");
+    } else if (vd) {
         L->ks = L->dim == 2 ? kernels_vd_2d(L->qs, trt, L->prec) : kernels_vd_3d(L->qs, trt, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with FP64 or FP32 storage");
     } else if (trt) {
@@ -241,6 +262,11 @@ void fill_params(lbm_handle* h) {
     kp.f32.trt_ls = float(kp.trt_ls);
     kp.f32.omega_gp = float(kp.omega_gp);
     kp.variable_density = c.variable_density;
+    kp.general_k = c.general_kappa;
+    for (int i = 0; i < 3; ++i) {
+        kp.kap0[i] = c.general_kappa ? c.kappa[0][i] : (i == 1 ? 0.0 : 1.0);
+        kp.kap1[i] = c.general_kappa ? c.kappa[1][i] : (i == 1 ? 0.0 : 1.0);
+    }
     kp.MA0 = c.M_A[0]; kp.MA1 = c.M_A[1]; kp.MB0 = c.M_B[0]; kp.MB1 = c.M_B[1];
     kp.nu0 = c.nu[0]; kp.nu1 = c.nu[1];
     kp.rho0 = L.qf ? c.rho0 : 1.0;

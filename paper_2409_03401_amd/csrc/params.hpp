@@ -18,7 +18,8 @@ enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
 enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_STEP_PHI = 3 };
 // collision operator of the fused step: the paper's BGK, or two relaxation times
 // (flags): COLL_TRT two relaxation times, COLL_VD the variable-density flow model
-enum Coll : int { COLL_BGK = 0, COLL_TRT = 1, COLL_VD = 2 };
+// COLL_GK general curvature matrices of the free energies (2 x 2 closure per node)
+enum Coll : int { COLL_BGK = 0, COLL_TRT = 1, COLL_VD = 2, COLL_GK = 4 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -49,6 +50,10 @@ struct KParams {
     // TRT (COLL_TRT): magic parameters of f and of the scalar lattices; symmetric rate of g
     double trt_lf, trt_ls, omega_gp;
     int variable_density;        // 1: f holds dimensionless populations (rho(phi) model)
+    // general curvatures: kappa_pi = (k_AA, k_AB, k_BB) of phases 0 and 1 (dc/dmu of each
+    // phase); general_k = 0 is the paper's identity
+    double kap0[3], kap1[3];
+    int general_k;
     double MA0, MA1, MB0, MB1;   // species mobilities per phase
     double nu0, nu1, rho0, drho;
     double gx, gy, gz;           // gravity in the kernel frame

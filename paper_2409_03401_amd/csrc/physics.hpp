@@ -18,26 +18,61 @@ struct Scalars {
 
 // Potentials from compositions, Eq. PotChem with p(1 - phi) = 1 - p(phi),
 // and the source S_phi of Eq. SourceTerm_Phi with Delta omega = -sum mu (c_0 - c_1).
+// GK (general curvature matrices kappa_pi = K (K_pi)^-1 of Eq. Taylor): the closure
+// c - c^eq(phi) = kappa(phi) mu, kappa(phi) = kappa_0 + p (kappa_1 - kappa_0), is a
+// 2 x 2 solve, and Delta omega gains -1/2 mu . (kappa_0 - kappa_1) mu.
+template <bool GK = false>
 __device__ __forceinline__ void potentials_and_source(double phi, double cA, double cB,
                                                       const KParams& P, double& muA,
                                                       double& muB, double& S) {
     const double pp = interp_p(phi);
-    muA = cA - P.c0A - pp * (P.c1A - P.c0A);
-    muB = cB - P.c0B - pp * (P.c1B - P.c0B);
-    const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
+    double domega;
+    if constexpr (!GK) {
+        muA = cA - P.c0A - pp * (P.c1A - P.c0A);
+        muB = cB - P.c0B - pp * (P.c1B - P.c0B);
+        domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
+    } else {
+        const double rA = cA - P.c0A - pp * (P.c1A - P.c0A);
+        const double rB = cB - P.c0B - pp * (P.c1B - P.c0B);
+        const double kAA = P.kap0[0] + pp * (P.kap1[0] - P.kap0[0]);
+        const double kAB = P.kap0[1] + pp * (P.kap1[1] - P.kap0[1]);
+        const double kBB = P.kap0[2] + pp * (P.kap1[2] - P.kap0[2]);
+        const double det = kAA * kBB - kAB * kAB;
+        muA = (kBB * rA - kAB * rB) / det;
+        muB = (kAA * rB - kAB * rA) / det;
+        const double dAA = P.kap0[0] - P.kap1[0], dAB = P.kap0[1] - P.kap1[1], dBB = P.kap0[2] - P.kap1[2];
+        domega = -0.5 * (dAA * muA * muA + 2.0 * dAB * muA * muB + dBB * muB * muB) -
+                 (muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B));
+    }
     S = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
 }
 
 // Moments of one node, Eqs. Moment0_c_alpha and Moment0_Phi.  phi = sum g + S/2
 // is implicit in phi; it is resolved by one predictor evaluation of S at sum g.
+template <bool GK = false>
 __device__ __forceinline__ Scalars node_scalars(double phis, double cA, double cB,
                                                 const KParams& P) {
     Scalars s;
     double muA, muB, S;
-    potentials_and_source(phis, cA, cB, P, muA, muB, S);
+    potentials_and_source<GK>(phis, cA, cB, P, muA, muB, S);
     s.phi = phis + 0.5 * S;
-    potentials_and_source(s.phi, cA, cB, P, s.muA, s.muB, s.S);
+    potentials_and_source<GK>(s.phi, cA, cB, P, s.muA, s.muB, s.S);
     return s;
+}
+
+// bulk free-energy density above the reference, in units of K: |mu|^2 / 2, or
+// 1/2 mu . kappa(phi) mu with general curvatures
+template <bool GK = false>
+__device__ __forceinline__ double bulk_free_energy(double phi, double muA, double muB, const KParams& P) {
+    if constexpr (!GK) {
+        return 0.5 * (muA * muA + muB * muB);
+    } else {
+        const double pp = interp_p(phi);
+        const double kAA = P.kap0[0] + pp * (P.kap1[0] - P.kap0[0]);
+        const double kAB = P.kap0[1] + pp * (P.kap1[1] - P.kap0[1]);
+        const double kBB = P.kap0[2] + pp * (P.kap1[2] - P.kap0[2]);
+        return 0.5 * (kAA * muA * muA + 2.0 * kAB * muA * muB + kBB * muB * muB);
+    }
 }
 
 }  // namespace lbm

@@ -57,6 +57,7 @@ class _Config(ctypes.Structure):
         ("sigma", ctypes.c_double), ("nu", ctypes.c_double * 2),
         ("store_ref", ctypes.c_double * 4), ("store_shift", ctypes.c_int32 * 4),
         ("collision", ctypes.c_int32), ("variable_density", ctypes.c_int32), ("trt_magic", ctypes.c_double * 2),
+        ("general_kappa", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kappa", (ctypes.c_double * 3) * 2),
     ]
 
 
@@ -152,6 +153,8 @@ class LBMConfig:
     trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)
     # False: Boussinesq (the paper's); True: rho(phi) model with pressure and viscous forces
     variable_density: bool = False
+    # general curvatures ((k_AA, k_AB, k_BB) of phase 0, of phase 1) = K (K_pi)^-1; None: identity
+    kappa: Optional[Tuple[Tuple[float, float, float], Tuple[float, float, float]]] = None
 
     @property
     def nodes(self):
@@ -191,6 +194,11 @@ class LBMConfig:
             c.store_shift[i] = int(self.store_shift[i])
         c.collision = _COLLISION[self.collision]
         c.variable_density = int(bool(self.variable_density))
+        c.general_kappa = int(self.kappa is not None)
+        if self.kappa is not None:
+            for pi in range(2):
+                for i in range(3):
+                    c.kappa[pi][i] = float(self.kappa[pi][i])
         c.trt_magic[0], c.trt_magic[1] = float(self.trt_magic[0]), float(self.trt_magic[1])
         return c
 

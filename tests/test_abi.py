@@ -36,7 +36,8 @@ def test_struct_layout_matches_header():
     assert lbm._Config.W.offset == 40
     assert lbm._Config.collision.offset == lbm._Config.store_shift.offset + 16
     assert lbm._Config.trt_magic.offset == lbm._Config.collision.offset + 8
-    assert ctypes.sizeof(lbm._Config) == lbm._Config.trt_magic.offset + 16
+    assert lbm._Config.general_kappa.offset == lbm._Config.trt_magic.offset + 16
+    assert ctypes.sizeof(lbm._Config) == lbm._Config.kappa.offset + 48
 
 
 def _cfg(**kw):
@@ -77,6 +78,11 @@ def test_state_bytes_layout():
     (dict(variable_density=True), lbm.LBM_EINVAL),                     # needs a fluid lattice
     (dict(variable_density=True, fluid="D2Q9", drho=-1.0), lbm.LBM_EINVAL),  # rho(1) = 0
     (dict(variable_density=True, fluid="D2Q9", precision="fp16"), lbm.LBM_EUNSUPPORTED),
+    (dict(kappa=((1.0, 1.2, 1.0), (1.0, 0.0, 1.0))), lbm.LBM_EINVAL),      # not positive definite
+    (dict(kappa=((1.0, 0.0, 1.0), (-1.0, 0.0, 1.0))), lbm.LBM_EINVAL),
+    (dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0)), precision="bf16"), lbm.LBM_EUNSUPPORTED),
+    (dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0)), collision="TRT"), lbm.LBM_EUNSUPPORTED),
+    (dict(kappa=((0.6, 0.0, 1.0), (1.0, 0.0, 1.0))), lbm.LBM_EUNSTABLE),  # D2Q5: below 1 - w_0 = 2/3
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:

@@ -1,0 +1,140 @@
+"""General curvature matrices of the free energies on the GPU (general_kappa = 1),
+against the FP64 oracle's closure (oracle/model.py with kappa) on the same seeded
+inputs.
+
+Bars as for the paper's model: FP64 populations within 1e-12 and diagnostics within
+1e-11, FP32 relative L2 within 1e-5 on phi, c^A, c^B and the populations.  Identity
+matrices through the general path reproduce the paper's kernels.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from helpers import (MOMENT_NAMES, field_errors, gpu_config, max_abs, oracle_moments, oracle_params,
+                     oracle_populations, rel_l2)
+from oracle import lbm as olbm
+from oracle import model
+from paper_2409_03401_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# smallest eigenvalues 0.84 and 0.94: above 1 - w_0 of every composition lattice
+KAPPA = ((1.0, 0.1, 0.9), (0.95, -0.05, 1.2))
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _drops(shape, n, rmin, rmax, W, seed, wall_axes=()):
+    rng = np.random.default_rng(seed)
+    drops = inputs.place_droplets(shape, n, rmin, rmax, W, rng, wall_axes=wall_axes)
+    phi = inputs.droplet_field(shape, drops, W, wall_axes=wall_axes)
+    mu = rng.normal(0.0, 5e-3, (2,) + shape)
+    return phi, mu[0], mu[1]
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    flow2 = dict(fluid="D2Q9", drho=0.5, g=(0.0, -1e-4, 0.0), sigma=1e-3, nu=(0.1, 0.05))
+    flow3 = dict(fluid="D3Q19", drho=0.5, g=(0.0, 0.0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
+    if name == "2d_noflow":
+        p = inputs._base(75, 41, 1, W=3.0, kappa=KAPPA)
+        return (p, *_drops((1, 41, 75), 5, 3.0, 7.0, 3.0, 71), 40)
+    if name == "2d_flow_walls":
+        p = inputs._base(66, 48, 1, W=4.0, bc=("periodic", "walls", "periodic"), kappa=KAPPA, **flow2)
+        return (p, *_drops((1, 48, 66), 3, 4.0, 8.0, 4.0, 72, (1,)), 40)
+    if name == "2d_d2q9_scalars":
+        p = inputs._base(60, 44, 1, W=3.0, scalar="D2Q9", kappa=KAPPA)
+        return (p, *_drops((1, 44, 60), 4, 3.0, 7.0, 3.0, 73), 40)
+    if name == "3d_flow_walls":
+        p = inputs._base(21, 18, 20, W=4.0, bc=("periodic", "periodic", "walls"), kappa=KAPPA, **flow3)
+        return (p, *_drops((20, 18, 21), 1, 4.0, 5.0, 4.0, 74, (2,)), 12)
+    raise KeyError(name)
+
+
+CASES = ["2d_noflow", "2d_flow_walls", "2d_d2q9_scalars", "3d_flow_walls"]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name):
+    p, phi0, muA0, muB0, steps = case(name)
+    prm = oracle_params(p)
+    st = olbm.run(olbm.init(phi0, muA0, muB0, prm), prm, steps)
+    return oracle_moments(prm, st), oracle_populations(prm, st), olbm.diagnostics(st, prm)
+
+
+def _gpu(name, precision):
+    from paper_2409_03401_amd.lbm import Simulation
+    p, phi0, muA0, muB0, steps = case(name)
+    print(f"[general kappa] {name} shape={phi0.shape} {precision} steps={steps}", flush=True)
+    sim = Simulation(gpu_config(p, precision), phi0, muA0, muB0)
+    sim.step(steps)
+    return ({k: v.cpu().numpy() for k, v in sim.moments().items()}, sim.populations().cpu().numpy(),
+            sim.diagnostics())
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_gk_parity_fp64(name):
+    _require_gpu()
+    mom, pops, diag = _gpu(name, "fp64")
+    ora_m, ora_p, ora_d = oracle_case(name)
+    err = max_abs(pops, ora_p)
+    assert err <= 1e-12, err
+    for k in MOMENT_NAMES:
+        assert max_abs(mom[k], ora_m[k]) <= 1e-12 * max(1.0, np.abs(ora_m[k]).max()), k
+    for k in ("sum_cA", "sum_cB", "sum_phi", "free_energy"):
+        assert abs(diag[k] - ora_d[k]) <= 1e-11 * max(1.0, abs(ora_d[k])), k
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_gk_parity_fp32(name):
+    _require_gpu()
+    mom, pops, _ = _gpu(name, "fp32")
+    ora_m, ora_p, _ = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("phi", "cA", "cB"):
+        assert errs[k][0] <= 1e-5, (k, errs[k])
+    assert rel_l2(pops, ora_p) <= 1e-5
+
+
+def test_gk_identity_is_the_paper_model():
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    p, phi0, muA0, muB0, steps = case("2d_flow_walls")
+    ident = ((1.0, 0.0, 1.0), (1.0, 0.0, 1.0))
+    a = Simulation(gpu_config(dict(p, kappa=None), "fp64"), phi0, muA0, muB0)
+    b = Simulation(gpu_config(dict(p, kappa=ident), "fp64"), phi0, muA0, muB0)
+    a.step(steps)
+    b.step(steps)
+    assert (a.populations() - b.populations()).abs().max().item() < 1e-13
+
+
+def test_gk_flat_interface_coexistence():
+    """Uniform mu on the coexistence line Delta omega = 0: the flat interface stays
+    (start-up transient only); off the line it moves with the sign of Delta omega."""
+    _require_gpu()
+    from scipy.optimize import brentq
+    from paper_2409_03401_amd.lbm import Simulation
+    c_eq = ((0.2, 0.1), (0.6, 0.3))
+    muB = 0.02
+    muA = brentq(lambda a: model.delta_omega((a, muB), c_eq, KAPPA), -0.2, 0.2)
+    nx = 96
+    x = np.arange(nx) - (nx - 1) / 2.0
+    phi0 = np.repeat((0.5 * (1.0 + np.tanh(2.0 * x / 4.0)))[None, None, :], 8, axis=1)
+    p = inputs._base(nx, 8, 1, W=4.0, lam=2.0, bc=("walls", "periodic", "periodic"), c_eq=c_eq, kappa=KAPPA)
+    moved = {}
+    for shift in (0.0, 0.01, -0.01):
+        sim = Simulation(gpu_config(p, "fp64"), phi0, np.full_like(phi0, muA + shift), np.full_like(phi0, muB))
+        s0 = sim.diagnostics()["sum_phi"]
+        sim.step(300)
+        moved[shift] = sim.diagnostics()["sum_phi"] - s0
+    d_plus = model.delta_omega((muA + 0.01, muB), c_eq, KAPPA)
+    assert abs(moved[0.01]) > 20 * abs(moved[0.0]) and np.sign(moved[0.01]) == np.sign(d_plus)
+    assert abs(moved[-0.01]) > 20 * abs(moved[0.0]) and np.sign(moved[-0.01]) == -np.sign(d_plus)

@@ -649,7 +649,7 @@ def test_variable_density_conserves_mass():
 # general curvature matrices K_pi (Eq. Taylor with a full matrix; the paper's model has
 # K_pi = K identity)
 
-KAPPA = ((1.0, 0.2, 0.8), (0.6, -0.1, 1.3))   # (k_AA, k_AB, k_BB) of phases 0 and 1
+KAPPA = ((1.0, 0.1, 0.9), (0.95, -0.05, 1.2))   # (k_AA, k_AB, k_BB) of phases 0 and 1
 C_EQ = ((0.2, 0.1), (0.6, 0.3))
 
 
@@ -722,6 +722,21 @@ def test_general_curvature_flat_interface_coexistence():
     assert abs(moved[0.0]) < 5e-3
     assert np.sign(moved[0.01]) == np.sign(d_plus) and abs(moved[0.01]) > 20 * abs(moved[0.0])
     assert np.sign(moved[-0.01]) == -np.sign(d_plus) and abs(moved[-0.01]) > 20 * abs(moved[0.0])
+
+
+@pytest.mark.parametrize("scalar,stable,unstable", [("D2Q5", 0.70, 0.65), ("D2Q9", 0.5, None)])
+def test_general_curvature_lattice_stability(scalar, stable, unstable):
+    """The composition lattice relaxes h towards w_k mu with mu = kappa^-1 (c - c^eq):
+    on D2Q5 a checkerboard mode grows once the smallest eigenvalue of kappa drops below
+    1 - w_0 = 2/3 (the limit the library enforces); D2Q9 stays stable further down."""
+    def growth(k):
+        prm = lbm.Params(nx=32, ny=32, scalar=scalar, W=3.0, lam=2.0, kappa=((k, 0.0, k), (k, 0.0, k)))
+        mu = 1e-6 * np.random.default_rng(1).standard_normal((2,) + prm.shape)
+        st = lbm.run(lbm.init(np.zeros(prm.shape), mu[0], mu[1], prm), prm, 200)
+        return np.abs(lbm.moments(st, prm)["muA"]).max() / np.abs(mu[0]).max()
+    assert growth(stable) < 1.0
+    if unstable is not None:
+        assert growth(unstable) > 1e3
 
 
 def test_general_curvature_run_conserves_and_matches_identity():
