@@ -59,3 +59,51 @@ D3Q7 = Lattice("D3Q7", 3,
                [Fr(1, 4)] + [Fr(1, 8)] * 6)
 
 BY_NAME = {lat.name: lat for lat in (D2Q9, D3Q19, D2Q5, D3Q7)}
+
+
+# ----------------------------------------------------------------------------------------
+# moment basis for multiple-relaxation-time collisions
+
+def _monomials(dim):
+    """Polynomials in (cx, cy, cz) whose values on a lattice span its moment space, in
+    increasing order; the second order is split into the trace and traceless parts so
+    that bulk and shear stresses are separate moments.  Returned as (order, function)."""
+    x = lambda e: e[0]
+    y = lambda e: e[1]
+    z = lambda e: e[2]
+    if dim == 2:
+        return [(0, lambda e: 1), (1, x), (1, y),
+                (2, lambda e: x(e) ** 2 + y(e) ** 2), (2, lambda e: x(e) ** 2 - y(e) ** 2),
+                (2, lambda e: x(e) * y(e)),
+                (3, lambda e: x(e) ** 2 * y(e)), (3, lambda e: x(e) * y(e) ** 2),
+                (4, lambda e: x(e) ** 2 * y(e) ** 2)]
+    return [(0, lambda e: 1), (1, x), (1, y), (1, z),
+            (2, lambda e: x(e) ** 2 + y(e) ** 2 + z(e) ** 2),
+            (2, lambda e: 2 * x(e) ** 2 - y(e) ** 2 - z(e) ** 2), (2, lambda e: y(e) ** 2 - z(e) ** 2),
+            (2, lambda e: x(e) * y(e)), (2, lambda e: x(e) * z(e)), (2, lambda e: y(e) * z(e)),
+            (3, lambda e: x(e) ** 2 * y(e)), (3, lambda e: x(e) ** 2 * z(e)), (3, lambda e: y(e) ** 2 * x(e)),
+            (3, lambda e: y(e) ** 2 * z(e)), (3, lambda e: z(e) ** 2 * x(e)), (3, lambda e: z(e) ** 2 * y(e)),
+            (4, lambda e: x(e) ** 2 * y(e) ** 2), (4, lambda e: x(e) ** 2 * z(e) ** 2),
+            (4, lambda e: y(e) ** 2 * z(e) ** 2)]
+
+
+def moment_basis(lat):
+    """Rows of an invertible moment matrix M (exact rationals) orthogonal in the
+    weighted product <a, b> = sum_k w_k a_k b_k, by Gram-Schmidt over the monomials
+    above (skipping those that are dependent on the lattice), with the polynomial
+    order of each row.  Its inverse is M^-1_{k i} = w_k M_{i k} / <M_i, M_i>."""
+    rows, orders = [], []
+    for order, fn in _monomials(lat.dim):
+        v = [Fr(fn(tuple(int(c) for c in lat.e[k]))) for k in range(lat.Q)]
+        for r in rows:
+            num = sum(w * a * b for w, a, b in zip(lat.w_exact, v, r))
+            den = sum(w * b * b for w, b in zip(lat.w_exact, r))
+            v = [a - num / den * b for a, b in zip(v, r)]
+        if any(a != 0 for a in v):
+            rows.append(v)
+            orders.append(order)
+        if len(rows) == lat.Q:
+            break
+    assert len(rows) == lat.Q, lat.name
+    return rows, orders
+

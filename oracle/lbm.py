@@ -40,7 +40,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 from . import geometry, model
-from .lattices import BY_NAME, D2Q9, D3Q19
+from .lattices import BY_NAME, D2Q9, D3Q19, moment_basis
 
 
 @dataclass
@@ -63,7 +63,10 @@ class Params:
     sigma: float = 0.0
     nu: Tuple[float, float] = (0.1, 0.1)       # (phase 0, phase 1)
     gravity_mean_subtract: bool = False
-    collision: str = "BGK"                      # "BGK" (the paper's) or "TRT"
+    collision: str = "BGK"                      # "BGK" (the paper's), "TRT" or "MRT"
+    # MRT rates of the moments the transport coefficients leave free: f (bulk, third
+    # order, fourth order); g, h^A, h^B (second, third, fourth order)
+    mrt_rates: Tuple[Tuple[float, float, float], Tuple[float, float, float]] = ((1.2, 1.1, 1.2), (1.1, 1.0, 1.2))
     variable_density: bool = False              # False: Boussinesq (the paper's); True: rho(phi)
     # general curvatures: ((k_AA, k_AB, k_BB) of phase 0, same of phase 1) = K (K_pi)^-1;
     # None is the paper's K_pi = K identity
@@ -235,6 +238,56 @@ def trt_partner_rate(w, magic):
     to BGK in Section 3; Ginzburg's form): the rate that the transport coefficient does
     not fix follows from the magic parameter Lambda = (1/w+ - 1/2)(1/w- - 1/2)."""
     return 1.0 / (0.5 + magic / (1.0 / w - 0.5))
+
+
+_BASES = {}
+
+
+def _basis(lat):
+    if lat.name not in _BASES:
+        rows, orders = moment_basis(lat)
+        M = np.array([[float(a) for a in r] for r in rows])
+        D = np.array([float(sum(w * a * a for w, a in zip(lat.w_exact, r))) for r in rows])
+        _BASES[lat.name] = (M, D, orders)
+    return _BASES[lat.name]
+
+
+def mrt_collide(X, eqs, src, lat, rates):
+    """Multiple-relaxation-time collision (the MRT alternative the paper names in
+    Section 3): the non-equilibrium part n = X - eqs (shifted equilibria, as in BGK)
+    is taken to the weighted-orthogonal moment basis M of lattices.moment_basis, moment
+    i is relaxed at rates[i] (a scalar or a field), and the result is taken back:
+        X*_k = X_k - sum_i (w_k M_ik / <M_i, M_i>) rates_i (M n)_i + src_k.
+    Equal rates give the BGK collision; even/odd-order rates w+ / w- give TRT."""
+    M, D, _ = _basis(lat)
+    n = [X[k] - eqs[k] for k in range(lat.Q)]
+    m = [sum(M[i, k] * n[k] for k in range(lat.Q) if M[i, k] != 0.0) * rates[i] / D[i] for i in range(lat.Q)]
+    return np.stack([X[k] - lat.w[k] * sum(M[i, k] * m[i] for i in range(lat.Q) if M[i, k] != 0.0) + src[k]
+                     for k in range(lat.Q)])
+
+
+def mrt_rates(lat, transport_rate, free, fluid):
+    """Rate of each row of the moment basis.  Orders 0 and 1 of f are conserved by the
+    collision (their n moments vanish; rate 1).  f: the traceless second order relaxes
+    at the viscous rate, the trace at free[0], third and fourth orders at free[1],
+    free[2].  g, h: the first order (the diffusive flux) at the mobility rate, second,
+    third and fourth orders at free[0], free[1], free[2]; order 0 with the other even
+    orders at free[0] (it is conserved for h; for g the phi predictor leaves a small
+    S difference, which BGK and TRT relax with the even rate too)."""
+    _, _, orders = _basis(lat)
+    rates, first2 = [], True
+    for o in orders:
+        if fluid:
+            if o <= 1:
+                rates.append(1.0)
+            elif o == 2:
+                rates.append(free[0] if first2 else transport_rate)
+                first2 = False
+            else:
+                rates.append(free[1] if o == 3 else free[2])
+        else:
+            rates.append(free[0] if o == 0 else transport_rate if o == 1 else free[o - 2])
+    return rates
 
 
 def trt_collide(X, eqs, src, lat, w_sym, w_anti):
@@ -423,11 +476,16 @@ def step(st, prm):
         u = [zero, zero, zero]
 
     trt = prm.collision == "TRT"
+    mrt = prm.collision == "MRT"
     lam_f, lam_s = prm.trt_magic
 
     # g: Eqs. LBE_Phi, Geq, Source_LBE_Phi
     wg = rate(prm.M_phi, slat.cs2)
-    if not trt:
+    if mrt:
+        Gk = [slat.w[k] * S for k in range(slat.Q)]
+        g_post = mrt_collide(st.g, [g_equilibrium_k(slat, k, phi, u, Gk[k]) for k in range(slat.Q)], Gk, slat,
+                             mrt_rates(slat, wg, prm.mrt_rates[1], False))
+    elif not trt:
         g_post = np.stack([st.g[k] - wg * (st.g[k] - g_equilibrium_k(slat, k, phi, u, slat.w[k] * S))
                            + slat.w[k] * S for k in range(slat.Q)])
     else:  # the diffusive flux is the antisymmetric part: M_phi sets w-
@@ -439,7 +497,10 @@ def step(st, prm):
     h_post = []
     for h, c, mu, Mpair in ((st.hA, m["cA"], m["muA"], prm.M_A), (st.hB, m["cB"], m["muB"], prm.M_B)):
         wh = rate(model.mobility(phi, Mpair), slat.cs2)
-        if not trt:
+        if mrt:
+            h_post.append(mrt_collide(h, [h_equilibrium_k(slat, k, c, mu, u) for k in range(slat.Q)],
+                                      [0.0] * slat.Q, slat, mrt_rates(slat, wh, prm.mrt_rates[1], False)))
+        elif not trt:
             h_post.append(np.stack([h[k] - wh * (h[k] - h_equilibrium_k(slat, k, c, mu, u))
                                     for k in range(slat.Q)]))
         else:
@@ -450,7 +511,10 @@ def step(st, prm):
     if prm.fluid:
         # f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq
         wf = rate(model.viscosity(phi, prm.nu), flat.cs2)
-        if not trt:
+        if mrt:
+            f_post = mrt_collide(st.f, [f_equilibrium_k(flat, k, p_eq, u, rho_eq, Fk[k]) for k in range(flat.Q)],
+                                 Fk, flat, mrt_rates(flat, wf, prm.mrt_rates[0], True))
+        elif not trt:
             f_post = np.stack([st.f[k] - wf * (st.f[k] - f_equilibrium_k(flat, k, p_eq, u, rho_eq, Fk[k]))
                                + Fk[k] for k in range(flat.Q)])
         else:  # the viscous stress is the symmetric part: nu sets w+

@@ -576,6 +576,81 @@ def test_trt_conserves_mass_and_pressure_sum():
 
 
 # ----------------------------------------------------------------------------------------
+# MRT collision (the multiple-relaxation-time alternative named in Section 3)
+
+@pytest.mark.parametrize("lat", [lattices.D2Q5, lattices.D2Q9, lattices.D3Q7, lattices.D3Q19], ids=lambda l: l.name)
+def test_moment_basis_exact(lat):
+    """Weighted-orthogonal rows, exact inverse M^-1_{k i} = w_k M_ik / <M_i, M_i>, the
+    first rows are 1 and c, and the orders run 0, 1, 2 (, 3, 4)."""
+    rows, orders = lattices.moment_basis(lat)
+    Q = lat.Q
+    D = [sum(w * a * a for w, a in zip(lat.w_exact, r)) for r in rows]
+    for i in range(Q):
+        for j in range(Q):
+            dot = sum(w * a * b for w, a, b in zip(lat.w_exact, rows[i], rows[j]))
+            assert dot == (D[i] if i == j else 0)
+    for k in range(Q):       # (M^-1 M)_{kl} = delta_kl, exactly
+        for l in range(Q):
+            assert sum(lat.w_exact[k] * rows[i][k] / D[i] * rows[i][l] for i in range(Q)) == (1 if k == l else 0)
+    assert all(a == 1 for a in rows[0])
+    for a in range(lat.dim):
+        assert [int(v) for v in rows[1 + a]] == [int(e[a]) for e in lat.e]
+    assert orders == sorted(orders) and orders[:lat.dim + 1] == [0] + [1] * lat.dim
+
+
+@pytest.mark.parametrize("scalar", ["D2Q5", "D2Q9"])
+def test_mrt_reduces_to_bgk_and_trt(scalar):
+    """Uniform rates: MRT with every free rate equal to the BGK rate is BGK, and with
+    even / odd orders at w+ / w- it is TRT (to rounding)."""
+    rng = np.random.default_rng(17)
+    M, nu, cs2 = 0.1, 0.08, 1.0 / 3.0
+    wv, wm = lbm.rate(nu, cs2), lbm.rate(M, cs2)
+    common = dict(nx=26, ny=22, fluid="D2Q9", scalar=scalar, bc=("periodic", "walls", "periodic"), W=4.0,
+                  lam=21.05, M_phi=M, M_A=(M, M), M_B=(M, M), drho=0.5, g=(0, -1e-4, 0), sigma=1e-3,
+                  nu=(nu, nu))
+    fields = _droplet_fields((1, 22, 26), [(13, 11, 0)], [5], 4.0, rng)
+    run = lambda prm: lbm.run(lbm.init(*fields, prm), prm, 20)
+    a = run(lbm.Params(**common))
+    b = run(lbm.Params(**common, collision="MRT", mrt_rates=((wv, wv, wv), (wm, wm, wm))))
+    lf, ls = 3.0 / 16.0, 0.25
+    c = run(lbm.Params(**common, collision="TRT", trt_magic=(lf, ls)))
+    wmf, wps = lbm.trt_partner_rate(wv, lf), lbm.trt_partner_rate(wm, ls)
+    d = run(lbm.Params(**common, collision="MRT", mrt_rates=((wv, wmf, wv), (wps, wm, wps))))
+    for k in ("f", "g", "hA", "hB"):
+        assert np.abs(getattr(a, k) - getattr(b, k)).max() < 1e-14, k
+        assert np.abs(getattr(c, k) - getattr(d, k)).max() < 1e-14, k
+
+
+def test_mrt_poiseuille_exact():
+    """The wall position depends on the shear and third-order rates only: with
+    (1/s_nu - 1/2)(1/s_3 - 1/2) = 3/16 the profile is the parabola whatever the bulk and
+    fourth-order rates."""
+    N, nu = 12, 0.5
+    s3 = lbm.trt_partner_rate(lbm.rate(nu, 1.0 / 3.0), 3.0 / 16.0)
+    prm = lbm.Params(nx=2, ny=N, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=21.05, drho=1.0,
+                     g=(1e-6, 0, 0), sigma=1e-3, nu=(nu, nu), collision="MRT", mrt_rates=((1.1, s3, 1.3), (1, 1, 1)))
+    phi0 = np.ones(prm.shape)
+    st = lbm.run(lbm.init(phi0, 0 * phi0, 0 * phi0, prm), prm, 1000)
+    ux = lbm.moments(st, prm)["ux"][0, :, 0]
+    ref = analytic.poiseuille(np.arange(N), N, 1e-6, 1.0, nu)
+    assert np.abs(ux - ref).max() < 1e-9 * ref.max()
+
+
+def test_mrt_conserves_mass():
+    rng = np.random.default_rng(18)
+    prm = lbm.Params(nx=24, ny=20, fluid="D2Q9", scalar="D2Q9", bc=("walls", "walls", "periodic"), W=4.0,
+                     lam=21.05, M_A=(0.1, 0.05), M_B=(0.08, 0.12), drho=0.5, g=(0, -1e-4, 0), sigma=1e-3,
+                     nu=(0.1, 0.05), collision="MRT")
+    st = lbm.init(*_droplet_fields(prm.shape, [(12, 10, 0)], [5], 4.0, rng), prm)
+    d0, p0 = lbm.diagnostics(st, prm), st.f.sum()
+    st = lbm.run(st, prm, 60)
+    d1 = lbm.diagnostics(st, prm)
+    for key in ("sum_cA", "sum_cB"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * abs(d0[key]), key
+    assert abs(st.f.sum() - p0) <= 1e-12 * max(1.0, abs(d0["sum_phi"]))
+
+
+# ----------------------------------------------------------------------------------------
 # variable-density flow (the rho(phi) alternative to Boussinesq named after Eq. Velocity)
 
 def test_variable_density_reduces_to_boussinesq():
