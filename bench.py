@@ -35,6 +35,7 @@ WORKLOADS = {
     "ostwald_paper_2d_4096": dict(kind="ostwald_paper_2d", n=4096, precision="fp32"),
     # the two-relaxation-time collision on the sedimentation workload
     "sediment_3d_256_trt": dict(kind="sediment_3d", n=256, precision="fp32", collision="TRT"),
+    "sediment_3d_256_mrt": dict(kind="sediment_3d", n=256, precision="fp32", collision="MRT"),
     # the variable-density flow model (density ratio 1.5) on the sedimentation workload
     "sediment_3d_256_vd": dict(kind="sediment_3d", n=256, precision="fp32", variable_density=True),
 }
@@ -56,7 +57,8 @@ def build_workload(name):
     w = _build_workload(name)
     spec = WORKLOADS[name]
     if spec.get("collision"):
-        w.params = dict(w.params, collision=spec["collision"], trt_magic=(3.0 / 16.0, 0.25))
+        w.params = dict(w.params, collision=spec["collision"], trt_magic=(3.0 / 16.0, 0.25),
+                        mrt_rates=((1.2, 1.1, 1.2), (1.1, 1.0, 1.2)))
     if spec.get("variable_density"):
         w.params = dict(w.params, variable_density=True)
     return w

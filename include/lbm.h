@@ -49,6 +49,16 @@ extern "C" {
  * storage, no adjoint. */
 #define LBM_BGK 0
 #define LBM_TRT 1
+/* LBM_MRT, the multiple-relaxation-time alternative Section 3 names: X - X^eq is
+ * taken to a moment basis orthogonal in sum_k w_k a_k b_k (Gram-Schmidt over the
+ * polynomials 1, c, |c|^2, the traceless second order, then third and fourth
+ * order), each moment relaxed at its own rate, and taken back; sources as in BGK.
+ * f: the traceless second order at the viscous rate, the trace (bulk), third and
+ * fourth orders at mrt_rates[0][0..2], orders 0 and 1 conserved.  g, h^A, h^B: the
+ * first order (diffusive flux) at the mobility rate, orders 0 and 2 at
+ * mrt_rates[1][0], third and fourth at mrt_rates[1][1..2].  Rates in (0, 2);
+ * FP64 and FP32 storage, Boussinesq, no adjoint. */
+#define LBM_MRT 2
 
 /* general_kappa = 1 (FP64 / FP32 storage, BGK, Boussinesq, no adjoint): the
  * quadratic free energies of Eq. Taylor with full curvature matrices K_pi, given
@@ -144,6 +154,7 @@ typedef struct lbm_config {
     int32_t general_kappa;     /* 0: the paper's K_pi = K identity; 1: kappa below  */
     int32_t reserved;          /* 0                                                 */
     double kappa[2][3];        /* per phase (k_AA, k_AB, k_BB) = K (K_pi)^-1        */
+    double mrt_rates[2][3];    /* LBM_MRT: f (bulk, 3rd, 4th), scalars (2nd, 3rd, 4th) */
 } lbm_config;
 
 typedef struct lbm_handle lbm_handle;

@@ -36,6 +36,9 @@ const KernelSet* kernels_paper_3d(int fluid, int prec);
 // the two-relaxation-time collision (scalar lattice 5 / 9 in 2D, 7 / 19 in 3D): FP64 / FP32, no adjoint
 const KernelSet* kernels_trt_2d(int scalar, int fluid, int prec);
 const KernelSet* kernels_trt_3d(int scalar, int fluid, int prec);
+// the multiple-relaxation-time collision (same lattice pairs): FP64 / FP32, no adjoint
+const KernelSet* kernels_mrt_2d(int scalar, int fluid, int prec);
+const KernelSet* kernels_mrt_3d(int scalar, int fluid, int prec);
 // the variable-density flow model (needs the fluid lattice): FP64 / FP32, no adjoint
 const KernelSet* kernels_vd_2d(int scalar, bool trt, int prec);
 const KernelSet* kernels_vd_3d(int scalar, bool trt, int prec);

@@ -296,6 +296,48 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
         if constexpr (LBM_PHASES) __builtin_amdgcn_sched_barrier(0); \
     } while (0)
 
+// MRT relaxation of one field (the multiple-relaxation-time alternative to BGK):
+// n_k = X_k - eqs(k) to the moment basis, moment i times rate(i) / <M_i, M_i>, back
+// with M^-1_{k i} = w_k M_ik / <M_i, M_i>, then out(k, X_k - w_k (M^T m)_k + src(k)).
+template <class L>
+inline constexpr MomentBasis<L::Q> kBasis = make_moment_basis<L>();
+
+template <class L, class C, class EQ, class SRC, class RATE, class OUT>
+__device__ __forceinline__ void mrt_relax(const C (&X)[L::Q], EQ&& eqs, SRC&& src, RATE&& rate, OUT&& out) {
+    constexpr int Q = L::Q;
+    C n[Q], m[Q];
+    static_for<0, Q>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        n[k] = X[k] - eqs(kc);
+    });
+    static_for<0, Q>([&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        C a = C(0);
+        static_for<0, Q>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            constexpr double mik = kBasis<L>.M[i][k];
+            if constexpr (mik != 0.0) a += C(mik) * n[k];
+        });
+        m[i] = a * (rate(ic) * C(kBasis<L>.invD[i]));
+    });
+    static_for<0, Q>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        C a = C(0);
+        static_for<0, Q>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            constexpr double mik = kBasis<L>.M[i][k];
+            if constexpr (mik != 0.0) a += C(mik) * m[i];
+        });
+        out(kc, X[k] - C(L::w(k)) * a + src(kc));
+    });
+}
+
+// order of row i of the basis, and whether it is the trace of the second order
+template <class L, int I>
+constexpr int basis_order() { return kBasis<L>.order[I]; }
+template <class L, int I>
+constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBasis<L>.order[I - 1] != 2); }
+
 template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
 k_lbm(const KParams P) {
@@ -315,6 +357,7 @@ k_lbm(const KParams P) {
     constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
     constexpr C inv_cs2s = C(1.0 / SL::cs2);
     constexpr bool TRTC = (COLL & COLL_TRT) != 0;
+    constexpr bool MRTC = (COLL & COLL_MRT) != 0;
     constexpr bool VD = FLOW && (COLL & COLL_VD) != 0;
     constexpr bool GK = (COLL & COLL_GK) != 0;
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
@@ -676,7 +719,37 @@ k_lbm(const KParams P) {
                     const C rho0 = VD ? C(3) : KC(P.rho0, P.f32.rho0);
                     const C g0 = C(1) - C(1.5) * uu, e0 = p_h - C(0.5) * rho0 * uu;
                     const C fsc = VD ? C(3) * irho : C(1);
-                    if constexpr (!TRTC) {
+                    if constexpr (MRTC) {
+                        // MRT: the traceless second order at the viscous rate wf, the trace,
+                        // third and fourth orders at the given rates; orders 0 and 1 are
+                        // conserved (rate 1)
+                        auto feqs = [&](auto kc, C& Fk) __attribute__((always_inline)) -> C {
+                            constexpr int k = decltype(kc)::value;
+                            constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
+                            const C wk = C(FL::w(k));
+                            const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
+                            const C eF = edot<ex, ey, ez>(F[0], F[1], F[2]);
+                            Fk = wk * (g0 + eu * (C(3) + C(4.5) * eu)) * (eF - uF);
+                            if constexpr (VD) Fk *= fsc;
+                            return wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu)) - C(0.5) * Fk;
+                        };
+                        C Fks[QF];
+                        mrt_relax<FL>(fpop,
+                            [&](auto kc) __attribute__((always_inline)) -> C {
+                                return feqs(kc, Fks[decltype(kc)::value]);
+                            },
+                            [&](auto kc) __attribute__((always_inline)) -> C { return Fks[decltype(kc)::value]; },
+                            [&](auto ic) __attribute__((always_inline)) -> C {
+                                constexpr int i = decltype(ic)::value;
+                                constexpr int o = basis_order<FL, i>();
+                                if constexpr (o <= 1) return C(1);
+                                else if constexpr (basis_trace<FL, i>()) return KC(P.mrt_f[0], P.f32.mrt_f[0]);
+                                else if constexpr (o == 2) return wf;
+                                else if constexpr (o == 3) return KC(P.mrt_f[1], P.f32.mrt_f[1]);
+                                else return KC(P.mrt_f[2], P.f32.mrt_f[2]);
+                            },
+                            [&](auto kc, C v) __attribute__((always_inline)) { push(kc, kc, FLT{}, v); });
+                    } else if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
@@ -735,7 +808,32 @@ k_lbm(const KParams P) {
                     const C keep = C(1) - wg;
                     const C wphi = wg * phi;
                     const C srcS = (C(1) - C(0.5) * wg) * C(m.S);
-                    if constexpr (!TRTC) {
+                    if constexpr (MRTC) {
+                        // MRT: the first order (diffusive flux) at the M_phi rate, orders 0
+                        // and 2 at the given even rate, third and fourth at theirs
+                        const C S = C(m.S), hS = C(0.5) * C(m.S);
+                        mrt_relax<SL>(g,
+                            [&](auto kc) __attribute__((always_inline)) -> C {
+                                constexpr int k = decltype(kc)::value;
+                                constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                                const C wk = C(SL::w(k));
+                                if constexpr (ex != 0 || ey != 0 || ez != 0)
+                                    return wk * (phi * (C(1) + edot<ex, ey, ez>(u[0], u[1], u[2]) * inv_cs2s) - hS);
+                                else
+                                    return wk * (phi - hS);
+                            },
+                            [&](auto kc) __attribute__((always_inline)) -> C { return C(SL::w(decltype(kc)::value)) * S; },
+                            [&](auto ic) __attribute__((always_inline)) -> C {
+                                constexpr int o = basis_order<SL, decltype(ic)::value>();
+                                if constexpr (o == 1) return wg;
+                                else if constexpr (o == 3) return KC(P.mrt_s[1], P.f32.mrt_s[1]);
+                                else if constexpr (o == 4) return KC(P.mrt_s[2], P.f32.mrt_s[2]);
+                                else return KC(P.mrt_s[0], P.f32.mrt_s[0]);
+                            },
+                            [&](auto kc, C v) __attribute__((always_inline)) {
+                                push(IC<G0 + decltype(kc)::value>{}, kc, SLT{}, v);
+                            });
+                    } else if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
@@ -786,7 +884,36 @@ k_lbm(const KParams P) {
                     const C MB = KC(P.MB0, P.f32.MB0) * (C(1) - phi) + KC(P.MB1, P.f32.MB1) * phi;
                     const C wA = rcp<C>(MA * inv_cs2s + C(0.5));
                     const C wB = rcp<C>(MB * inv_cs2s + C(0.5));
-                    if constexpr (TRTC) {
+                    if constexpr (MRTC) {
+                        // MRT: the first order at the mobility rate, the others at the given
+                        // rates (order 0 with the even rate: c is conserved exactly)
+                        auto rates = [&](C wflux) __attribute__((always_inline)) {
+                            return [&, wflux](auto ic) __attribute__((always_inline)) -> C {
+                                constexpr int o = basis_order<SL, decltype(ic)::value>();
+                                if constexpr (o == 1) return wflux;
+                                else if constexpr (o == 3) return KC(P.mrt_s[1], P.f32.mrt_s[1]);
+                                else if constexpr (o == 4) return KC(P.mrt_s[2], P.f32.mrt_s[2]);
+                                else return KC(P.mrt_s[0], P.f32.mrt_s[0]);
+                            };
+                        };
+                        auto heq = [&](double c, double mu) __attribute__((always_inline)) {
+                            return [&, c, mu](auto kc) __attribute__((always_inline)) -> C {
+                                constexpr int k = decltype(kc)::value;
+                                constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                                if constexpr (k == 0) return C(c - (1.0 - SL::w(0)) * mu);
+                                else return C(SL::w(k)) * (C(mu) + C(c) * edot<ex, ey, ez>(u[0], u[1], u[2]) * inv_cs2s);
+                            };
+                        };
+                        auto zero = [&](auto) __attribute__((always_inline)) -> C { return C(0); };
+                        mrt_relax<SL>(a, heq(sA, m.muA), zero, rates(wA),
+                                      [&](auto kc, C v) __attribute__((always_inline)) {
+                                          push(IC<A0 + decltype(kc)::value>{}, kc, SLT{}, v);
+                                      });
+                        mrt_relax<SL>(b, heq(sB, m.muB), zero, rates(wB),
+                                      [&](auto kc, C v) __attribute__((always_inline)) {
+                                          push(IC<B0 + decltype(kc)::value>{}, kc, SLT{}, v);
+                                      });
+                    } else if constexpr (TRTC) {
                         // TRT: the mobility sets the antisymmetric rate w- = wA (wB); w+ from
                         // the magic parameter, 1/w+ - 1/2 = Lambda_s / (M / c_s^2)
                         const C ls = KC(P.trt_ls, P.f32.trt_ls);

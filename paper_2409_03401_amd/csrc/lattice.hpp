@@ -142,4 +142,96 @@ struct D3Q7K {
     static constexpr double cs2 = 0.25;
 };
 
+// ---------------------------------------------------------------------------
+// Moment basis of a lattice for the multiple-relaxation-time collision: rows
+// orthogonal in the weighted product <a, b> = sum_k w_k a_k b_k, from Gram-Schmidt
+// over polynomials in the lattice vector of increasing order (the second order split
+// into its trace and traceless parts), skipping those dependent on the lattice.
+// The inverse is M^-1_{k i} = w_k M_ik / <M_i, M_i>.  Built at compile time.
+
+template <int Q>
+struct MomentBasis {
+    double M[Q][Q];
+    double invD[Q];  // 1 / <M_i, M_i>
+    int order[Q];
+};
+
+// value of polynomial j (and its order) at the vector (x, y, z) in 2D or 3D
+constexpr double basis_poly(int dim, int j, int x, int y, int z, int& order) {
+    if (dim == 2) {
+        // 1, x, y, x^2 + y^2, x^2 - y^2, xy, x^2 y, x y^2, x^2 y^2
+        const int ord[9] = {0, 1, 1, 2, 2, 2, 3, 3, 4};
+        order = ord[j];
+        switch (j) {
+            case 0: return 1;
+            case 1: return x;
+            case 2: return y;
+            case 3: return x * x + y * y;
+            case 4: return x * x - y * y;
+            case 5: return x * y;
+            case 6: return x * x * y;
+            case 7: return x * y * y;
+            default: return x * x * y * y;
+        }
+    }
+    const int ord[19] = {0, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 4, 4, 4};
+    order = ord[j];
+    switch (j) {
+        case 0: return 1;
+        case 1: return x;
+        case 2: return y;
+        case 3: return z;
+        case 4: return x * x + y * y + z * z;
+        case 5: return 2 * x * x - y * y - z * z;
+        case 6: return y * y - z * z;
+        case 7: return x * y;
+        case 8: return x * z;
+        case 9: return y * z;
+        case 10: return x * x * y;
+        case 11: return x * x * z;
+        case 12: return y * y * x;
+        case 13: return y * y * z;
+        case 14: return z * z * x;
+        case 15: return z * z * y;
+        case 16: return x * x * y * y;
+        case 17: return x * x * z * z;
+        default: return y * y * z * z;
+    }
+}
+
+// L: a lattice in the kernel frame (2D lattices use x and z)
+template <class L>
+constexpr MomentBasis<L::Q> make_moment_basis() {
+    MomentBasis<L::Q> B{};
+    constexpr int Q = L::Q;
+    const int npoly = L::DIM == 2 ? 9 : 19;
+    int nrows = 0;
+    for (int j = 0; j < npoly && nrows < Q; ++j) {
+        double v[Q] = {};
+        int ord = 0;
+        for (int k = 0; k < Q; ++k) {
+            // 2D kernel frame: the second axis of the lattice is z
+            const int x = L::ex(k), y = L::DIM == 2 ? L::ez(k) : L::ey(k), z = L::DIM == 2 ? 0 : L::ez(k);
+            v[k] = basis_poly(L::DIM, j, x, y, z, ord);
+        }
+        for (int r = 0; r < nrows; ++r) {
+            double num = 0, den = 0;
+            for (int k = 0; k < Q; ++k) {
+                num += L::w(k) * v[k] * B.M[r][k];
+                den += L::w(k) * B.M[r][k] * B.M[r][k];
+            }
+            for (int k = 0; k < Q; ++k) v[k] -= num / den * B.M[r][k];
+        }
+        double nn = 0;
+        for (int k = 0; k < Q; ++k) nn += L::w(k) * v[k] * v[k];
+        if (nn > 1e-12) {
+            for (int k = 0; k < Q; ++k) B.M[nrows][k] = (v[k] > -1e-12 && v[k] < 1e-12) ? 0.0 : v[k];
+            B.invD[nrows] = 1.0 / nn;
+            B.order[nrows] = ord;
+            ++nrows;
+        }
+    }
+    return B;
+}
+
 }  // namespace lbm

@@ -70,9 +70,15 @@ int check_config(const lbm_config* c, Layout* L) {
         return fail(LBM_EUNSUPPORTED, "scalar lattice must be LBM_D2Q5, LBM_D2Q9, LBM_D3Q7 or LBM_D3Q19");
     }
     const bool paper_scalar = c->scalar == LBM_D2Q9 || c->scalar == LBM_D3Q19;
-    if (c->collision != LBM_BGK && c->collision != LBM_TRT)
-        return fail(LBM_EINVAL, "collision must be LBM_BGK or LBM_TRT");
+    if (c->collision != LBM_BGK && c->collision != LBM_TRT && c->collision != LBM_MRT)
+        return fail(LBM_EINVAL, "collision must be LBM_BGK, LBM_TRT or LBM_MRT");
     const bool trt = c->collision == LBM_TRT;
+    const bool mrt = c->collision == LBM_MRT;
+    if (mrt)
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 3; ++j)
+                if (!(c->mrt_rates[i][j] > 0 && c->mrt_rates[i][j] < 2))
+                    return fail(LBM_EUNSTABLE, "mrt_rates must lie in (0, 2)");
     if (c->variable_density != 0 && c->variable_density != 1)
         return fail(LBM_EINVAL, "variable_density must be 0 or 1");
     const bool vd = c->variable_density == 1;
@@ -92,7 +98,7 @@ int check_config(const lbm_config* c, Layout* L) {
             if (lmin < one_minus_w0)
                 return fail(LBM_EUNSTABLE, "kappa's smallest eigenvalue is below 1 - w_0 of the D2Q5 / D3Q7 lattice");
         }
-        if (trt || vd) return fail(LBM_EUNSUPPORTED, "general_kappa runs with the BGK Boussinesq step");
+        if (trt || mrt || vd) return fail(LBM_EUNSUPPORTED, "general_kappa runs with the BGK Boussinesq step");
     }
     if (vd && c->fluid == LBM_NONE) return fail(LBM_EINVAL, "variable_density needs a fluid lattice");
     if (vd && !(c->rho0 + c->drho > 0)) return fail(LBM_EINVAL, "variable_density needs rho0 + drho > 0");
@@ -164,7 +170,11 @@ int check_config(const lbm_config* c, Layout* L) {
     // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
     int want_tx = 0, want_ty = 0;
     if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
-    if (gk) {
+    if (mrt && vd) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with BGK or TRT");
+    if (mrt) {
+        L->ks = L->dim == 2 ? kernels_mrt_2d(L->qs, L->qf, L->prec) : kernels_mrt_3d(L->qs, L->qf, L->prec);
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "the MRT collision runs with FP64 or FP32 storage");
+    } else if (gk) {
         L->ks = L->dim == 2 ? kernels_gk_2d(L->qs, L->qf, L->prec) : kernels_gk_3d(L->qs, L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "general_kappa runs with FP64 or FP32 storage");
     } else if (vd) {
@@ -263,6 +273,12 @@ void fill_params(lbm_handle* h) {
     kp.f32.omega_gp = float(kp.omega_gp);
     kp.variable_density = c.variable_density;
     kp.general_k = c.general_kappa;
+    for (int i = 0; i < 3; ++i) {
+        kp.mrt_f[i] = c.mrt_rates[0][i];
+        kp.mrt_s[i] = c.mrt_rates[1][i];
+        kp.f32.mrt_f[i] = float(kp.mrt_f[i]);
+        kp.f32.mrt_s[i] = float(kp.mrt_s[i]);
+    }
     for (int i = 0; i < 3; ++i) {
         kp.kap0[i] = c.general_kappa ? c.kappa[0][i] : (i == 1 ? 0.0 : 1.0);
         kp.kap1[i] = c.general_kappa ? c.kappa[1][i] : (i == 1 ? 0.0 : 1.0);

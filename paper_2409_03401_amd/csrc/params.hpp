@@ -19,7 +19,8 @@ enum Mode : int { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_DIAG = 2, MODE_STEP_PHI 
 // collision operator of the fused step: the paper's BGK, or two relaxation times
 // (flags): COLL_TRT two relaxation times, COLL_VD the variable-density flow model
 // COLL_GK general curvature matrices of the free energies (2 x 2 closure per node)
-enum Coll : int { COLL_BGK = 0, COLL_TRT = 1, COLL_VD = 2, COLL_GK = 4 };
+// COLL_MRT multiple relaxation times on the lattice's moment basis
+enum Coll : int { COLL_BGK = 0, COLL_TRT = 1, COLL_VD = 2, COLL_GK = 4, COLL_MRT = 8 };
 
 // Storage traits.  FP64 / FP32 store every population as is.  The 16-bit
 // formats store the moving populations (k != 0) as d = (x - w_k ref) * 2^s in
@@ -50,6 +51,9 @@ struct KParams {
     // TRT (COLL_TRT): magic parameters of f and of the scalar lattices; symmetric rate of g
     double trt_lf, trt_ls, omega_gp;
     int variable_density;        // 1: f holds dimensionless populations (rho(phi) model)
+    // MRT (COLL_MRT): free rates of f (bulk, third, fourth order) and of g, h (second,
+    // third, fourth order)
+    double mrt_f[3], mrt_s[3];
     // general curvatures: kappa_pi = (k_AA, k_AB, k_BB) of phases 0 and 1 (dc/dmu of each
     // phase); general_k = 0 is the paper's identity
     double kap0[3], kap1[3];
@@ -65,6 +69,7 @@ struct KParams {
     struct {
         float cap, inv_W2, drho, gx, gy, gz, inv_rho0, rho0, nu0, nu1, omega_g, MA0, MA1, MB0, MB1;
         float trt_lf, trt_ls, omega_gp;
+        float mrt_f[3], mrt_s[3];
     } f32;
     // population copies addressed by the fused kernel: slot s of a copy starts at
     // base + (#moving slots before s) * stride_m + (#rest slots before s) * stride_r

@@ -25,8 +25,8 @@ LBM_NONE, LBM_D2Q9, LBM_D3Q19, LBM_D2Q5, LBM_D3Q7 = 0, 9, 19, 5, 7
 LBM_PERIODIC, LBM_WALLS = 0, 1
 LBM_FP64, LBM_FP32, LBM_FP32_FP16STORE, LBM_FP32_BF16STORE = 0, 1, 2, 3
 LBM_OUT_F64, LBM_OUT_F32 = 0, 1
-LBM_BGK, LBM_TRT = 0, 1
-_COLLISION = {"BGK": LBM_BGK, "TRT": LBM_TRT}
+LBM_BGK, LBM_TRT, LBM_MRT = 0, 1, 2
+_COLLISION = {"BGK": LBM_BGK, "TRT": LBM_TRT, "MRT": LBM_MRT}
 MOMENTS = ("phi", "cA", "cB", "muA", "muB", "p", "ux", "uy", "uz")
 DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interface_measure",
                "free_energy", "nan_count", "droplets", "mean_radius")
@@ -58,6 +58,7 @@ class _Config(ctypes.Structure):
         ("store_ref", ctypes.c_double * 4), ("store_shift", ctypes.c_int32 * 4),
         ("collision", ctypes.c_int32), ("variable_density", ctypes.c_int32), ("trt_magic", ctypes.c_double * 2),
         ("general_kappa", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kappa", (ctypes.c_double * 3) * 2),
+        ("mrt_rates", (ctypes.c_double * 3) * 2),
     ]
 
 
@@ -148,9 +149,11 @@ class LBMConfig:
     # (x - w_k store_ref[F]) * 2^store_shift[F]
     store_ref: Tuple[float, float, float, float] = (0.0, 0.5, 0.0, 0.0)
     store_shift: Tuple[int, int, int, int] = (8, 0, 6, 6)
-    # "BGK" (the paper's) or "TRT"; TRT magic parameters of (f, the scalar lattices)
+    # "BGK" (the paper's), "TRT" or "MRT"; TRT magic parameters of (f, the scalar lattices)
     collision: str = "BGK"
     trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)
+    # MRT free rates: f (bulk, third, fourth order), scalars (second, third, fourth order)
+    mrt_rates: Tuple[Tuple[float, float, float], Tuple[float, float, float]] = ((1.2, 1.1, 1.2), (1.1, 1.0, 1.2))
     # False: Boussinesq (the paper's); True: rho(phi) model with pressure and viscous forces
     variable_density: bool = False
     # general curvatures ((k_AA, k_AB, k_BB) of phase 0, of phase 1) = K (K_pi)^-1; None: identity
@@ -194,6 +197,9 @@ class LBMConfig:
             c.store_shift[i] = int(self.store_shift[i])
         c.collision = _COLLISION[self.collision]
         c.variable_density = int(bool(self.variable_density))
+        for i in range(2):
+            for j in range(3):
+                c.mrt_rates[i][j] = float(self.mrt_rates[i][j])
         c.general_kappa = int(self.kappa is not None)
         if self.kappa is not None:
             for pi in range(2):

@@ -37,7 +37,8 @@ def test_struct_layout_matches_header():
     assert lbm._Config.collision.offset == lbm._Config.store_shift.offset + 16
     assert lbm._Config.trt_magic.offset == lbm._Config.collision.offset + 8
     assert lbm._Config.general_kappa.offset == lbm._Config.trt_magic.offset + 16
-    assert ctypes.sizeof(lbm._Config) == lbm._Config.kappa.offset + 48
+    assert lbm._Config.mrt_rates.offset == lbm._Config.kappa.offset + 48
+    assert ctypes.sizeof(lbm._Config) == lbm._Config.mrt_rates.offset + 48
 
 
 def _cfg(**kw):
@@ -83,6 +84,9 @@ def test_state_bytes_layout():
     (dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0)), precision="bf16"), lbm.LBM_EUNSUPPORTED),
     (dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0)), collision="TRT"), lbm.LBM_EUNSUPPORTED),
     (dict(kappa=((0.6, 0.0, 1.0), (1.0, 0.0, 1.0))), lbm.LBM_EUNSTABLE),  # D2Q5: below 1 - w_0 = 2/3
+    (dict(collision="MRT", mrt_rates=((1.2, 2.0, 1.2), (1.0, 1.0, 1.0))), lbm.LBM_EUNSTABLE),
+    (dict(collision="MRT", precision="bf16"), lbm.LBM_EUNSUPPORTED),
+    (dict(collision="MRT", fluid="D2Q9", variable_density=True), lbm.LBM_EUNSUPPORTED),
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:

@@ -1,0 +1,138 @@
+"""The multiple-relaxation-time collision on the GPU (LBM_MRT), against the FP64
+oracle's MRT (oracle/lbm.py, mrt_collide on lattices.moment_basis) on the same seeded
+inputs.
+
+Bars as for BGK: FP64 populations within 1e-12, FP32 relative L2 within 1e-5 on phi,
+c^A, c^B and on the populations.  Property at a size of its own: with the shear and
+third-order rates on the magic pair (Lambda = 3/16) the steady Poiseuille profile
+between half-way walls is the exact parabola whatever the bulk and fourth-order
+rates (the oracle pin, here on the GPU in FP64).
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+from helpers import (MOMENT_NAMES, field_errors, gpu_config, max_abs, oracle_moments, oracle_params,
+                     oracle_populations, rel_l2)
+from oracle import analytic
+from oracle import lbm as olbm
+from paper_2409_03401_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MRT = dict(collision="MRT", mrt_rates=((1.2, 1.1, 1.3), (1.1, 1.0, 1.2)))
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _drops(shape, n, rmin, rmax, W, seed, wall_axes=()):
+    rng = np.random.default_rng(seed)
+    drops = inputs.place_droplets(shape, n, rmin, rmax, W, rng, wall_axes=wall_axes)
+    phi = inputs.droplet_field(shape, drops, W, wall_axes=wall_axes)
+    mu = rng.normal(0.0, 1e-3, (2,) + shape)
+    return phi, mu[0], mu[1]
+
+
+@functools.lru_cache(maxsize=None)
+def case(name):
+    """(params, phi0, muA0, muB0, steps); unequal mobilities per phase so that the
+    transport rates vary from node to node."""
+    flow2 = dict(drho=0.5, g=(0.0, -1e-4, 0.0), sigma=1e-3, nu=(0.1, 0.05))
+    flow3 = dict(drho=0.5, g=(0.0, 0.0, -1e-4), sigma=1e-3, nu=(0.1, 0.05))
+    mob = dict(M_A=(0.1, 0.05), M_B=(0.08, 0.12))
+    if name == "2d_d2q5_flow_walls":
+        p = inputs._base(70, 45, 1, W=4.0, fluid="D2Q9", bc=("periodic", "walls", "periodic"), **flow2, **mob, **MRT)
+        return (p, *_drops((1, 45, 70), 3, 4.0, 8.0, 4.0, 51, (1,)), 40)
+    if name == "2d_d2q9_noflow":
+        p = inputs._base(66, 40, 1, W=3.0, scalar="D2Q9", **mob, **MRT)
+        return (p, *_drops((1, 40, 66), 4, 3.0, 7.0, 3.0, 52), 40)
+    if name == "3d_d3q7_flow_walls":
+        p = inputs._base(21, 18, 20, W=4.0, fluid="D3Q19", bc=("periodic", "walls", "walls"), **flow3, **mob, **MRT)
+        return (p, *_drops((20, 18, 21), 1, 4.0, 5.0, 4.0, 53, (1, 2)), 12)
+    if name == "3d_d3q19_flow":
+        p = inputs._base(18, 17, 19, W=4.0, fluid="D3Q19", scalar="D3Q19", bc=("walls", "periodic", "periodic"),
+                         **flow3, **mob, **MRT)
+        return (p, *_drops((19, 17, 18), 1, 4.0, 5.0, 4.0, 54, (0,)), 10)
+    raise KeyError(name)
+
+
+CASES = ["2d_d2q5_flow_walls", "2d_d2q9_noflow", "3d_d3q7_flow_walls", "3d_d3q19_flow"]
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name):
+    p, phi0, muA0, muB0, steps = case(name)
+    prm = oracle_params(p)
+    st = olbm.run(olbm.init(phi0, muA0, muB0, prm), prm, steps)
+    return oracle_moments(prm, st), oracle_populations(prm, st)
+
+
+def _gpu(name, precision):
+    from paper_2409_03401_amd.lbm import Simulation
+    p, phi0, muA0, muB0, steps = case(name)
+    print(f"[mrt] {name} shape={phi0.shape} {precision} steps={steps}", flush=True)
+    sim = Simulation(gpu_config(p, precision), phi0, muA0, muB0)
+    sim.step(steps)
+    return {k: v.cpu().numpy() for k, v in sim.moments().items()}, sim.populations().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_mrt_parity_fp64(name):
+    _require_gpu()
+    mom, pops = _gpu(name, "fp64")
+    ora_m, ora_p = oracle_case(name)
+    err = max_abs(pops, ora_p)
+    assert err <= 1e-12, err
+    for k in MOMENT_NAMES:
+        assert max_abs(mom[k], ora_m[k]) <= 1e-12 * max(1.0, np.abs(ora_m[k]).max()), k
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_mrt_parity_fp32(name):
+    _require_gpu()
+    mom, pops = _gpu(name, "fp32")
+    ora_m, ora_p = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("phi", "cA", "cB"):
+        assert errs[k][0] <= 1e-5, (k, errs[k])
+    assert rel_l2(pops, ora_p) <= 1e-5
+
+
+@pytest.mark.parametrize("nu", [0.5, 0.2])
+def test_mrt_poiseuille_exact_on_gpu(nu):
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation
+    N = 12
+    w_nu = olbm.rate(nu, 1.0 / 3.0)
+    s3 = olbm.trt_partner_rate(w_nu, 3.0 / 16.0)
+    p = inputs._base(64, N, 1, W=4.0, fluid="D2Q9", bc=("periodic", "walls", "periodic"), drho=1.0,
+                     g=(1e-6, 0.0, 0.0), sigma=1e-3, nu=(nu, nu), collision="MRT",
+                     mrt_rates=((1.1, s3, 1.3), (1.0, 1.0, 1.0)))
+    phi0 = np.ones((1, N, 64))
+    sim = Simulation(gpu_config(p, "fp64"), phi0, 0 * phi0, 0 * phi0)
+    sim.step(1000 if nu == 0.5 else 2200)
+    ux = sim.moments(("ux",))["ux"].cpu().numpy()[0]
+    ref = analytic.poiseuille(np.arange(N), N, 1e-6, 1.0, nu)
+    assert np.abs(ux - ref[:, None]).max() < 1e-9 * ref.max()
+
+
+def test_mrt_unsupported():
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import LBM_EUNSUPPORTED, LBMError, Simulation
+    p, phi0, muA0, muB0, _ = case("2d_d2q5_flow_walls")
+    with pytest.raises(LBMError) as e:
+        Simulation(gpu_config(p, "fp16"), phi0, muA0, muB0)
+    assert e.value.code == LBM_EUNSUPPORTED
+    sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
+    work = sim.adjoint_workspace()
+    with pytest.raises(LBMError) as e:
+        sim.adjoint_seed(sim.save(), np.zeros(phi0.size), work)
+    assert e.value.code == LBM_EUNSUPPORTED
