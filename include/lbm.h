@@ -106,7 +106,7 @@ extern "C" {
 #define LBM_D_SUM_CA 0        /* sum_x c^A                                          */
 #define LBM_D_SUM_CB 1        /* sum_x c^B                                          */
 #define LBM_D_SUM_PHI 2       /* sum_x phi                                          */
-#define LBM_D_KINETIC 3       /* sum_x rho0 |u|^2 / 2                               */
+#define LBM_D_KINETIC 3       /* sum_x rho |u|^2 / 2 (rho0, or rho(phi) if variable) */
 #define LBM_D_MAX_U 4         /* max_x |u|                                          */
 #define LBM_D_INTERFACE 5     /* sum_x (4/W) phi (1 - phi), integrand of Eq. Rmoy_2D */
 #define LBM_D_FREE_ENERGY 6   /* sum_x [W^2/2 |grad phi|^2 + omega_dw + lambda/2 |mu|^2] */

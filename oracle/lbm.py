@@ -542,7 +542,8 @@ DIAG_NAMES = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u",
 
 def diagnostics(st, prm):
     """Global reductions of the current state:
-    sums of c^A, c^B and phi; kinetic energy sum rho0 |u|^2 / 2; max |u|;
+    sums of c^A, c^B and phi; kinetic energy sum rho |u|^2 / 2 (rho0, or rho(phi) with
+    variable density); max |u|;
     interface measure sum (4/W) phi (1 - phi) (the integrand of Eq. Rmoy_2D);
     free energy sum [W^2/2 |grad phi|^2 + omega_dw(phi) + lambda/2 (mu_A^2 + mu_B^2)],
     which is the functional of Eq. functional in units of H after the Legendre
@@ -560,7 +561,8 @@ def diagnostics(st, prm):
     bad = ~(np.isfinite(phi) & np.isfinite(m["cA"]) & np.isfinite(m["cB"]))
     n_drops = geometry.euler_characteristic(phi.real, prm.bc)
     return dict(sum_cA=m["cA"].sum(), sum_cB=m["cB"].sum(), sum_phi=phi.sum(),
-                kinetic_energy=(0.5 * prm.rho0 * u2).sum(), max_u=np.sqrt(u2.real).max(),
+                kinetic_energy=(0.5 * (density(phi, prm) if prm.variable_density else prm.rho0) * u2).sum(),
+                max_u=np.sqrt(u2.real).max(),
                 interface_measure=((4.0 / prm.W) * phi * (1.0 - phi)).sum(),
                 free_energy=fe.sum(), nan_count=int(bad.sum()),
                 droplets=n_drops, mean_radius=geometry.mean_radius(phi.real, prm.W, n_drops))

@@ -992,7 +992,7 @@ k_lbm(const KParams P) {
                 acc[0] += sA;
                 acc[1] += sB;
                 acc[2] += m.phi;
-                acc[3] += 0.5 * P.rho0 * u2;
+                acc[3] += 0.5 * (VD ? P.rho0 + P.drho * m.phi : P.rho0) * u2;
                 acc[4] = fmax(acc[4], sqrt(u2));
                 acc[5] += (4.0 / P.W) * m.phi * (1.0 - m.phi);
                 acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) + P.lam * bulk_free_energy<GK>(m.phi, m.muA, m.muB, P);

@@ -65,7 +65,7 @@ def oracle_case(name):
     p, phi0, muA0, muB0, steps = case(name)
     prm = oracle_params(p)
     st = olbm.run(olbm.init(phi0, muA0, muB0, prm), prm, steps)
-    return oracle_moments(prm, st), oracle_populations(prm, st)
+    return oracle_moments(prm, st), oracle_populations(prm, st), olbm.diagnostics(st, prm)
 
 
 def _gpu(name, precision):
@@ -74,26 +74,30 @@ def _gpu(name, precision):
     print(f"[variable density] {name} shape={phi0.shape} {precision} steps={steps}", flush=True)
     sim = Simulation(gpu_config(p, precision), phi0, muA0, muB0)
     sim.step(steps)
-    return {k: v.cpu().numpy() for k, v in sim.moments().items()}, sim.populations().cpu().numpy()
+    return ({k: v.cpu().numpy() for k, v in sim.moments().items()}, sim.populations().cpu().numpy(),
+            sim.diagnostics())
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_vd_parity_fp64(name):
     _require_gpu()
-    mom, pops = _gpu(name, "fp64")
-    ora_m, ora_p = oracle_case(name)
+    mom, pops, diag = _gpu(name, "fp64")
+    ora_m, ora_p, ora_d = oracle_case(name)
     err = max_abs(pops, ora_p)
     assert err <= 1e-12, err
     for k in MOMENT_NAMES:
         assert max_abs(mom[k], ora_m[k]) <= 1e-12 * max(1.0, np.abs(ora_m[k]).max()), k
     assert np.abs(ora_m["ux"]).max() > 1e-7   # a flow develops
+    # kinetic energy with rho(phi), max |u|, free energy
+    for k in ("kinetic_energy", "max_u", "free_energy"):
+        assert abs(diag[k] - ora_d[k]) <= 1e-10 * abs(ora_d[k]), k
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_vd_parity_fp32(name):
     _require_gpu()
-    mom, pops = _gpu(name, "fp32")
-    ora_m, ora_p = oracle_case(name)
+    mom, pops, _ = _gpu(name, "fp32")
+    ora_m, ora_p, _ = oracle_case(name)
     errs = field_errors(mom, ora_m)
     print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
     for k in ("phi", "cA", "cB"):
