@@ -28,6 +28,12 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+def _variant(w, **kw):
+    """The same seeded workload with model-variant parameters."""
+    w.params = dict(w.params, **kw)
+    return w
+
+
 WORKLOADS = {
     # name: (builder, precision, steps)
     "sediment_3d_256_fp32": (lambda: inputs.sediment_3d(n=256, precision="fp32"), "fp32", 3),
@@ -35,6 +41,14 @@ WORKLOADS = {
     "ostwald_2d_1024_fp32": (lambda: inputs.ostwald_2d(n=1024, precision="fp32"), "fp32", 3),
     "single_drop_2d_512_fp32": (lambda: inputs.single_drop_2d(n=512, precision="fp32"), "fp32", 3),
     "spinodal_3d_512_bf16": (lambda: inputs.spinodal_3d(n=512, precision="bf16"), "bf16", 1),
+    # model variants on the 256^3 sedimentation workload (the bench.py variant lines)
+    "sediment_3d_256_trt_fp32": (lambda: _variant(inputs.sediment_3d(n=256), collision="TRT",
+                                                  trt_magic=(3.0 / 16.0, 0.25)), "fp32", 3),
+    "sediment_3d_256_mrt_fp32": (lambda: _variant(inputs.sediment_3d(n=256), collision="MRT",
+                                                  mrt_rates=((1.2, 1.1, 1.2), (1.1, 1.0, 1.2))), "fp32", 3),
+    "sediment_3d_256_vd_fp32": (lambda: _variant(inputs.sediment_3d(n=256), variable_density=True), "fp32", 3),
+    "sediment_3d_256_kappa_fp32": (lambda: _variant(inputs.sediment_3d(n=256),
+                                                    kappa=((1.0, 0.1, 0.9), (0.95, -0.05, 1.2))), "fp32", 3),
 }
 
 
