@@ -354,6 +354,21 @@ def main():
                 "GBps": round(bytes_per_update(c16) * c16.nodes / (kms16 * 1e-3) / 1e9, 1),
             }
 
+    if not args.no_extra and args.workload == "sediment_3d_256":
+        # model variants (collision operators, variable density, the paper's lattices)
+        variants = {}
+        for name in ("sediment_3d_256_trt", "sediment_3d_256_mrt", "sediment_3d_256_vd", "ostwald_paper_2d_4096"):
+            print(f"[bench] timing the variant {name}", file=sys.stderr, flush=True)
+            wv = build_workload(name)
+            cv, wallv, kmsv, _, _ = time_gpu(wv, args.steps, args.warmup)
+            variants[name] = {
+                "MLUPS": round(cv.nodes * args.steps / wallv / 1e6, 1),
+                "bytes_per_update": bytes_per_update(cv),
+                "kernel_ms": round(kmsv, 4),
+                "GBps": round(bytes_per_update(cv) * cv.nodes / (kmsv * 1e-3) / 1e9, 1),
+            }
+        extra["variants"] = variants
+
     if not args.no_extra:
         print("[bench] timing the adjoint (forward, recompute + backward)", file=sys.stderr, flush=True)
         extra["adjoint"] = adjoint_timing()
