@@ -38,6 +38,9 @@ WORKLOADS = {
     "sediment_3d_256_mrt": dict(kind="sediment_3d", n=256, precision="fp32", collision="MRT"),
     # the variable-density flow model (density ratio 1.5) on the sedimentation workload
     "sediment_3d_256_vd": dict(kind="sediment_3d", n=256, precision="fp32", variable_density=True),
+    # ripening with sedimentation at 512^3 (the paper's 3D run shape, one GPU's share)
+    "ripening_sediment_3d_512_bf16": dict(kind="sediment_3d", n=512, precision="bf16", ndrops=2000,
+                                          rmin=6.0, rmax=12.0, phi_eq=0.25),
 }
 
 
@@ -69,7 +72,8 @@ def _build_workload(name):
     spec = WORKLOADS[name]
     kind = spec["kind"]
     if kind == "sediment_3d":
-        return inputs.sediment_3d(n=spec["n"], precision=spec["precision"])
+        kw = {k: spec[k] for k in ("ndrops", "rmin", "rmax", "phi_eq") if k in spec}
+        return inputs.sediment_3d(n=spec["n"], precision=spec["precision"], **kw)
     if kind == "spinodal_3d":
         return inputs.spinodal_3d(n=spec["n"], precision=spec["precision"])
     if kind == "ostwald_2d":

@@ -236,8 +236,13 @@ def ostwald_2d(n=1024, ndrops=400, precision="fp32", rng_index=1):
     return Workload(f"ostwald_2d_{n}_{precision}", p, precision, 20000, phi0, mu[0], mu[1], drops=drops)
 
 
-def sediment_3d(n=256, ndrops=64, rmin=10.0, rmax=18.0, precision="fp32", rng_index=2, nz=None, ny=None):
-    """C3: 3D droplets sedimenting between walls at z = 0, n - 1, D3Q19 + 3 x D3Q7."""
+def sediment_3d(n=256, ndrops=64, rmin=10.0, rmax=18.0, precision="fp32", rng_index=2, nz=None, ny=None,
+                phi_eq=None):
+    """C3: 3D droplets sedimenting between walls at z = 0, n - 1, D3Q19 + 3 x D3Q7.
+    phi_eq: use the paper's initial condition (Section 4.2.1) instead of mu_0 = 0 with
+    the closure: compositions stepped at phi = 1/2 for the inventory whose equilibrium
+    phase fraction is phi_eq (a supersaturated matrix when phi_eq exceeds the droplets'
+    fraction), mu_0 = 0."""
     nz = nz or n
     ny = ny or n
     p = _base(n, ny, nz, fluid="D3Q19", bc=("periodic", "periodic", "walls"), drho=0.5,
@@ -246,7 +251,12 @@ def sediment_3d(n=256, ndrops=64, rmin=10.0, rmax=18.0, precision="fp32", rng_in
     drops = place_droplets((nz, ny, n), ndrops, rmin, rmax, p["W"], rng, wall_axes=(2,))
     phi0 = droplet_field((nz, ny, n), drops, p["W"], wall_axes=(2,))
     z = np.zeros((nz, ny, n))
-    return Workload(f"sediment_3d_{n}_{precision}", p, precision, 10000, phi0, z, z.copy(), drops=drops)
+    c0 = None
+    if phi_eq is not None:
+        c_eq = p["c_eq"]
+        cg = tuple(c_eq[0][a] + phi_eq * (c_eq[1][a] - c_eq[0][a]) for a in range(2))
+        c0, _ = stepped_composition(phi0, c_eq, cg)
+    return Workload(f"sediment_3d_{n}_{precision}", p, precision, 10000, phi0, z, z.copy(), drops=drops, c0=c0)
 
 
 def single_drop_2d(n=512, R=40.0, centre=None, precision="fp32"):
