@@ -33,6 +33,7 @@ WORKLOADS = {
     "single_drop_2d_512": dict(kind="single_drop_2d", n=512, precision="fp32"),
     # the paper's own discretisation and initial condition (D2Q9 for every equation)
     "ostwald_paper_2d_4096": dict(kind="ostwald_paper_2d", n=4096, precision="fp32"),
+    "ostwald_paper_2d_4096_bf16": dict(kind="ostwald_paper_2d", n=4096, precision="bf16"),
     # the two-relaxation-time collision on the sedimentation workload
     "sediment_3d_256_trt": dict(kind="sediment_3d", n=256, precision="fp32", collision="TRT"),
     "sediment_3d_256_mrt": dict(kind="sediment_3d", n=256, precision="fp32", collision="MRT"),

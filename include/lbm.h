@@ -34,7 +34,7 @@ extern "C" {
 /* ---- configuration values --------------------------------------------------- */
 #define LBM_NONE 0            /* no flow: u = 0, no f populations                  */
 #define LBM_D2Q9 9            /* fluid lattices, Tables tab:D2Q9 / tab:D3Q19; also */
-#define LBM_D3Q19 19          /* the paper's scalar lattices (FP64 / FP32 only)    */
+#define LBM_D3Q19 19          /* the paper's scalar lattices (no adjoint)          */
 #define LBM_D2Q5 5            /* reduced scalar lattices for phi, c^A, c^B         */
 #define LBM_D3Q7 7
 

@@ -185,7 +185,7 @@ int check_config(const lbm_config* c, Layout* L) {
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "the TRT collision runs with FP64 or FP32 storage");
     } else if (paper_scalar) {
         L->ks = L->dim == 2 ? kernels_paper_2d(L->qf, L->prec) : kernels_paper_3d(L->qf, L->prec);
-        if (!L->ks) return fail(LBM_EUNSUPPORTED, "D2Q9 / D3Q19 scalar lattices run with FP64 or FP32 storage");
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "no kernel for the D2Q9 / D3Q19 scalar lattices at this precision");
     } else {
         L->ks = L->dim == 2 ? kernels_2d(L->qf, L->prec, want_tx) : kernels_3d(L->qf, L->prec, want_tx, want_ty);
     }

@@ -4,7 +4,7 @@ Compos_Init: c stepped at phi = 1/2 with mu = 0, lbm_init_composition).
 
 Parity with the FP64 oracle on the same seeded inputs, bars as for the reduced
 lattices: FP64 populations within 1e-12, FP32 relative L2 within 1e-5 on phi, c^A,
-c^B.  The full-size ripening box of the paper (4096^2) is checked on sampled nodes
+c^B, 16-bit storage within 1e-3 on c^A, c^B (1e-2 on phi).  The full-size ripening box of the paper (4096^2) is checked on sampled nodes
 against exact oracle windows.
 """
 
@@ -113,6 +113,21 @@ def test_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
+@pytest.mark.parametrize("name", ["2d_flow_walls", "3d_flow_walls", "2d_paper_initial_condition"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_parity_16bit(name, prec):
+    """16-bit storage of the moving populations (FP32 rest populations and arithmetic)
+    on the paper's lattices: c^A, c^B within 1e-3 relative L2, phi within 1e-2."""
+    _require_gpu()
+    _, mom, _ = _gpu(name, prec)
+    ora_m, _ = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("cA", "cB"):
+        assert errs[k][0] <= 1e-3, (k, errs[k])
+    assert errs["phi"][0] <= 1e-2
+
+
 def test_paper_initial_condition_moments():
     """Right after lbm_init_composition the compositions are the given step field
     exactly (FP64) and the mean composition is the inventory (0.31, 0.31)."""
@@ -133,9 +148,6 @@ def test_unsupported_combinations():
     _require_gpu()
     from paper_2409_03401_amd.lbm import LBM_EUNSUPPORTED, LBMError, Simulation
     p, phi0, muA0, muB0, _, _ = case("2d_noflow_periodic")
-    with pytest.raises(LBMError) as e:
-        Simulation(gpu_config(p, "bf16"), phi0, muA0, muB0)
-    assert e.value.code == LBM_EUNSUPPORTED
     sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
     work = sim.adjoint_workspace()
     with pytest.raises(LBMError) as e:
