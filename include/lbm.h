@@ -45,8 +45,8 @@ extern "C" {
  * added as in BGK).  The transport coefficient sets one rate as in BGK: the
  * viscosity sets w+ of f, the mobilities set w- of g, h^A, h^B; the other follows
  * from the magic parameter Lambda = (1/w+ - 1/2)(1/w- - 1/2) (trt_magic; 3/16
- * puts half-way bounce-back walls exactly at the half link).  FP64 and FP32
- * storage, no adjoint. */
+ * puts half-way bounce-back walls exactly at the half link).  Any storage
+ * precision, no adjoint. */
 #define LBM_BGK 0
 #define LBM_TRT 1
 /* LBM_MRT, the multiple-relaxation-time alternative Section 3 names: X - X^eq is
@@ -57,10 +57,10 @@ extern "C" {
  * fourth orders at mrt_rates[0][0..2], orders 0 and 1 conserved.  g, h^A, h^B: the
  * first order (diffusive flux) at the mobility rate, orders 0 and 2 at
  * mrt_rates[1][0], third and fourth at mrt_rates[1][1..2].  Rates in (0, 2);
- * FP64 and FP32 storage, Boussinesq, no adjoint. */
+ * any storage precision, Boussinesq, no adjoint. */
 #define LBM_MRT 2
 
-/* general_kappa = 1 (FP64 / FP32 storage, BGK, Boussinesq, no adjoint): the
+/* general_kappa = 1 (any storage precision, BGK, Boussinesq, no adjoint): the
  * quadratic free energies of Eq. Taylor with full curvature matrices K_pi, given
  * as kappa_pi = K (K_pi)^-1 (symmetric positive definite; the identity is the
  * paper's model).  The grand potentials become -1/2 mu.kappa_pi mu - mu.c_pi^eq,

@@ -95,19 +95,27 @@ const KernelSet* family_for_prec(int prec) {
     }
 }
 
-// the paper's scalar lattices (BGK): all four storage precisions, no adjoint
-template <class SL, class FL, int TX, int TY>
+// the paper's scalar lattices, the TRT / MRT collisions and general curvatures: all
+// four storage precisions, no adjoint
+template <class SL, class FL, int TX, int TY, int COLL = COLL_BGK>
 const KernelSet* family_all_prec_noadj(int prec) {
     switch (prec) {
-        case P64: return &Family<SL, FL, P64, TX, TY, false>::set;
-        case P32: return &Family<SL, FL, P32, TX, TY, false>::set;
-        case P16: return &Family<SL, FL, P16, TX, TY, false>::set;
-        case PB16: return &Family<SL, FL, PB16, TX, TY, false>::set;
+        case P64: return &Family<SL, FL, P64, TX, TY, false, COLL>::set;
+        case P32: return &Family<SL, FL, P32, TX, TY, false, COLL>::set;
+        case P16: return &Family<SL, FL, P16, TX, TY, false, COLL>::set;
+        case PB16: return &Family<SL, FL, PB16, TX, TY, false, COLL>::set;
         default: return nullptr;
     }
 }
 
-// the TRT / MRT collisions and the other model variants: FP64 and FP32 storage, no adjoint
+// one precision of a family without adjoint (for splitting large families over
+// translation units)
+template <class SL, class FL, int TX, int TY, int COLL, int PREC>
+const KernelSet* family_one_prec() {
+    return &Family<SL, FL, PREC, TX, TY, false, COLL>::set;
+}
+
+// the variable-density model: FP64 and FP32 storage, no adjoint
 template <class SL, class FL, int TX, int TY, int COLL = COLL_BGK>
 const KernelSet* family_fp_only(int prec) {
     switch (prec) {

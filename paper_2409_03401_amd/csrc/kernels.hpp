@@ -734,6 +734,7 @@ k_lbm(const KParams P) {
                             return wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu)) - C(0.5) * Fk;
                         };
                         C Fks[QF];
+                        C resm = C(0), restm = C(0);
                         mrt_relax<FL>(fpop,
                             [&](auto kc) __attribute__((always_inline)) -> C {
                                 return feqs(kc, Fks[decltype(kc)::value]);
@@ -748,7 +749,11 @@ k_lbm(const KParams P) {
                                 else if constexpr (o == 3) return KC(P.mrt_f[1], P.f32.mrt_f[1]);
                                 else return KC(P.mrt_f[2], P.f32.mrt_f[2]);
                             },
-                            [&](auto kc, C v) __attribute__((always_inline)) { push(kc, kc, FLT{}, v); });
+                            [&](auto kc, C v) __attribute__((always_inline)) {
+                                if constexpr (decltype(kc)::value == 0 && FEEDBACK) restm = v;
+                                else push_r(kc, kc, FLT{}, v, resm);
+                            });
+                        if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, restm + resm);
                     } else if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
@@ -780,23 +785,26 @@ k_lbm(const KParams P) {
                             if constexpr (VD) Fk *= fsc;
                             eqs = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu)) - C(0.5) * Fk;
                         };
+                        C res = C(0), rest = C(0);
                         static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                             constexpr int k = decltype(kc)::value;
                             constexpr int o = FL::opp(k);
                             if constexpr (k == 0) {
                                 C eqs, Fk;
                                 eqsrc(kc, eqs, Fk);
-                                push(kc, kc, FLT{}, fpop[0] - wf * (fpop[0] - eqs) + Fk);
+                                rest = fpop[0] - wf * (fpop[0] - eqs) + Fk;
+                                if constexpr (!FEEDBACK) push(kc, kc, FLT{}, rest);
                             } else if constexpr (k < o) {
                                 C eqk, Fk, eqo, Fo;
                                 eqsrc(kc, eqk, Fk);
                                 eqsrc(IC<o>{}, eqo, Fo);
                                 const C nk = fpop[k] - eqk, no = fpop[o] - eqo;
                                 const C sp = wf * C(0.5) * (nk + no), sm = wm * C(0.5) * (nk - no);
-                                push(kc, kc, FLT{}, fpop[k] - sp - sm + Fk);
-                                push(IC<o>{}, IC<o>{}, FLT{}, fpop[o] - sp + sm + Fo);
+                                push_r(kc, kc, FLT{}, fpop[k] - sp - sm + Fk, res);
+                                push_r(IC<o>{}, IC<o>{}, FLT{}, fpop[o] - sp + sm + Fo, res);
                             }
                         });
+                        if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + res);
                     }
                 }
 
@@ -812,6 +820,7 @@ k_lbm(const KParams P) {
                         // MRT: the first order (diffusive flux) at the M_phi rate, orders 0
                         // and 2 at the given even rate, third and fourth at theirs
                         const C S = C(m.S), hS = C(0.5) * C(m.S);
+                        C resm = C(0), restm = C(0);
                         mrt_relax<SL>(g,
                             [&](auto kc) __attribute__((always_inline)) -> C {
                                 constexpr int k = decltype(kc)::value;
@@ -831,8 +840,10 @@ k_lbm(const KParams P) {
                                 else return KC(P.mrt_s[0], P.f32.mrt_s[0]);
                             },
                             [&](auto kc, C v) __attribute__((always_inline)) {
-                                push(IC<G0 + decltype(kc)::value>{}, kc, SLT{}, v);
+                                if constexpr (decltype(kc)::value == 0 && FEEDBACK) restm = v;
+                                else push_r(IC<G0 + decltype(kc)::value>{}, kc, SLT{}, v, resm);
                             });
+                        if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, restm + resm);
                     } else if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
@@ -862,18 +873,21 @@ k_lbm(const KParams P) {
                             else
                                 return wk * (phi - hS);
                         };
+                        C res = C(0), rest = C(0);
                         static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
                             constexpr int k = decltype(kc)::value;
                             constexpr int o = SL::opp(k);
                             if constexpr (k == 0) {
-                                push(IC<G0>{}, kc, SLT{}, g[0] - wp * (g[0] - eqs(kc)) + C(SL::w(0)) * S);
+                                rest = g[0] - wp * (g[0] - eqs(kc)) + C(SL::w(0)) * S;
+                                if constexpr (!FEEDBACK) push(IC<G0>{}, kc, SLT{}, rest);
                             } else if constexpr (k < o) {
                                 const C nk = g[k] - eqs(kc), no = g[o] - eqs(IC<o>{});
                                 const C sp = wp * C(0.5) * (nk + no), sm = wg * C(0.5) * (nk - no);
-                                push(IC<G0 + k>{}, kc, SLT{}, g[k] - sp - sm + C(SL::w(k)) * S);
-                                push(IC<G0 + o>{}, IC<o>{}, SLT{}, g[o] - sp + sm + C(SL::w(o)) * S);
+                                push_r(IC<G0 + k>{}, kc, SLT{}, g[k] - sp - sm + C(SL::w(k)) * S, res);
+                                push_r(IC<G0 + o>{}, IC<o>{}, SLT{}, g[o] - sp + sm + C(SL::w(o)) * S, res);
                             }
                         });
+                        if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + res);
                     }
                 }
 
@@ -905,25 +919,32 @@ k_lbm(const KParams P) {
                             };
                         };
                         auto zero = [&](auto) __attribute__((always_inline)) -> C { return C(0); };
+                        C resA = C(0), restA = C(0), resB = C(0), restB = C(0);
                         mrt_relax<SL>(a, heq(sA, m.muA), zero, rates(wA),
                                       [&](auto kc, C v) __attribute__((always_inline)) {
-                                          push(IC<A0 + decltype(kc)::value>{}, kc, SLT{}, v);
+                                          if constexpr (decltype(kc)::value == 0 && FEEDBACK) restA = v;
+                                          else push_r(IC<A0 + decltype(kc)::value>{}, kc, SLT{}, v, resA);
                                       });
                         mrt_relax<SL>(b, heq(sB, m.muB), zero, rates(wB),
                                       [&](auto kc, C v) __attribute__((always_inline)) {
-                                          push(IC<B0 + decltype(kc)::value>{}, kc, SLT{}, v);
+                                          if constexpr (decltype(kc)::value == 0 && FEEDBACK) restB = v;
+                                          else push_r(IC<B0 + decltype(kc)::value>{}, kc, SLT{}, v, resB);
                                       });
+                        if constexpr (FEEDBACK) {
+                            push(IC<A0>{}, IC<0>{}, SLT{}, restA + resA);
+                            push(IC<B0>{}, IC<0>{}, SLT{}, restB + resB);
+                        }
                     } else if constexpr (TRTC) {
                         // TRT: the mobility sets the antisymmetric rate w- = wA (wB); w+ from
                         // the magic parameter, 1/w+ - 1/2 = Lambda_s / (M / c_s^2)
                         const C ls = KC(P.trt_ls, P.f32.trt_ls);
                         const C wpA = rcp<C>(C(0.5) + ls * rcp<C>(MA * inv_cs2s));
                         const C wpB = rcp<C>(C(0.5) + ls * rcp<C>(MB * inv_cs2s));
-                        // rest populations (symmetric) in double, as in BGK
-                        push(IC<A0>{}, IC<0>{}, SLT{},
-                             C(double(a[0]) - double(wpA) * (double(a[0]) - (sA - (1.0 - SL::w(0)) * m.muA))));
-                        push(IC<B0>{}, IC<0>{}, SLT{},
-                             C(double(b[0]) - double(wpB) * (double(b[0]) - (sB - (1.0 - SL::w(0)) * m.muB))));
+                        // rest populations (symmetric) in double, as in BGK, stored last with
+                        // the rounding residues of 16-bit storage
+                        const double pa = double(a[0]) - double(wpA) * (double(a[0]) - (sA - (1.0 - SL::w(0)) * m.muA));
+                        const double pb = double(b[0]) - double(wpB) * (double(b[0]) - (sB - (1.0 - SL::w(0)) * m.muB));
+                        C resA = C(0), resB = C(0);
                         const C muA = C(m.muA), muB = C(m.muB);
                         const C cuA = C(sA) * inv_cs2s, cuB = C(sB) * inv_cs2s;
                         static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
@@ -936,12 +957,14 @@ k_lbm(const KParams P) {
                                 // h^eq_k = w_k (mu + c eu / c_s^2): symmetric part w_k mu, antisymmetric w_k c eu / c_s^2
                                 const C npA = C(0.5) * (a[k] + a[o]) - wk * muA, nmA = C(0.5) * (a[k] - a[o]) - wk * cuA * eu;
                                 const C npB = C(0.5) * (b[k] + b[o]) - wk * muB, nmB = C(0.5) * (b[k] - b[o]) - wk * cuB * eu;
-                                push(IC<A0 + k>{}, kc, SLT{}, a[k] - wpA * npA - wA * nmA);
-                                push(IC<A0 + o>{}, IC<o>{}, SLT{}, a[o] - wpA * npA + wA * nmA);
-                                push(IC<B0 + k>{}, kc, SLT{}, b[k] - wpB * npB - wB * nmB);
-                                push(IC<B0 + o>{}, IC<o>{}, SLT{}, b[o] - wpB * npB + wB * nmB);
+                                push_r(IC<A0 + k>{}, kc, SLT{}, a[k] - wpA * npA - wA * nmA, resA);
+                                push_r(IC<A0 + o>{}, IC<o>{}, SLT{}, a[o] - wpA * npA + wA * nmA, resA);
+                                push_r(IC<B0 + k>{}, kc, SLT{}, b[k] - wpB * npB - wB * nmB, resB);
+                                push_r(IC<B0 + o>{}, IC<o>{}, SLT{}, b[o] - wpB * npB + wB * nmB, resB);
                             }
                         });
+                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(resA)));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(resB)));
                     } else {
                     // rest populations in double: they carry the conserved composition
                     const double whA = double(wA), whB = double(wB);

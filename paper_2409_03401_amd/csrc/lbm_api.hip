@@ -173,16 +173,16 @@ int check_config(const lbm_config* c, Layout* L) {
     if (mrt && vd) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with BGK or TRT");
     if (mrt) {
         L->ks = L->dim == 2 ? kernels_mrt_2d(L->qs, L->qf, L->prec) : kernels_mrt_3d(L->qs, L->qf, L->prec);
-        if (!L->ks) return fail(LBM_EUNSUPPORTED, "the MRT collision runs with FP64 or FP32 storage");
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "no MRT kernel for this lattice / precision");
     } else if (gk) {
         L->ks = L->dim == 2 ? kernels_gk_2d(L->qs, L->qf, L->prec) : kernels_gk_3d(L->qs, L->qf, L->prec);
-        if (!L->ks) return fail(LBM_EUNSUPPORTED, "general_kappa runs with FP64 or FP32 storage");
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "no general_kappa kernel for this lattice / precision");
     } else if (vd) {
         L->ks = L->dim == 2 ? kernels_vd_2d(L->qs, trt, L->prec) : kernels_vd_3d(L->qs, trt, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with FP64 or FP32 storage");
     } else if (trt) {
         L->ks = L->dim == 2 ? kernels_trt_2d(L->qs, L->qf, L->prec) : kernels_trt_3d(L->qs, L->qf, L->prec);
-        if (!L->ks) return fail(LBM_EUNSUPPORTED, "the TRT collision runs with FP64 or FP32 storage");
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "no TRT kernel for this lattice / precision");
     } else if (paper_scalar) {
         L->ks = L->dim == 2 ? kernels_paper_2d(L->qf, L->prec) : kernels_paper_3d(L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "no kernel for the D2Q9 / D3Q19 scalar lattices at this precision");

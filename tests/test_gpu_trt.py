@@ -104,6 +104,21 @@ def test_trt_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
+@pytest.mark.parametrize("name", ["2d_d2q5_flow_walls", "3d_d3q7_flow_walls", "3d_d3q19_flow"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_trt_parity_16bit(name, prec):
+    """16-bit storage (FP32 rest populations and arithmetic): c^A, c^B within 1e-3
+    relative L2, phi within 1e-2."""
+    _require_gpu()
+    mom, _ = _gpu(name, prec)
+    ora_m, _ = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("cA", "cB"):
+        assert errs[k][0] <= 1e-3, (k, errs[k])
+    assert errs["phi"][0] <= 1e-2
+
+
 @pytest.mark.parametrize("nu", [0.5, 0.2])
 def test_trt_poiseuille_exact_on_gpu(nu):
     _require_gpu()
@@ -123,9 +138,6 @@ def test_trt_unsupported():
     _require_gpu()
     from paper_2409_03401_amd.lbm import LBM_EUNSUPPORTED, LBMError, Simulation
     p, phi0, muA0, muB0, _ = case("2d_d2q5_flow_walls")
-    with pytest.raises(LBMError) as e:
-        Simulation(gpu_config(p, "bf16"), phi0, muA0, muB0)
-    assert e.value.code == LBM_EUNSUPPORTED
     sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
     work = sim.adjoint_workspace()
     with pytest.raises(LBMError) as e:
