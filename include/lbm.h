@@ -69,7 +69,7 @@ extern "C" {
  * -1/2 mu.(kappa_0 - kappa_1) mu, and the free-energy diagnostic uses
  * 1/2 mu.kappa(phi) mu.  lbm_init takes mu_0 and derives c from this closure. */
 
-/* variable_density = 1 (needs a fluid lattice; FP64 / FP32 storage, no adjoint):
+/* variable_density = 1 (needs a fluid lattice; any storage precision, no adjoint):
  * the high-density-ratio form Section 3 names after Eq. Velocity.  rho(phi) =
  * rho0 + drho phi enters the inertia; f holds dimensionless populations with
  * zeroth moment p* = p_h / (rho c_s^2) and equilibrium w_k [p* + c_k.u / c_s^2 +

@@ -179,7 +179,7 @@ int check_config(const lbm_config* c, Layout* L) {
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "no general_kappa kernel for this lattice / precision");
     } else if (vd) {
         L->ks = L->dim == 2 ? kernels_vd_2d(L->qs, trt, L->prec) : kernels_vd_3d(L->qs, trt, L->prec);
-        if (!L->ks) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with FP64 or FP32 storage");
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "no variable-density kernel for this lattice / precision");
     } else if (trt) {
         L->ks = L->dim == 2 ? kernels_trt_2d(L->qs, L->qf, L->prec) : kernels_trt_3d(L->qs, L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "no TRT kernel for this lattice / precision");

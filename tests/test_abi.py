@@ -75,8 +75,6 @@ def test_state_bytes_layout():
     (dict(collision="TRT", trt_magic=(0.25, float("inf"))), lbm.LBM_EINVAL),
     (dict(variable_density=True), lbm.LBM_EINVAL),                     # needs a fluid lattice
     (dict(variable_density=True, fluid="D2Q9", drho=-1.0), lbm.LBM_EINVAL),  # rho(1) = 0
-    (dict(variable_density=True, fluid="D2Q9", precision="fp16"), lbm.LBM_EUNSUPPORTED),
-    (dict(variable_density=True, fluid="D2Q9", collision="TRT", precision="bf16"), lbm.LBM_EUNSUPPORTED),
     (dict(kappa=((1.0, 1.2, 1.0), (1.0, 0.0, 1.0))), lbm.LBM_EINVAL),      # not positive definite
     (dict(kappa=((1.0, 0.0, 1.0), (-1.0, 0.0, 1.0))), lbm.LBM_EINVAL),
     (dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0)), collision="TRT"), lbm.LBM_EUNSUPPORTED),
@@ -130,7 +128,7 @@ def test_phase_field_run_rejects_configurations_without_adjoint(kw):
 
 
 @pytest.mark.parametrize("kw", [dict(collision="TRT"), dict(collision="MRT"), dict(scalar="D2Q9"),
-                                dict(kappa=((1.0, 0.1, 0.9), (0.95, -0.05, 1.2)))])
+                                dict(kappa=((1.0, 0.1, 0.9), (0.95, -0.05, 1.2))), dict(variable_density=True)])
 def test_variants_accept_16bit_storage(kw):
     for prec in ("fp16", "bf16"):
         assert lbm.state_bytes(_cfg(precision=prec, fluid="D2Q9", **kw)) > 0

@@ -105,6 +105,21 @@ def test_vd_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
+@pytest.mark.parametrize("name", ["2d_bgk_walls", "3d_bgk_walls", "3d_trt_d3q19"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_vd_parity_16bit(name, prec):
+    """16-bit storage (FP32 rest populations and arithmetic): c^A, c^B within 1e-3
+    relative L2, phi within 1e-2."""
+    _require_gpu()
+    mom, _, _ = _gpu(name, prec)
+    ora_m, _, _ = oracle_case(name)
+    errs = field_errors(mom, ora_m)
+    print({k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in errs.items()}, flush=True)
+    for k in ("cA", "cB"):
+        assert errs[k][0] <= 1e-3, (k, errs[k])
+    assert errs["phi"][0] <= 1e-2
+
+
 def test_vd_equal_densities_is_boussinesq():
     _require_gpu()
     from paper_2409_03401_amd.lbm import Simulation
