@@ -17,10 +17,10 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "liblbm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["lbm_2d.hip", "lbm_3d.hip", "lbm_paper_2d.hip", "lbm_paper_3d.hip", "lbm_trt_2d.hip", "lbm_trt_3d.hip",
-           "lbm_vd_2d.hip", "lbm_vd_3d.hip", "lbm_gk_2d.hip", "lbm_gk_3d.hip",
-           "lbm_mrt_2d.hip", "lbm_mrt_3d.hip", "lbm_mrt_3d_q19.hip", "lbm_mrt_3d_q19_flow_fp.hip",
-           "lbm_mrt_3d_q19_flow_16.hip", "lbm_api.hip"]
+# the longest compiles first, so that the parallel build ends together
+SOURCES = ["lbm_mrt_3d_q19_flow_fp.hip", "lbm_mrt_3d_q19_flow_16.hip", "lbm_mrt_3d_q19.hip", "lbm_gk_3d.hip",
+           "lbm_trt_3d.hip", "lbm_mrt_2d.hip", "lbm_paper_3d.hip", "lbm_3d.hip", "lbm_2d.hip", "lbm_trt_2d.hip",
+           "lbm_gk_2d.hip", "lbm_vd_3d.hip", "lbm_mrt_3d.hip", "lbm_paper_2d.hip", "lbm_vd_2d.hip", "lbm_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -40,23 +40,39 @@ def build(verbose: bool = False, out: str = OUT, extra_flags=()) -> str:
     build_dir = BUILD_DIR if out == OUT else out + ".build"
     os.makedirs(build_dir, exist_ok=True)
     t0 = time.time()
-    procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        objs.append(obj)
-        cmd = [HIPCC, *CFLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    # at most `jobs` compilers at once (each large translation unit takes a few GB)
+    jobs = max(1, min(int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 4), 8))
+    pending = list(SOURCES)
+    running = []
     failed = []
-    for src, p in procs:
+
+    def reap(entry):
+        src, p = entry
         raw, _ = p.communicate()
         text = raw.decode(errors="replace")
         if p.returncode != 0:
             failed.append((src, text))
         elif verbose and text.strip():
             print(text)
+
+    for src in SOURCES:
+        objs.append(os.path.join(build_dir, src.replace(".hip", ".o")))
+    while pending or running:
+        while pending and len(running) < jobs:
+            src = pending.pop(0)
+            obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+            cmd = [HIPCC, *CFLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        done = [e for e in running if e[1].poll() is not None]
+        if not done:
+            time.sleep(0.2)
+            continue
+        for e in done:
+            running.remove(e)
+            reap(e)
     if failed:
         msg = "\n".join(f"--- {s} ---\n{t}" for s, t in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
