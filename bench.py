@@ -39,6 +39,9 @@ WORKLOADS = {
     "sediment_3d_256_mrt": dict(kind="sediment_3d", n=256, precision="fp32", collision="MRT"),
     # the variable-density flow model (density ratio 1.5) on the sedimentation workload
     "sediment_3d_256_vd": dict(kind="sediment_3d", n=256, precision="fp32", variable_density=True),
+    # general curvature matrices of the free energies (2 x 2 closure per node)
+    "sediment_3d_256_kappa": dict(kind="sediment_3d", n=256, precision="fp32",
+                                  kappa=((1.0, 0.1, 0.9), (0.95, -0.05, 1.2))),
     # ripening with sedimentation at 512^3 (the paper's 3D run shape, one GPU's share)
     "ripening_sediment_3d_512_bf16": dict(kind="sediment_3d", n=512, precision="bf16", ndrops=2000,
                                           rmin=6.0, rmax=12.0, phi_eq=0.25),
@@ -65,6 +68,8 @@ def build_workload(name):
                         mrt_rates=((1.2, 1.1, 1.2), (1.1, 1.0, 1.2)))
     if spec.get("variable_density"):
         w.params = dict(w.params, variable_density=True)
+    if spec.get("kappa"):
+        w.params = dict(w.params, kappa=spec["kappa"])
     return w
 
 
@@ -362,7 +367,8 @@ def main():
     if not args.no_extra and args.workload == "sediment_3d_256":
         # model variants (collision operators, variable density, the paper's lattices)
         variants = {}
-        for name in ("sediment_3d_256_trt", "sediment_3d_256_mrt", "sediment_3d_256_vd", "ostwald_paper_2d_4096"):
+        for name in ("sediment_3d_256_trt", "sediment_3d_256_mrt", "sediment_3d_256_vd", "sediment_3d_256_kappa",
+                     "ostwald_paper_2d_4096", "ostwald_paper_2d_4096_bf16"):
             print(f"[bench] timing the variant {name}", file=sys.stderr, flush=True)
             wv = build_workload(name)
             cv, wallv, kmsv, _, _ = time_gpu(wv, args.steps, args.warmup)
