@@ -34,7 +34,7 @@ extern "C" {
 /* ---- configuration values --------------------------------------------------- */
 #define LBM_NONE 0            /* no flow: u = 0, no f populations                  */
 #define LBM_D2Q9 9            /* fluid lattices, Tables tab:D2Q9 / tab:D3Q19; also */
-#define LBM_D3Q19 19          /* the paper's scalar lattices (no adjoint)          */
+#define LBM_D3Q19 19          /* the paper's scalar lattices                       */
 #define LBM_D2Q5 5            /* reduced scalar lattices for phi, c^A, c^B         */
 #define LBM_D3Q7 7
 
@@ -237,8 +237,9 @@ int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
  * field.  The adjoint of a state is dL/dX_k(x) for its arriving populations
  * (Section 3); it lives in the caller's device workspace `work` of
  * lbm_adjoint_bytes (FP32 adjoint populations, scratch rows and FP64 parameter
- * partials).  Supported for LBM_FP32 and LBM_FP64 storage with the D2Q5 / D3Q7
- * scalar lattices, without gravity_mean_subtract; other configurations return
+ * partials).  Supported for LBM_FP32 and LBM_FP64 storage with the paper's BGK
+ * Boussinesq model (either scalar lattice), without gravity_mean_subtract; other
+ * configurations (TRT, MRT, variable density, general curvatures) return
  * LBM_EUNSUPPORTED.
  * Calls that share one workspace must not overlap.
  *

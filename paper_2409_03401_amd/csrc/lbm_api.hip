@@ -621,7 +621,7 @@ int adjoint_ready(const lbm_handle* h, const void* work) {
     if (int r = check_handle(h)) return r;
     if (!work) return fail(LBM_EINVAL, "work is NULL");
     if (!h->ks->adj_step)
-        return fail(LBM_EUNSUPPORTED, "the adjoint runs on FP32 or FP64 storage with D2Q5 / D3Q7 scalars");
+        return fail(LBM_EUNSUPPORTED, "the adjoint runs on FP32 or FP64 storage with the BGK Boussinesq model");
     if (h->cfg.gravity_mean_subtract)
         return fail(LBM_EUNSUPPORTED, "the adjoint does not support gravity_mean_subtract");
     return LBM_OK;

@@ -440,9 +440,8 @@ class PhaseFieldRun(torch.autograd.Function):
     def forward(ctx, phi0, theta, cfg, steps, muA0, muB0, segment=None):
         if cfg.precision not in ("fp32", "fp64") or cfg.gravity_mean_subtract:
             raise ValueError("the adjoint runs on fp32 or fp64 storage without gravity_mean_subtract")
-        if (cfg.collision != "BGK" or cfg.variable_density or cfg.kappa is not None
-                or cfg.scalar not in ("D2Q5", "D3Q7")):
-            raise ValueError("the adjoint covers the paper's BGK Boussinesq model on D2Q5 / D3Q7 scalars")
+        if cfg.collision != "BGK" or cfg.variable_density or cfg.kappa is not None:
+            raise ValueError("the adjoint covers the paper's BGK Boussinesq model")
         steps = int(steps)
         seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
         c = with_theta(cfg, theta.detach().double().cpu().tolist())

@@ -113,12 +113,12 @@ def test_init_composition_rejects_null_compositions():
 
 
 
-@pytest.mark.parametrize("kw", [dict(collision="TRT"), dict(collision="MRT"), dict(scalar="D2Q9"),
+@pytest.mark.parametrize("kw", [dict(collision="TRT"), dict(collision="MRT"),
                                 dict(fluid="D2Q9", variable_density=True),
                                 dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0))), dict(precision="bf16")])
 def test_phase_field_run_rejects_configurations_without_adjoint(kw):
-    """The differentiable run covers the paper's BGK Boussinesq model on the reduced
-    scalar lattices at FP32 / FP64; other configurations fail before any device work."""
+    """The differentiable run covers the paper's BGK Boussinesq model at FP32 / FP64;
+    other configurations fail before any device work."""
     import torch
     cfg = _cfg(precision=kw.pop("precision", "fp32"), **kw)
     phi0 = torch.zeros(cfg.nodes, dtype=torch.float64)
