@@ -145,10 +145,11 @@ def test_paper_initial_condition_moments():
 
 
 def test_unsupported_combinations():
+    """The adjoint of 16-bit storage stays unsupported on the paper's lattices too."""
     _require_gpu()
     from paper_2409_03401_amd.lbm import LBM_EUNSUPPORTED, LBMError, Simulation
     p, phi0, muA0, muB0, _, _ = case("2d_noflow_periodic")
-    sim = Simulation(gpu_config(p, "fp32"), phi0, muA0, muB0)
+    sim = Simulation(gpu_config(p, "bf16"), phi0, muA0, muB0)
     work = sim.adjoint_workspace()
     with pytest.raises(LBMError) as e:
         sim.adjoint_seed(sim.save(), np.zeros(phi0.size), work)
