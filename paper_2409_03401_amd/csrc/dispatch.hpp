@@ -30,19 +30,19 @@ struct KernelSet {
 // default.  nullptr for unsupported combinations.
 const KernelSet* kernels_2d(int fluid, int prec, int tx);
 const KernelSet* kernels_3d(int fluid, int prec, int tx, int ty);
-// the paper's scalar lattices (D2Q9 / D3Q19 for g, h^A, h^B): FP64 / FP32, no adjoint
+// the paper's scalar lattices (D2Q9 / D3Q19 for g, h^A, h^B): all precisions, adjoint at FP64 / FP32
 const KernelSet* kernels_paper_2d(int fluid, int prec);
 const KernelSet* kernels_paper_3d(int fluid, int prec);
-// the two-relaxation-time collision (scalar lattice 5 / 9 in 2D, 7 / 19 in 3D): FP64 / FP32, no adjoint
+// the two-relaxation-time collision (scalar lattice 5 / 9 in 2D, 7 / 19 in 3D): all precisions, no adjoint
 const KernelSet* kernels_trt_2d(int scalar, int fluid, int prec);
 const KernelSet* kernels_trt_3d(int scalar, int fluid, int prec);
-// the multiple-relaxation-time collision (same lattice pairs): FP64 / FP32, no adjoint
+// the multiple-relaxation-time collision (same lattice pairs): all precisions, no adjoint
 const KernelSet* kernels_mrt_2d(int scalar, int fluid, int prec);
 const KernelSet* kernels_mrt_3d(int scalar, int fluid, int prec);
-// the variable-density flow model (needs the fluid lattice): FP64 / FP32, no adjoint
+// the variable-density flow model (needs the fluid lattice): all precisions, no adjoint
 const KernelSet* kernels_vd_2d(int scalar, bool trt, int prec);
 const KernelSet* kernels_vd_3d(int scalar, bool trt, int prec);
-// general curvature matrices of the free energies (BGK, Boussinesq): FP64 / FP32, no adjoint
+// general curvature matrices of the free energies (BGK, Boussinesq): all precisions, no adjoint
 const KernelSet* kernels_gk_2d(int scalar, int fluid, int prec);
 const KernelSet* kernels_gk_3d(int scalar, int fluid, int prec);
 

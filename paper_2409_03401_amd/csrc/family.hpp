@@ -1,6 +1,5 @@
-// Instantiation helper: the launchers of one (scalar lattice, fluid lattice)
-// family for the four storage precisions (FP64 and FP32 only for the paper's
-// scalar lattices, family_fp_only).
+// Instantiation helper: the launchers of one (scalar lattice, fluid lattice,
+// collision / model variant) family for the four storage precisions.
 #pragma once
 
 #include "dispatch.hpp"
@@ -95,7 +94,7 @@ const KernelSet* family_for_prec(int prec) {
     }
 }
 
-// the paper's scalar lattices, the TRT / MRT collisions and general curvatures: all
+// the TRT / MRT collisions, the variable-density model and general curvatures: all
 // four storage precisions, no adjoint
 template <class SL, class FL, int TX, int TY, int COLL = COLL_BGK>
 const KernelSet* family_all_prec_noadj(int prec) {
@@ -113,16 +112,6 @@ const KernelSet* family_all_prec_noadj(int prec) {
 template <class SL, class FL, int TX, int TY, int COLL, int PREC>
 const KernelSet* family_one_prec() {
     return &Family<SL, FL, PREC, TX, TY, false, COLL>::set;
-}
-
-// the variable-density model: FP64 and FP32 storage, no adjoint
-template <class SL, class FL, int TX, int TY, int COLL = COLL_BGK>
-const KernelSet* family_fp_only(int prec) {
-    switch (prec) {
-        case P64: return &Family<SL, FL, P64, TX, TY, false, COLL>::set;
-        case P32: return &Family<SL, FL, P32, TX, TY, false, COLL>::set;
-        default: return nullptr;
-    }
 }
 
 }  // namespace lbm

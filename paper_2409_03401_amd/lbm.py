@@ -32,7 +32,7 @@ DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interf
                "free_energy", "nan_count", "droplets", "mean_radius")
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP32_FP16STORE, "bf16": LBM_FP32_BF16STORE}
 _FLUID = {None: LBM_NONE, "none": LBM_NONE, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
-# D2Q5 / D3Q7: reduced scalar lattices; D2Q9 / D3Q19: the paper's (FP64 / FP32 only)
+# D2Q5 / D3Q7: reduced scalar lattices; D2Q9 / D3Q19: the paper's
 _SCALAR = {"D2Q5": LBM_D2Q5, "D3Q7": LBM_D3Q7, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
 _BC = {"periodic": LBM_PERIODIC, "walls": LBM_WALLS}
 _ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ESIZE: "LBM_ESIZE", LBM_EUNSTABLE: "LBM_EUNSTABLE",
