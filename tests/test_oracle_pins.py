@@ -598,6 +598,27 @@ def test_moment_basis_exact(lat):
     assert orders == sorted(orders) and orders[:lat.dim + 1] == [0] + [1] * lat.dim
 
 
+def test_moment_basis_matches_the_classical_d2q9_moments():
+    """The classical D2Q9 moment set (density, energy, energy square, momentum, heat
+    flux, stresses; orthogonal without weights) and the weighted Gram-Schmidt basis
+    span the same spaces order by order: span(rows of order <= k) agree for k = 0..4,
+    so the rates given per order act on the same physical moments."""
+    rows, orders = lattices.moment_basis(lattices.D2Q9)
+    M = np.array([[float(a) for a in r] for r in rows])
+    classical = {  # rows in the table order 0, +x, +y, -x, -y, ++, -+, --, +-
+        0: [[1, 1, 1, 1, 1, 1, 1, 1, 1]],
+        1: [[0, 1, 0, -1, 0, 1, -1, -1, 1], [0, 0, 1, 0, -1, 1, 1, -1, -1]],
+        2: [[-4, -1, -1, -1, -1, 2, 2, 2, 2], [0, 1, -1, 1, -1, 0, 0, 0, 0], [0, 0, 0, 0, 0, 1, -1, 1, -1]],
+        3: [[0, -2, 0, 2, 0, 1, -1, -1, 1], [0, 0, -2, 0, 2, 1, 1, -1, -1]],
+        4: [[4, -2, -2, -2, -2, 1, 1, 1, 1]],
+    }
+    for k in range(5):
+        ours = M[[i for i, o in enumerate(orders) if o <= k]]
+        theirs = np.array([r for j in range(k + 1) for r in classical[j]], dtype=float)
+        both = np.vstack([ours, theirs])
+        assert np.linalg.matrix_rank(ours) == np.linalg.matrix_rank(theirs) == np.linalg.matrix_rank(both), k
+
+
 @pytest.mark.parametrize("scalar", ["D2Q5", "D2Q9"])
 def test_mrt_reduces_to_bgk_and_trt(scalar):
     """Uniform rates: MRT with every free rate equal to the BGK rate is BGK, and with
