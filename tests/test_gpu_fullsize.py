@@ -38,6 +38,7 @@ WORKLOADS = {
     # name: (builder, precision, steps)
     "sediment_3d_256_fp32": (lambda: inputs.sediment_3d(n=256, precision="fp32"), "fp32", 3),
     "sediment_3d_256_bf16": (lambda: inputs.sediment_3d(n=256, precision="bf16"), "bf16", 3),
+    "sediment_3d_256_fp16": (lambda: inputs.sediment_3d(n=256, precision="fp16"), "fp16", 3),
     "ostwald_2d_1024_fp32": (lambda: inputs.ostwald_2d(n=1024, precision="fp32"), "fp32", 3),
     "single_drop_2d_512_fp32": (lambda: inputs.single_drop_2d(n=512, precision="fp32"), "fp32", 3),
     "spinodal_3d_512_bf16": (lambda: inputs.spinodal_3d(n=512, precision="bf16"), "bf16", 1),

@@ -156,15 +156,18 @@ def test_unsupported_combinations():
     assert e.value.code == LBM_EUNSUPPORTED
 
 
-def test_fullsize_paper_ripening_sampled():
-    """The paper's 4096^2 ripening box (FP32, D2Q9 everywhere, paper's initial
-    condition) for 3 steps, sampled nodes against exact FP64 oracle windows of
-    half-width 3K + 3."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fullsize_paper_ripening_sampled(prec):
+    """The paper's 4096^2 ripening box (D2Q9 everywhere, paper's initial condition)
+    for 3 steps, sampled nodes against exact FP64 oracle windows of half-width
+    3K + 3.  FP32: every field within 1e-5 of its window scale; BF16 storage: c^A,
+    c^B within 1e-3 of theirs, phi within 1e-2 of its range [0, 1]."""
     _require_gpu()
     from paper_2409_03401_amd.lbm import Simulation
     w = inputs.ostwald_paper_2d()
     steps = 3
-    sim = Simulation(gpu_config(w.params, "fp32"), w.phi0, w.muA0, w.muB0, c0=w.c0)
+    print(f"[paper lattice] fullsize ripening {w.phi0.shape} {prec} steps={steps}", flush=True)
+    sim = Simulation(gpu_config(w.params, prec), w.phi0, w.muA0, w.muB0, c0=w.c0)
     sim.step(steps)
     rng = inputs.rng_for(61)
     flat = w.phi0.reshape(-1)
@@ -184,7 +187,10 @@ def test_fullsize_paper_ripening_sampled():
         st = olbm.run(olbm.init(w.phi0[sub], w.muA0[sub], w.muB0[sub], prm,
                                 c0=(w.c0[0][sub], w.c0[1][sub])), prm, steps)
         m = olbm.moments(st, prm)
-        for k in ("phi", "cA", "cB", "muA", "muB"):
+        for k in ("phi", "cA", "cB", "muA", "muB") if prec == "fp32" else ("phi", "cA", "cB"):
             win = np.asarray(m[k])
             scale = max(np.abs(win).max(), np.abs(np.asarray(m["cA"])).max() if k.startswith("mu") else 0.0)
-            assert abs(gpu[k][i] - win[0, R, R]) <= 1e-5 * scale + 1e-12, (k, (y, x), gpu[k][i], win[0, R, R])
+            rel = 1e-5 if prec == "fp32" else (1e-2 if k == "phi" else 1e-3)
+            if prec != "fp32" and k == "phi":
+                scale = 1.0  # the order parameter's range; a window may hold phi = 0 only
+            assert abs(gpu[k][i] - win[0, R, R]) <= rel * scale + 1e-12, (k, (y, x), gpu[k][i], win[0, R, R])
