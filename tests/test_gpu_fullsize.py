@@ -12,7 +12,7 @@ over the whole box, which is passed to the window; later steps would need the
 global mean of a later state, so that workload runs one step.
 
 Bars as in test_gpu_parity.py: FP32 within 1e-5 of each field's scale in the
-window; 16-bit storage within 1e-3 relative on c^A, c^B and 1e-2 on phi.
+window; 16-bit storage within 1e-3 relative on c^A, c^B and 1e-2 of phi's range [0, 1].
 """
 
 import functools
@@ -150,7 +150,8 @@ def test_fullsize_sampled(name):
                     s = max(scale["ux"], scale["uy"], scale["uz"])
                 bar = 1e-5 * s + 1e-12
             else:
-                bar = {"cA": 1e-3 * scale["cA"], "cB": 1e-3 * scale["cB"], "phi": 1e-2 * scale["phi"]}.get(k)
+                # phi against its range [0, 1]: a window may hold phi = 0 only
+                bar = {"cA": 1e-3 * scale["cA"], "cB": 1e-3 * scale["cB"], "phi": 1e-2}.get(k)
             worst[k] = max(worst.get(k, 0.0), err)
             if bar is not None:
                 assert err <= bar, (name, c, k, gpu[k][i], ora[k])
