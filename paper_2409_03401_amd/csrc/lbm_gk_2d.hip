@@ -7,11 +7,11 @@ namespace lbm {
 
 const KernelSet* kernels_gk_2d(int scalar, int fluid, int prec) {
     if (scalar == 5) {
-        if (fluid == 0) return family_all_prec_noadj<D2Q5K, NoLattice, 64, 1, COLL_GK>(prec);
-        if (fluid == 9) return family_all_prec_noadj<D2Q5K, D2Q9K, 64, 1, COLL_GK>(prec);
+        if (fluid == 0) return family_all_prec_noadj<D2Q5K, NoLattice, 256, 1, COLL_GK>(prec);
+        if (fluid == 9) return family_all_prec_noadj<D2Q5K, D2Q9K, 256, 1, COLL_GK>(prec);
     } else if (scalar == 9) {
-        if (fluid == 0) return family_all_prec_noadj<D2Q9K, NoLattice, 64, 1, COLL_GK>(prec);
-        if (fluid == 9) return family_all_prec_noadj<D2Q9K, D2Q9K, 64, 1, COLL_GK>(prec);
+        if (fluid == 0) return family_all_prec_noadj<D2Q9K, NoLattice, 256, 1, COLL_GK>(prec);
+        if (fluid == 9) return family_all_prec_noadj<D2Q9K, D2Q9K, 256, 1, COLL_GK>(prec);
     }
     return nullptr;
 }
