@@ -314,6 +314,39 @@ def test_fourier_mode_diffusivity(scalar, axis):
     assert errs[0] / errs[1] > 3.0   # O(k^2) relative error
 
 
+@pytest.mark.parametrize("scalar", ["D2Q5", "D3Q7", "D2Q9"])
+@pytest.mark.parametrize("phase", [0, 1])
+def test_fourier_mode_per_phase_mobility(scalar, phase):
+    """The species mobility depends on the phase (Section 2.3): M(phi) = M_0 (1 - phi)
+    + M_1 phi.  In bulk phase pi (phi = pi everywhere: omega_dw'(pi) = p'(pi) = 0, so
+    S = 0 and phi stays pi up to the rounding of sum_k w_k) c = mu + c_pi,eq and a Fourier mode of each component
+    decays at M_pi k^2.  Unequal mobilities per phase and per component tell the phases
+    and the components apart: with them exchanged the rates would be off by 4x."""
+    N = 32
+    shape = [1, 1, 1]
+    axis = 2 if scalar == "D3Q7" else 0
+    shape[2 - axis] = N
+    nz, ny, nx = shape
+    M_A, M_B = (0.05, 0.2), (0.2, 0.05)
+    prm = lbm.Params(nx=nx, ny=ny, nz=nz, scalar=scalar, W=4.0, lam=10.0, M_phi=0.1,
+                     M_A=M_A, M_B=M_B, c_eq=((0.2, 0.1), (0.6, 0.3)))
+    coord = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")[2 - axis]
+    kw = 2 * math.pi / N
+    mode = np.sin(kw * coord)
+    st = lbm.init(np.full(prm.shape, float(phase)), 1e-3 * mode, -2e-3 * mode, prm)
+    t0 = 40
+    t1 = t0 + int(1.5 / (min(M_A[phase], M_B[phase]) * kw * kw))
+    st = lbm.run(st, prm, t0)
+    m0 = lbm.moments(st, prm)
+    st = lbm.run(st, prm, t1 - t0)
+    m1 = lbm.moments(st, prm)
+    assert np.abs(m1["phi"] - float(phase)).max() < 1e-12
+    for key, M in (("muA", M_A), ("muB", M_B)):
+        a0, a1 = (m0[key] * mode).sum(), (m1[key] * mode).sum()
+        rate_meas = -math.log(a1 / a0) / (t1 - t0)
+        assert abs(rate_meas / (M[phase] * kw * kw) - 1.0) < 0.02, (key, rate_meas / (M[phase] * kw * kw))
+
+
 @pytest.mark.parametrize("scalar", ["D2Q5", "D2Q9", "D3Q7", "D3Q19"])
 def test_fourier_mode_diagonal(scalar):
     """Isotropy of the composition lattice: a mode along a lattice diagonal decays at
@@ -418,10 +451,13 @@ def _interface_position(phi, x):
 
 
 def _run_couple(mu_l, mu_r, c_eq, M, Mphi, W, N, T, snaps):
+    """M[alpha]: the mobility of component alpha, one number or the pair (phase 0,
+    phase 1); lambda = lambda* of the phase-averaged mobilities."""
     dc = [c_eq[0][a] - c_eq[1][a] for a in range(2)]
-    lam = model.lambda_star(W, Mphi, M, c_eq)
+    pairs = [(m, m) if np.ndim(m) == 0 else tuple(m) for m in M]
+    lam = model.lambda_star(W, Mphi, [0.5 * (p[0] + p[1]) for p in pairs], c_eq)
     prm = lbm.Params(nx=N, ny=1, bc=("walls", "periodic", "periodic"), W=W, lam=lam, M_phi=Mphi,
-                     M_A=(M[0], M[0]), M_B=(M[1], M[1]), c_eq=c_eq)
+                     M_A=pairs[0], M_B=pairs[1], c_eq=c_eq)
     x = np.arange(N) - (N - 1) / 2.0
     phi0 = analytic.tanh_profile(x, W)
     muA0 = np.where(x < 0, mu_l[0], mu_r[0])
@@ -476,6 +512,102 @@ def test_diffusion_couple_moving_interface():
         ref = analytic.dc_mu_profile(x, snaps[1], xi, mu_l[a], mu_r[a], dc[a], M[a])
         far = np.abs(x - out[snaps[1]]["xI"]) > 3 * 4.0
         assert np.abs(out[snaps[1]][key] - ref)[far].max() < 0.05 * abs(mu_l[a] - mu_r[a])
+
+
+@pytest.mark.slow
+def test_diffusion_couple_per_phase_mobilities():
+    """A moving couple with different mobilities in the two phases (Section 2.3):
+    phase 0 (left) diffuses with M_0, phase 1 (right) with M_1, and the similarity
+    solution of Eqs. Stefan ... Solution_Mu with per-side diffusivities fixes the
+    interface velocity xi.  The measured xi must match it within 5%; with the phases'
+    mobilities exchanged the same couple moves at xi = -0.229 instead of -0.580."""
+    c_eq = ((0.3, 0.3), (0.4, 0.4))
+    M_A, M_B = (0.1, 0.025), (0.08, 0.02)
+    mu_l, mu_r = (0.1, 0.05), (-0.02, 0.0)
+    dc = [c_eq[0][a] - c_eq[1][a] for a in range(2)]
+    roots = analytic.dc_roots(mu_l, mu_r, dc, [M_A, M_B])
+    assert len(roots) == 1
+    xi = roots[0]
+    swapped = analytic.dc_roots(mu_l, mu_r, dc, [M_A[::-1], M_B[::-1]])
+    assert len(swapped) == 1 and abs(swapped[0] / xi - 1.0) > 0.5
+    snaps = [1000, 4000]
+    x, _, out = _run_couple(mu_l, mu_r, c_eq, (M_A, M_B), 0.12, 4.0, 512, snaps[-1], snaps)
+    xi_meas = (out[snaps[1]]["xI"] - out[snaps[0]]["xI"]) / (math.sqrt(snaps[1]) - math.sqrt(snaps[0]))
+    assert abs(xi_meas / xi - 1.0) < 0.05, (xi_meas, xi)
+
+
+# ----------------------------------------------------------------------------------------
+# the whole discrete map against exact rational arithmetic
+
+def _exact_case(name):
+    """Parameters (binary fractions, so both sides start from identical values) and step
+    count.  Unequal mobilities and viscosities per phase, capillary force, buoyancy."""
+    base = dict(W=4.0, lam=21.5, M_phi=0.125, M_A=(0.125, 0.0625), M_B=(0.09375, 0.15625),
+                c_eq=((0.25, 0.125), (0.625, 0.3125)), rho0=1.0, drho=0.5, sigma=1.0 / 16, nu=(0.125, 0.0625))
+    cases = {
+        "2d_noflow_walls": dict(nx=3, ny=3, nz=1, fluid=None, scalar="D2Q5", bc=("walls", "periodic", "periodic")),
+        "2d_flow_walls": dict(nx=3, ny=3, nz=1, fluid="D2Q9", scalar="D2Q5", bc=("periodic", "walls", "periodic"),
+                              g=(0.0, -1.0 / 4096, 0.0)),
+        "2d_paper_periodic_mean": dict(nx=3, ny=3, nz=1, fluid="D2Q9", scalar="D2Q9", bc=("periodic",) * 3,
+                                       g=(1.0 / 8192, -1.0 / 4096, 0.0), gravity_mean_subtract=True),
+        "3d_flow_walls": dict(nx=3, ny=3, nz=3, fluid="D3Q19", scalar="D3Q7", bc=("walls", "periodic", "walls"),
+                              g=(0.0, 0.0, -1.0 / 4096)),
+    }
+    return dict(base, **cases[name])
+
+
+@pytest.mark.parametrize("name", ["2d_noflow_walls", "2d_flow_walls", "2d_paper_periodic_mean", "3d_flow_walls"])
+def test_whole_map_matches_exact_rational_arithmetic(name):
+    """Every operation of the step (moments, closure with the predictor, source, stencil,
+    force, flow moments, the three collisions with rational rates, streaming with walls) is
+    +, -, x or /.  On random dyadic-rational populations the independent Fraction
+    reference of tests/exact_map.py is exact; two oracle steps must match it to 1e-14 of
+    each field's largest population (measured: <= 7e-16).  More steps are impractical: the
+    exact denominators reach 2e4 bits after two steps and 5e5 bits after three."""
+    import exact_map
+    p = _exact_case(name)
+    shape = (p["nz"], p["ny"], p["nx"])
+    nodes = [(x, y, z) for z in range(shape[0]) for y in range(shape[1]) for x in range(shape[2])]
+    rng = np.random.default_rng(5)
+
+    def dyadic(lo, hi, den=4096):
+        return Fr(int(rng.integers(int(lo * den), int(hi * den) + 1)), den)
+
+    _, sw = exact_map.LATTICES[p["scalar"]]
+    phi = {x: dyadic(0.05, 0.95) for x in nodes}
+    cA = {x: dyadic(0.2, 0.6) for x in nodes}
+    cB = {x: dyadic(0.1, 0.3) for x in nodes}
+    st = {"phi_ref": dyadic(0.3, 0.7) if p.get("gravity_mean_subtract") else Fr(0)}
+    st["g"] = [{x: sw[k] * phi[x] + dyadic(-0.01, 0.01) for x in nodes} for k in range(len(sw))]
+    st["hA"] = [{x: (cA[x] if k == 0 else 0) + dyadic(-0.01, 0.01) for x in nodes} for k in range(len(sw))]
+    st["hB"] = [{x: (cB[x] if k == 0 else 0) + dyadic(-0.01, 0.01) for x in nodes} for k in range(len(sw))]
+    if p["fluid"]:
+        _, fw = exact_map.LATTICES[p["fluid"]]
+        st["f"] = [{x: fw[k] * dyadic(-0.01, 0.01) + dyadic(-0.001, 0.001) for x in nodes} for k in range(len(fw))]
+
+    def arr(pops):
+        a = np.zeros((len(pops),) + shape)
+        for k, d in enumerate(pops):
+            for (x, y, z), v in d.items():
+                a[k, z, y, x] = float(v)
+        return a
+
+    exact_prm = {k: Fr(v) for k, v in p.items() if isinstance(v, float)}
+    exact_prm.update(shape=shape, bc=p["bc"], scalar=p["scalar"], fluid=p["fluid"],
+                     gravity_mean_subtract=p.get("gravity_mean_subtract", False),
+                     M_A=tuple(map(Fr, p["M_A"])), M_B=tuple(map(Fr, p["M_B"])), nu=tuple(map(Fr, p["nu"])),
+                     g=tuple(map(Fr, p.get("g", (0.0, 0.0, 0.0)))),
+                     c_eq=tuple(tuple(map(Fr, r)) for r in p["c_eq"]))
+    prm = lbm.Params(**p)
+    ost = lbm.State(g=arr(st["g"]), hA=arr(st["hA"]), hB=arr(st["hB"]), f=arr(st["f"]) if p["fluid"] else None,
+                    phi_ref=float(st["phi_ref"]))
+    for _ in range(2):
+        st = exact_map.step(st, exact_prm)
+        ost = lbm.step(ost, prm)
+        for key in ("g", "hA", "hB") + (("f",) if p["fluid"] else ()):
+            ex = arr(st[key])
+            assert np.abs(getattr(ost, key) - ex).max() <= 1e-14 * np.abs(ex).max(), key
+        assert abs(ost.phi_ref - float(st["phi_ref"])) <= 1e-15
 
 
 # ----------------------------------------------------------------------------------------
@@ -704,6 +836,27 @@ def _layered_channel_ode(N, W, phi_of, b_of, mu_of):
     I1, I2 = cum(inv), cum(B * inv)
     u = I2[-1] / I1[-1] * I1 - I2
     return np.interp(np.arange(N), ys, u)
+
+
+def test_boussinesq_layered_channel_per_phase_viscosity():
+    """The viscosity of Eq. QDM depends on the phase; the reading taken is
+    nu(phi) = nu_0 (1 - phi) + nu_1 phi.  Two layers between walls (phase 1 in the lower
+    half), driven along them by the buoyancy phi drho g of the Boussinesq model: the
+    steady profile solves d/dy (rho0 nu(phi) du/dy) = -phi drho g.  With the phases'
+    viscosities exchanged the profile is far off."""
+    N, W, drho, nu, g = 24, 4.0, 1.0, (0.2, 0.05), 1e-6
+    y0 = N / 2 - 0.5
+    phi_of = lambda y: 0.5 * (1.0 + np.tanh(2.0 * (y0 - y) / W))
+    prm = lbm.Params(nx=2, ny=N, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=W, lam=21.05,
+                     drho=drho, g=(g, 0, 0), sigma=1e-3, nu=nu)
+    phi0 = np.repeat(phi_of(np.arange(N))[None, :, None], 2, axis=2)
+    z = np.zeros_like(phi0)
+    st = lbm.run(lbm.init(phi0, z, z, prm), prm, 4000)
+    ux = lbm.moments(st, prm)["ux"][0, :, 0]
+    ref = _layered_channel_ode(N, W, phi_of, lambda p: p * drho * g, lambda p: nu[0] * (1 - p) + nu[1] * p)
+    swapped = _layered_channel_ode(N, W, phi_of, lambda p: p * drho * g, lambda p: nu[1] * (1 - p) + nu[0] * p)
+    assert np.abs(ux - ref).max() < 0.02 * ref.max()
+    assert np.abs(swapped - ref).max() > 0.3 * ref.max()
 
 
 def test_variable_density_layered_channel():
