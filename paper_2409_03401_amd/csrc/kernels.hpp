@@ -19,6 +19,7 @@
 // offset, so each load / store is one `global_* voffset, saddr` instruction.
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "adjoint.hpp"
@@ -284,9 +285,6 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #ifndef LBM_NT_FLUID
 #define LBM_NT_FLUID 1
 #endif
-#ifndef LBM_SCALAR_BASES
-#define LBM_SCALAR_BASES 1
-#endif
 #ifndef LBM_PHASES
 #define LBM_PHASES 0
 #endif
@@ -388,33 +386,32 @@ k_lbm(const KParams P) {
     using FLT = std::common_type<FL>;
 
     // wave-uniform slot bases of the source and destination copies.  The 2 x Q_tot
-    // 64-bit bases do not fit in the SGPR file: hoisted out of the plane loop they
-    // would be spilled to VGPR lanes and read back with v_readlane (a VALU
-    // instruction each).  refresh_bases() at the top of every iteration hands the
-    // loop opaque copies of the copy bases and strides, so each slot base is
-    // recomputed on the scalar unit next to its use.
-    const char* sbase = P.src_base;
-    char* dbase = P.dst_base;
-    unsigned long long smov = P.stride_m, srest = P.stride_r;
-    // measured on 256^3: BF16 storage 15.0 -> 19.4 GLUPS (the 16-bit step is
-    // instruction-bound); FP32 unchanged (HBM-bound)
-    auto refresh_bases = [&]() __attribute__((always_inline)) {
-        if constexpr (LBM_SCALAR_BASES) asm volatile("" : "+s"(sbase), "+s"(dbase), "+s"(smov), "+s"(srest));
-    };
-    auto slot_off = [&](auto s_) __attribute__((always_inline)) -> unsigned long long {
-        constexpr int S = decltype(s_)::value;
-        constexpr int rb = SLOTS::rest_before(S);
-        return (unsigned long long)(S - rb) * smov + (unsigned long long)rb * srest;
-    };
-    // the opaque copies lose the address space; the casts restore `global` so the
+    // 64-bit bases do not fit in the SGPR file, and computing each from a copy base and
+    // the slot strides costs about eight scalar instructions.  The host stores every
+    // base in the parameter block; the kernel reads them through a kernel-argument
+    // pointer that refresh_bases() makes opaque at the top of every plane, so each base
+    // is one scalar load (merged with its neighbours) next to its use, and nothing is
+    // hoisted into the SGPR file and spilled.
+    using kconst = __attribute__((address_space(4))) const char;
+    using kslot = __attribute__((address_space(4))) const unsigned long long;
+    static_assert(offsetof(KParams, dst_slot) == offsetof(KParams, src_slot) + kMaxSlots * sizeof(void*),
+                  "slot tables are adjacent");
+    // the parameter block is the kernel's only argument, at offset 0 of the segment
+    kconst* kargs = (kconst*)__builtin_amdgcn_kernarg_segment_ptr();
+    auto refresh_bases = [&]() __attribute__((always_inline)) { asm volatile("" : "+s"(kargs)); };
+    // the table entries lose the address space; the casts restore `global` so the
     // accesses stay global_* with a 32-bit voffset instead of flat_* with 64-bit addresses
     using gconst = __attribute__((address_space(1))) const char;
     using gmut = __attribute__((address_space(1))) char;
     auto src = [&](auto s_) __attribute__((always_inline)) -> const char* {
-        return (const char*)((gconst*)sbase + slot_off(s_));
+        constexpr int S = decltype(s_)::value;
+        const unsigned long long b = reinterpret_cast<kslot*>(kargs + offsetof(KParams, src_slot))[S];
+        return (const char*)(gconst*)b;
     };
     auto dst = [&](auto s_) __attribute__((always_inline)) -> char* {
-        return (char*)((gmut*)dbase + slot_off(s_));
+        constexpr int S = decltype(s_)::value;
+        const unsigned long long b = reinterpret_cast<kslot*>(kargs + offsetof(KParams, dst_slot))[S];
+        return (char*)(gmut*)b;
     };
     // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
     auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {

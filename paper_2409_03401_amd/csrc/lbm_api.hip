@@ -238,6 +238,11 @@ namespace {
 void set_slots(const lbm_handle* h, KParams& kp, const char* src, char* dst) {
     kp.src_base = src;
     kp.dst_base = dst;
+    for (int s = 0; s < kMaxSlots; ++s) {
+        const bool used = s < h->L.nslots;
+        kp.src_slot[s] = (src && used) ? src + h->L.slot_off[s] : nullptr;
+        kp.dst_slot[s] = (dst && used) ? dst + h->L.slot_off[s] : nullptr;
+    }
 }
 
 void fill_params(lbm_handle* h) {

@@ -103,6 +103,12 @@ struct KParams {
     double* ref_copy;
     // MODE_STEP_PHI: receives phi of the source state ([node], compute type)
     void* phi_out;
+    // absolute base of every slot of the source and the destination copy (canonical slot
+    // order; filled on the host from src_base / dst_base).  The fused kernel reads them
+    // from the kernel-argument segment (this block is its only argument, at offset 0)
+    // with one scalar load per slot and plane instead of 64-bit scalar arithmetic.
+    const char* src_slot[kMaxSlots];
+    char* dst_slot[kMaxSlots];
 };
 
 constexpr int kAuxRows = 10;
