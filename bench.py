@@ -1,14 +1,19 @@
 """Throughput of the fused coupled LBM step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sediment_3d_256]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload spinodal_3d_512_bf16]
 
 Prints one JSON line.  A step is one pass of the whole hot path (scalar moments with
 the phi predictor, LDS-staged grad/lap phi, capillary + buoyancy force, collision of
-f, g, h^A, h^B, streaming with bounce-back walls) over every node of the workload.
-`value` is million lattice-node updates per second over the timed steps with all
-inputs resident in HBM.  `roofline` prices the fused step kernel against the HBM peak
-with its algorithmic bytes (every population read once and written once per update).
-`cpu_baseline` is the FP64 numpy oracle timed on a bounded crop of the same workload.
+f, g, h^A, h^B, streaming with periodic or bounce-back boundaries) over every node of
+the workload.  The default workload is the largest single-GPU configuration: a 512^3
+periodic box, D3Q19 + 3 x D3Q7, BF16 moving populations with FP32 compute, buoyancy
+with the mean subtracted.  `value` is million lattice-node updates per second over the
+timed steps with all inputs resident in HBM.  `roofline` prices the fused step kernel
+against the HBM peak with its algorithmic bytes (every population read once and
+written once per update) and against the measured 1:1 read/write stream ceiling of
+the library's streaming probe.  `cpu_baseline` is the FP64 numpy oracle on a bounded
+crop of the same workload, at one thread and on all host cores (one independent crop
+per core), timed before the GPU is touched.
 """
 
 import argparse
@@ -29,6 +34,7 @@ WORKLOADS = {
     "sediment_3d_256_bf16": dict(kind="sediment_3d", n=256, precision="bf16"),
     "sediment_3d_256_fp16": dict(kind="sediment_3d", n=256, precision="fp16"),
     "spinodal_3d_512_bf16": dict(kind="spinodal_3d", n=512, precision="bf16"),
+    "spinodal_3d_256_bf16": dict(kind="spinodal_3d", n=256, precision="bf16"),
     "ostwald_2d_1024": dict(kind="ostwald_2d", n=1024, precision="fp32"),
     "single_drop_2d_512": dict(kind="single_drop_2d", n=512, precision="fp32"),
     # the paper's own discretisation and initial condition (D2Q9 for every equation)
@@ -118,26 +124,41 @@ def time_gpu(w, steps, warmup):
     return cfg, wall, kernel_ms, diag, resident
 
 
-def copy_ceiling(mib=1024, reps=5):
-    """Device-to-device copy of `mib` MiB (torch copy kernel): a measured HBM ceiling
-    for plain streaming on this GPU, read + write bytes per second."""
+def stream_ceiling(mib=2048, reps=5, grids=(1024, 2048, 4096, 8192, 16384, 65536)):
+    """Measured HBM ceilings from the library's streaming probe (lbm_probe_stream:
+    16-byte non-temporal loads and stores, grid-stride loop), best over a sweep of grid
+    sizes: copy (1:1 read/write, the pattern of a step; read + write bytes per second),
+    read only and write only, in GB/s, on buffers of `mib` MiB each."""
+    import ctypes
     import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    from paper_2409_03401_amd import lbm as L
+    n = mib * (1 << 20)
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    stream = torch.cuda.current_stream()
+    out = {}
+    for mode, name, factor in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+        best, best_grid = 0.0, None
+        for grid in grids:
+            def launch():
+                L._check(L.lib().lbm_probe_stream(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                                  ctypes.c_size_t(n), mode, grid, ctypes.c_void_p(stream.cuda_stream)))
+            launch()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gbs = factor * n / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+            if gbs > best:
+                best, best_grid = gbs, grid
+        out[name] = {"GBps": round(best, 1), "grid": best_grid}
     del a, b
     torch.cuda.empty_cache()
-    return 2 * 4 * n / (ms * 1e-3) / 1e9
+    return out
 
 
 def profiled_traffic(workload, kernel_sha):
@@ -164,20 +185,21 @@ def kernel_sources_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2409_03401_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hpp", ".hip")):
+        if name.endswith((".hpp", ".hip")) and name != "probe.hip":
             h.update(name.encode())
             h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
 
 
-def cpu_baseline(budget_s=12.0):
-    """The oracle as it stands on a 64^3 crop of the sediment workload (same recipe:
-    walls in z, D3Q19 + 3 x D3Q7, 4 droplets R ~ U[10, 14]), timed for about budget_s."""
+def _oracle_crop_worker(args):
+    """Step the oracle on a 64^3 crop of the workload recipe for about budget_s;
+    returns (node updates, seconds).  Runs in its own process for the all-core leg."""
+    name, budget_s = args
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
     from oracle import lbm as olbm
-    from paper_2409_03401_amd import inputs
-    w = inputs.sediment_3d(n=64, ndrops=4, rmin=10.0, rmax=14.0)
+    w = _crop_workload(name)
     prm = olbm.Params(**w.params)
-    st = olbm.init(w.phi0, w.muA0, w.muB0, prm)
+    st = olbm.init(w.phi0, w.muA0, w.muB0, prm, c0=w.c0)
     st = olbm.step(st, prm)  # warm-up
     n = 0
     t0 = time.perf_counter()
@@ -186,11 +208,53 @@ def cpu_baseline(budget_s=12.0):
         n += 1
         el = time.perf_counter() - t0
         if el >= budget_s and n >= 3:
-            break
-    nodes = w.nodes
-    return {"value": nodes * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"64^3 crop of the sediment workload, D3Q19 + 3xD3Q7, FP64 numpy, {n} steps "
-                      f"in {el:.1f} s (single thread; host has {os.cpu_count()} logical CPUs)"}
+            return w.nodes * n, el, n
+
+
+def _crop_workload(name):
+    """The 64^3 crop of a 3D workload's recipe that the oracle is timed on."""
+    from paper_2409_03401_amd import inputs
+    if WORKLOADS[name]["kind"] == "spinodal_3d":
+        return inputs.spinodal_3d(n=64)
+    return inputs.sediment_3d(n=64, ndrops=4, rmin=10.0, rmax=14.0)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def cpu_baseline(name, budget_s=10.0, max_workers=16):
+    """The oracle as it stands (FP64 numpy, never tuned for this) on a 64^3 crop of the
+    workload's recipe: one process on one thread, then one independent crop per host
+    core (up to max_workers processes, the machine's CPU share) stepping at once.  Must run
+    before the GPU is touched (the pool forks)."""
+    import multiprocessing as mp
+    upd, el, n = _oracle_crop_worker((name, budget_s))
+    single = upd / el / 1e6
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(cores, max_workers))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_crop_worker, [(name, budget_s)] * workers)
+    wall = time.perf_counter() - t0
+    total = sum(r[0] for r in res)
+    allcore = total / wall / 1e6
+    crop = "spinodal box" if WORKLOADS[name]["kind"] == "spinodal_3d" else "sediment workload"
+    return {"value": round(allcore, 3), "unit": "MLUPS", "cores": workers, "kind": "oracle",
+            "single_thread": {"value": round(single, 3), "unit": "MLUPS", "cores": 1, "steps": n},
+            "sample": f"64^3 crop of the {crop} recipe, D3Q19 + 3xD3Q7, FP64 numpy oracle; "
+                      f"1 thread: {n} steps in {el:.1f} s; all cores: {workers} processes, one crop each, "
+                      f"{total / 64 ** 3:.0f} node-steps in {wall:.1f} s; host {_cpu_model()}, "
+                      f"{cores} logical CPUs available"}
 
 
 def adjoint_timing(n=512, steps=4096, segment=None, kind="single_drop_2d"):
@@ -277,19 +341,39 @@ def series_run(name, steps, every):
     }
 
 
+def variant_line(name, steps, warmup):
+    """Throughput line of one more workload (same timing as the headline)."""
+    print(f"[bench] timing {name}", file=sys.stderr, flush=True)
+    w = build_workload(name)
+    c, wall, kms, d, _ = time_gpu(w, steps, warmup)
+    bpu = bytes_per_update(c)
+    return {"MLUPS": round(c.nodes * steps / wall / 1e6, 1), "bytes_per_update": bpu,
+            "kernel_ms": round(kms, 4), "GBps": round(bpu * c.nodes / (kms * 1e-3) / 1e9, 1),
+            "nan_count": int(d["nan_count"])}
+
+
+# extra throughput lines of the default run: the sedimentation workload at the three
+# storage precisions, the model variants, the paper's own discretisation
+EXTRA_LINES = ("sediment_3d_256", "sediment_3d_256_bf16", "sediment_3d_256_fp16", "sediment_3d_256_trt",
+               "sediment_3d_256_mrt", "sediment_3d_256_vd", "sediment_3d_256_kappa", "ostwald_paper_2d_4096",
+               "ostwald_paper_2d_4096_bf16")
+
+NORTH_STAR_FRAC = 0.70   # the forward-step bandwidth target, as a fraction of the HBM peak
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sediment_3d_256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="spinodal_3d_512_bf16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 16-bit storage variants and the adjoint timing")
+                    help="skip the extra workload lines and the adjoint timing")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time the differentiable run (forward, backward, ratio)")
     ap.add_argument("--adjoint-n", type=int, nargs="+", default=[512, 2048],
-                    help="grid sizes n (n x n) for --adjoint-only")
+                    help="grid sizes n (n x n) of the adjoint timing")
     ap.add_argument("--adjoint-steps", type=int, default=4096)
     ap.add_argument("--adjoint-kind", default="single_drop_2d", choices=["single_drop_2d", "sediment_3d"])
     ap.add_argument("--series", default=None, choices=sorted(WORKLOADS),
@@ -317,6 +401,12 @@ def main():
                                    "multi-GPU runs (--gpus > 1) are not supported"}))
         sys.exit(2)
 
+    # the oracle's timing forks a process per core: it runs before the GPU is touched
+    cpu = None
+    if not (args.no_cpu_baseline or args.series or args.adjoint_only):
+        print("[bench] timing the CPU oracle (one thread, then all cores)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.workload)
+
     import torch
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -340,6 +430,7 @@ def main():
     w = build_workload(args.workload)
     print(f"[bench] timing {args.steps} steps after {args.warmup} warm-up steps", file=sys.stderr, flush=True)
     cfg, wall, kernel_ms, diag, resident = time_gpu(w, args.steps, args.warmup)
+    del w
     if diag["nan_count"] != 0:
         print(json.dumps({"error": "non-finite state after the timed steps"}))
         sys.exit(1)
@@ -348,46 +439,20 @@ def main():
     bpu = bytes_per_update(cfg)
     achieved = bpu * nodes / (kernel_ms * 1e-3) / 1e9
 
-    print("[bench] measuring the copy ceiling", file=sys.stderr, flush=True)
-    ceiling = copy_ceiling()
+    print("[bench] measuring the streaming ceilings", file=sys.stderr, flush=True)
+    ceilings = stream_ceiling()
+    copy_gbs = ceilings["copy"]["GBps"]
 
     extra = {}
-    if not args.no_extra and args.workload == "sediment_3d_256":
-        for prec in ("bf16", "fp16"):
-            print(f"[bench] timing the {prec} storage variant", file=sys.stderr, flush=True)
-            w16 = build_workload(f"sediment_3d_256_{prec}")
-            c16, wall16, kms16, d16, _ = time_gpu(w16, args.steps, args.warmup)
-            extra[f"{prec}_store"] = {
-                "MLUPS": round(c16.nodes * args.steps / wall16 / 1e6, 1),
-                "bytes_per_update": bytes_per_update(c16),
-                "kernel_ms": round(kms16, 4),
-                "GBps": round(bytes_per_update(c16) * c16.nodes / (kms16 * 1e-3) / 1e9, 1),
-            }
-
-    if not args.no_extra and args.workload == "sediment_3d_256":
-        # model variants (collision operators, variable density, the paper's lattices)
-        variants = {}
-        for name in ("sediment_3d_256_trt", "sediment_3d_256_mrt", "sediment_3d_256_vd", "sediment_3d_256_kappa",
-                     "ostwald_paper_2d_4096", "ostwald_paper_2d_4096_bf16"):
-            print(f"[bench] timing the variant {name}", file=sys.stderr, flush=True)
-            wv = build_workload(name)
-            cv, wallv, kmsv, _, _ = time_gpu(wv, args.steps, args.warmup)
-            variants[name] = {
-                "MLUPS": round(cv.nodes * args.steps / wallv / 1e6, 1),
-                "bytes_per_update": bytes_per_update(cv),
-                "kernel_ms": round(kmsv, 4),
-                "GBps": round(bytes_per_update(cv) * cv.nodes / (kmsv * 1e-3) / 1e9, 1),
-            }
-        extra["variants"] = variants
-
     if not args.no_extra:
-        print("[bench] timing the adjoint (forward, recompute + backward)", file=sys.stderr, flush=True)
-        extra["adjoint"] = adjoint_timing()
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        extra["lines"] = {name: variant_line(name, args.steps, args.warmup)
+                          for name in EXTRA_LINES if name != args.workload}
+        adj = {}
+        for n in args.adjoint_n:
+            print(f"[bench] timing the adjoint at {n}^2 (forward, recompute + backward)", file=sys.stderr,
+                  flush=True)
+            adj[str(n)] = adjoint_timing(n=n, steps=args.adjoint_steps)
+        extra["adjoint"] = adj
 
     out = {
         "metric": "MLUPS coupled step",
@@ -400,7 +465,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}.get(cfg.precision, "f32"),
+        "dtype": {"fp64": "f64"}.get(cfg.precision, "f32"),
         "data": "synthetic",
         "config": {
             "workload": args.workload,
@@ -421,8 +486,11 @@ def main():
             "kernel": "k_lbm (fused step)",
             "bytes_per_update": bpu,
             "kernel_ms": round(kernel_ms, 4),
-            "copy_ceiling_GBps": round(ceiling, 1),
-            "frac_of_copy_ceiling": round(achieved / ceiling, 4),
+            "stream_ceilings_GBps": ceilings,
+            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
+            "target_frac": NORTH_STAR_FRAC,
+            "gap_to_target_GBps": round(NORTH_STAR_FRAC * HBM_PEAK_GBS - achieved, 1),
+            "copy_ceiling_frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
         },
         "cpu_baseline": cpu,
     }

@@ -146,8 +146,13 @@ typedef struct lbm_config {
     double g[3];               /* gravity                                           */
     double sigma;              /* surface tension                                   */
     double nu[2];              /* kinematic viscosity per phase                     */
-    double store_ref[4];       /* 16-bit storage: reference per field f, g, hA, hB  */
-    int32_t store_shift[4];    /* 16-bit storage: power-of-two scale per field      */
+    double store_ref[4];       /* 16-bit storage: reference per field f, g, hA, hB:
+                                  moving population k is stored as the deviation
+                                  x - w_k store_ref[F], rounded to nearest even;
+                                  hA, hB must be 0 (w_k mu is near zero)            */
+    int32_t store_shift[4];    /* FP16 storage: the deviation is scaled by
+                                  2^store_shift[F] before rounding (FP16's range);
+                                  BF16 (FP32's exponent range) ignores it           */
     int32_t collision;         /* LBM_BGK (the paper's, 0) or LBM_TRT               */
     int32_t variable_density;  /* 0: Boussinesq (the paper's); 1: rho(phi) model    */
     double trt_magic[2];       /* LBM_TRT: Lambda of f and of g, h^A, h^B (> 0)     */
@@ -161,7 +166,11 @@ typedef struct lbm_handle lbm_handle;
 
 /* Size of the state buffer lbm_init needs (two population copies, a small
  * reduction area and a one-byte-per-node mask of the diagnostics), and of one
- * checkpoint written by lbm_save. */
+ * checkpoint written by lbm_save.
+ * Tuning only: the environment variables LBM_TILE ("64x4" or "32x8" in 3D; "64x1",
+ * "128x1" or "256x1" in 2D) and LBM_ZC (planes per work-group) override the launch
+ * geometry the library chooses.  They are read whenever a configuration is checked,
+ * so lbm_state_bytes and lbm_init must see the same values. */
 int lbm_state_bytes(const lbm_config* cfg, size_t* bytes);
 int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes);
 
@@ -269,6 +278,16 @@ int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, cons
 int lbm_adjoint_theta(lbm_handle* h, void* work, double* grad_theta, void* stream);
 int lbm_adjoint_get(lbm_handle* h, void* work, double* dst, void* stream);
 int lbm_adjoint_set(lbm_handle* h, void* work, const double* src, void* stream);
+
+/*
+ * HBM streaming probe (measurement only, no part of the method): streams `bytes`
+ * (a multiple of 16; 16-byte aligned device buffers) with non-temporal 16-byte
+ * accesses over `grid` work-groups of 256 threads.  mode 0 copies src to dst (one
+ * read and one write per byte, the traffic pattern of a step), 1 reads src only (dst
+ * must hold 1 KiB; written only for negative input), 2 writes dst only.  Returns
+ * LBM_EINVAL for bad arguments.  Asynchronous on `stream`; time it with events.
+ */
+int lbm_probe_stream(const void* src, void* dst, size_t bytes, int32_t mode, int32_t grid, void* stream);
 
 /* Number of steps taken since lbm_init (host counter). */
 int64_t lbm_step_count(const lbm_handle* h);

@@ -159,11 +159,17 @@ __device__ __forceinline__ typename Stor<PREC>::C ld_at(const char* slot, unsign
         return ld_raw<float, NT>(reinterpret_cast<const float*>(slot + idx * 4u));
     } else {
         const unsigned short bits = ld_raw<unsigned short, NT>(reinterpret_cast<const unsigned short*>(slot + idx * 2u));
-        float v;
-        if constexpr (PREC == P16) v = __half2float(__ushort_as_half(bits));
-        else v = float(__builtin_bit_cast(__bf16, bits));
-        return fmaf(v, inv_scale, wref);
+        if constexpr (PREC == P16) return fmaf(__half2float(__ushort_as_half(bits)), inv_scale, wref);
+        else return float(__builtin_bit_cast(__bf16, bits)) + wref;  // BF16: no scale
     }
+}
+
+// 16-bit encoding of one moving population: d = (v - w_k ref) 2^s in FP16, or v - w_k ref
+// in BF16 (its exponent range is FP32's, so it takes no scale), rounded to nearest even
+template <int PREC>
+__device__ __forceinline__ float enc_d(float v, float wref, float scale) {
+    if constexpr (PREC == P16) return (v - wref) * scale;
+    else return v - wref;
 }
 
 // encode and store one population; populations written by a step are read again
@@ -176,7 +182,7 @@ __device__ __forceinline__ void st_at(char* slot, unsigned idx, float wref, floa
     } else if constexpr (PREC == P32 || REST) {
         __builtin_nontemporal_store(float(v), reinterpret_cast<float*>(slot + idx * 4u));
     } else {
-        const float d = (v - wref) * scale;
+        const float d = enc_d<PREC>(v, wref, scale);
         unsigned short bits;
         if constexpr (PREC == P16) bits = __half_as_ushort(__float2half_rn(d));
         else bits = __builtin_bit_cast(unsigned short, __bf16(d));  // round to nearest even
@@ -193,21 +199,42 @@ __device__ __forceinline__ typename Stor<PREC>::C st_at_r(char* slot, unsigned i
         st_at<PREC, REST>(slot, idx, wref, scale, v);
         return v;
     } else {
-        const float d = (v - wref) * scale;
+        const float d = enc_d<PREC>(v, wref, scale);
         unsigned short bits;
         float back;
         if constexpr (PREC == P16) {
             const __half hd = __float2half_rn(d);
             bits = __half_as_ushort(hd);
-            back = __half2float(hd);
+            back = __half2float(hd) * inv_scale;
         } else {
             const __bf16 bd = __bf16(d);  // round to nearest even
             bits = __builtin_bit_cast(unsigned short, bd);
             back = float(bd);
         }
         __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short*>(slot + idx * 2u));
-        return fmaf(back, inv_scale, wref);
+        return back + wref;
     }
+}
+
+// store a moving 16-bit population and return its rounding residue in the encoded
+// domain, d - round(d); (value - stored value) is that times 2^-s (FP16) or itself (BF16)
+template <int PREC>
+__device__ __forceinline__ float st_at_res(char* slot, unsigned idx, float wref, float scale, float v) {
+    static_assert(PREC == P16 || PREC == PB16, "16-bit formats only");
+    const float d = enc_d<PREC>(v, wref, scale);
+    unsigned short bits;
+    float back;
+    if constexpr (PREC == P16) {
+        const __half hd = __float2half_rn(d);
+        bits = __half_as_ushort(hd);
+        back = __half2float(hd);
+    } else {
+        const __bf16 bd = __bf16(d);  // round to nearest even
+        bits = __builtin_bit_cast(unsigned short, bd);
+        back = float(bd);
+    }
+    __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short*>(slot + idx * 2u));
+    return d - back;
 }
 
 // runtime-slot variants (generic copy kernels)
@@ -414,9 +441,12 @@ k_lbm(const KParams P) {
         return (char*)(gmut*)b;
     };
     // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
+    // (zero for h^A, h^B, whose moving equilibria w_k mu are near zero)
     auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {
         using L = typename decltype(lat_)::type;
-        return float(L::w(decltype(k_)::value)) * P.fref[SLOTS::field(decltype(s_)::value)];
+        constexpr int F = SLOTS::field(decltype(s_)::value);
+        if constexpr (F >= 2) return 0.0f;
+        else return float(L::w(decltype(k_)::value)) * P.fref[F];
     };
     auto load = [&](auto s_, auto k_, auto lat_, unsigned idx) __attribute__((always_inline)) -> C {
         constexpr int S = decltype(s_)::value;
@@ -435,11 +465,16 @@ k_lbm(const KParams P) {
         constexpr int S = decltype(s_)::value;
         st_at<PREC, SLOTS::rest(S)>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[SLOTS::field(S)], v);
     };
-    // store and add the rounding residue (value - stored value) to res
+    // store a 16-bit moving population and add its rounding residue, in the encoded
+    // domain, to res; fb<F>(res) is the residue in values of field F
     auto store_r = [&](auto s_, auto k_, auto lat_, unsigned idx, C v, C& res) __attribute__((always_inline)) {
         constexpr int S = decltype(s_)::value;
-        constexpr int F = SLOTS::field(S);
-        res += v - st_at_r<PREC, SLOTS::rest(S)>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[F], P.finv[F], v);
+        static_assert(!SLOTS::rest(S), "rest populations carry no residue");
+        res += st_at_res<PREC>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[SLOTS::field(S)], v);
+    };
+    auto fb = [&](auto f_, C res) __attribute__((always_inline)) -> C {
+        if constexpr (PREC == P16) return res * P.finv[decltype(f_)::value];
+        else return res;
     };
 
     // scalar populations arriving at node idx (pull from idx - e_k)
@@ -750,7 +785,7 @@ k_lbm(const KParams P) {
                                 if constexpr (decltype(kc)::value == 0 && FEEDBACK) restm = v;
                                 else push_r(kc, kc, FLT{}, v, resm);
                             });
-                        if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, restm + resm);
+                        if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, restm + fb(IC<0>{}, resm));
                     } else if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
@@ -766,7 +801,7 @@ k_lbm(const KParams P) {
                         if constexpr (k == 0 && FEEDBACK) rest = v;
                         else push_r(kc, kc, FLT{}, v, res);
                     });
-                    if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + res);
+                    if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + fb(IC<0>{}, res));
                     } else {
                         // TRT: the viscosity sets the symmetric rate w+ = wf; w- from the
                         // magic parameter, 1/w- - 1/2 = Lambda_f / (1/wf - 1/2) = Lambda_f / (3 nu)
@@ -801,7 +836,7 @@ k_lbm(const KParams P) {
                                 push_r(IC<o>{}, IC<o>{}, FLT{}, fpop[o] - sp + sm + Fo, res);
                             }
                         });
-                        if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + res);
+                        if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + fb(IC<0>{}, res));
                     }
                 }
 
@@ -840,7 +875,7 @@ k_lbm(const KParams P) {
                                 if constexpr (decltype(kc)::value == 0 && FEEDBACK) restm = v;
                                 else push_r(IC<G0 + decltype(kc)::value>{}, kc, SLT{}, v, resm);
                             });
-                        if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, restm + resm);
+                        if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, restm + fb(IC<1>{}, resm));
                     } else if constexpr (!TRTC) {
                     C res = C(0), rest = C(0);
                     static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
@@ -854,7 +889,7 @@ k_lbm(const KParams P) {
                         if constexpr (k == 0 && FEEDBACK) rest = v;
                         else push_r(IC<G0 + k>{}, kc, SLT{}, v, res);
                     });
-                    if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + res);
+                    if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + fb(IC<1>{}, res));
                     } else {
                         // TRT: M_phi sets the antisymmetric rate w- = wg; w+ (uniform) from
                         // the magic parameter on the host.  Shifted equilibrium
@@ -884,7 +919,7 @@ k_lbm(const KParams P) {
                                 push_r(IC<G0 + o>{}, IC<o>{}, SLT{}, g[o] - sp + sm + C(SL::w(o)) * S, res);
                             }
                         });
-                        if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + res);
+                        if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + fb(IC<1>{}, res));
                     }
                 }
 
@@ -928,8 +963,8 @@ k_lbm(const KParams P) {
                                           else push_r(IC<B0 + decltype(kc)::value>{}, kc, SLT{}, v, resB);
                                       });
                         if constexpr (FEEDBACK) {
-                            push(IC<A0>{}, IC<0>{}, SLT{}, restA + resA);
-                            push(IC<B0>{}, IC<0>{}, SLT{}, restB + resB);
+                            push(IC<A0>{}, IC<0>{}, SLT{}, restA + fb(IC<2>{}, resA));
+                            push(IC<B0>{}, IC<0>{}, SLT{}, restB + fb(IC<3>{}, resB));
                         }
                     } else if constexpr (TRTC) {
                         // TRT: the mobility sets the antisymmetric rate w- = wA (wB); w+ from
@@ -960,8 +995,8 @@ k_lbm(const KParams P) {
                                 push_r(IC<B0 + o>{}, IC<o>{}, SLT{}, b[o] - wpB * npB + wB * nmB, resB);
                             }
                         });
-                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(resA)));
-                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(resB)));
+                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(fb(IC<2>{}, resA))));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(fb(IC<3>{}, resB))));
                     } else {
                     // rest populations in double: they carry the conserved composition
                     const double whA = double(wA), whB = double(wB);
@@ -986,8 +1021,8 @@ k_lbm(const KParams P) {
                         push_r(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu), resB);
                     });
                     if constexpr (FEEDBACK) {
-                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(resA)));
-                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(resB)));
+                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(fb(IC<2>{}, resA))));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(fb(IC<3>{}, resB))));
                     }
                     }
                 }

@@ -139,6 +139,8 @@ int check_config(const lbm_config* c, Layout* L) {
     if (c->precision >= LBM_FP32_FP16STORE)
         for (int i = 0; i < 4; ++i) {
             if (!finite(c->store_ref[i])) return fail(LBM_EINVAL, "store_ref must be finite");
+            if (i >= 2 && c->store_ref[i] != 0.0)
+                return fail(LBM_EINVAL, "store_ref of h^A, h^B must be 0 (their moving populations have no reference)");
             if (c->store_shift[i] < -30 || c->store_shift[i] > 30)
                 return fail(LBM_EINVAL, "store_shift out of [-30, 30]");
         }
@@ -166,8 +168,8 @@ int check_config(const lbm_config* c, Layout* L) {
     L->copy_bytes = off;
 
     // kernels and launch geometry: TX x TY node columns marching along z in chunks
-    // of zc planes, aiming at about 2048 work-groups (8 per compute unit).
-    // LBM_TILE ("TXxTY") and LBM_ZC override the tile and the chunk for tuning.
+    // of zc planes (see below).  Tuning only: the environment variables LBM_TILE
+    // ("TXxTY", 2D: "TXx1") and LBM_ZC override the tile and the chunk length.
     int want_tx = 0, want_ty = 0;
     if (const char* e = std::getenv("LBM_TILE")) std::sscanf(e, "%dx%d", &want_tx, &want_ty);
     if (mrt && vd) return fail(LBM_EUNSUPPORTED, "the variable-density model runs with BGK or TRT");
@@ -193,7 +195,25 @@ int check_config(const lbm_config* c, Layout* L) {
     L->tx = L->ks->tx;
     L->ty = L->ks->ty;
     const long long gx = (L->NX + L->tx - 1) / L->tx, gy = (L->NY + L->ty - 1) / L->ty;
-    long long nchunks = std::max(1LL, std::min<long long>(L->NZ, 2048 / std::max(1LL, gx * gy)));
+    const long long cols = std::max(1LL, gx * gy);
+    long long nchunks;
+    if (L->dim == 2) {
+        // rows of TX nodes: about 2048 work-groups (8 per compute unit); a 512^2 box then
+        // takes one or two rows per group, the fastest on one MI355X (measured)
+        nchunks = 2048 / cols;
+    } else {
+        // 3D columns: measured on one MI355X (256 compute units), the step is fastest when
+        // all of its work-groups are resident at once, with two per compute unit for
+        // FP32 / FP64 storage (HBM-bound: 15.2 GLUPS at 256^3 against 14.5 with 2048
+        // groups) and three for 16-bit storage (instruction-bound: 21.4 against 20.5);
+        // when the columns alone exceed that, with 64-plane chunks (512^3 BF16: 20.9
+        // GLUPS against 20.0 with 256-plane chunks).  Equal chunks: zc divides nz evenly
+        // when it can.  The layout depends only on the configuration, never on the device.
+        constexpr long long kCUs = 256;
+        const long long per_cu = (L->prec == LBM_FP32 || L->prec == LBM_FP64) ? 2 : 3;
+        nchunks = cols <= per_cu * kCUs ? (per_cu * kCUs) / cols : (L->NZ + 63) / 64;
+    }
+    nchunks = std::max(1LL, std::min<long long>(L->NZ, nchunks));
     int zc = int((L->NZ + nchunks - 1) / nchunks);
     if (const char* e = std::getenv("LBM_ZC")) {
         const int v = std::atoi(e);
@@ -313,7 +333,8 @@ void fill_params(lbm_handle* h) {
     kp.f32.MB1 = float(kp.MB1);
     const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
     for (int f = 0; f < 4; ++f) {
-        const int sh = sixteen ? c.store_shift[f] : 0;
+        // BF16 has the exponent range of FP32: its deviations are stored unscaled
+        const int sh = L.prec == LBM_FP32_FP16STORE ? c.store_shift[f] : 0;
         kp.fref[f] = sixteen ? float(c.store_ref[f]) : 0.0f;
         kp.fscale[f] = std::ldexp(1.0f, sh);
         kp.finv[f] = std::ldexp(1.0f, -sh);

@@ -16,8 +16,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# LBM_LIBRARY selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_HERE, "liblbm.so")
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 # ---- constants of include/lbm.h ------------------------------------------------------
 LBM_OK, LBM_EINVAL, LBM_ESIZE, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_EHIP = 0, -1, -2, -3, -4, -5
@@ -98,6 +97,8 @@ _SIGS = {
     "lbm_adjoint_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_step_count": (ctypes.c_int64, [ctypes.c_void_p]),
+    "lbm_probe_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_void_p]),
     "lbm_destroy": (None, [ctypes.c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
@@ -146,7 +147,7 @@ class LBMConfig:
     gravity_mean_subtract: bool = False
     precision: str = "fp32"
     # 16-bit storage: moving population k of field F (f, g, hA, hB) is stored as
-    # (x - w_k store_ref[F]) * 2^store_shift[F]
+    # (x - w_k store_ref[F]) * 2^store_shift[F] in FP16, as x - w_k store_ref[F] in BF16
     store_ref: Tuple[float, float, float, float] = (0.0, 0.5, 0.0, 0.0)
     store_shift: Tuple[int, int, int, int] = (8, 0, 6, 6)
     # "BGK" (the paper's), "TRT" or "MRT"; TRT magic parameters of (f, the scalar lattices)
