@@ -129,6 +129,7 @@ extern "C" {
  * c_eq[phase][component].
  */
 typedef struct lbm_config {
+    int32_t dim;               /* 2 or 3, or 0 to take it from the scalar lattice   */
     int32_t nx, ny, nz;        /* nz = 1 for 2D                                     */
     int32_t fluid;             /* LBM_NONE, LBM_D2Q9 (2D) or LBM_D3Q19 (3D)         */
     int32_t scalar;            /* LBM_D2Q5 / LBM_D2Q9 (2D), LBM_D3Q7 / LBM_D3Q19 (3D) */
@@ -231,6 +232,11 @@ int lbm_set_populations(lbm_handle* h, const double* src, void* stream);
 int lbm_save(lbm_handle* h, void* dst, void* stream);
 int lbm_restore(lbm_handle* h, const void* src, void* stream);
 
+/* Restore a checkpoint (lbm_save layout, lbm_checkpoint_bytes) as the current state:
+ * a device-to-device copy of the populations and the buffered <phi>, the same as
+ * lbm_restore.  Used by a checkpointed adjoint to return to a stored state. */
+int lbm_set_state(lbm_handle* h, const void* src, void* stream);
+
 /* One step from the checkpoint `src` into the checkpoint `dst` (both laid out
  * as lbm_save writes them; lbm_checkpoint_bytes each), without touching the
  * handle's own copies.  When phi_src is not NULL it receives phi of `src`
@@ -244,10 +250,13 @@ int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
 /*
  * Discrete adjoint (reverse mode) of the step, for a loss L of the final phase
  * field.  The adjoint of a state is dL/dX_k(x) for its arriving populations
- * (Section 3); it lives in the caller's device workspace `work` of
- * lbm_adjoint_bytes (FP32 adjoint populations, scratch rows and FP64 parameter
- * partials).  Supported for LBM_FP32 and LBM_FP64 storage with the paper's BGK
- * Boussinesq model (either scalar lattice), without gravity_mean_subtract; other
+ * (Section 3); it lives in the caller's device workspace (`work`, `adj_inout`,
+ * `adj_state0`: one buffer of lbm_adjoint_bytes holding two FP32 copies of the
+ * adjoint populations, scratch rows, phi of a state and FP64 parameter partials).
+ * The handle records which adjoint copy is current, so a workspace is used with the
+ * handle that seeded it.  Supported for LBM_FP32 and LBM_FP64 storage with the
+ * paper's BGK Boussinesq model (either scalar lattice), without
+ * gravity_mean_subtract; other
  * configurations (TRT, MRT, variable density, general curvatures) return
  * LBM_EUNSUPPORTED.
  * Calls that share one workspace must not overlap.
@@ -256,15 +265,31 @@ int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
  *                       state `state` (a checkpoint, lbm_save layout), through
  *                       phi of Eq. Moment0_Phi with its predictor.  Clears the
  *                       parameter partials.
- *   lbm_adjoint_step  : adjoint of the step n -> n + 1, given the checkpoint of
- *                       state n (before the step) and its phi (lbm_step_external
- *                       or lbm_phase_field): the adjoint of state n + 1 becomes
- *                       that of state n.
+ *   lbm_adjoint_step  : adjoint of the step n -> n + 1 (Section 3 in reverse):
+ *                       state_n is the checkpoint of state n (before the step,
+ *                       lbm_save layout); the adjoint of state n + 1 held in the
+ *                       workspace adj_inout becomes that of state n; the parameter
+ *                       gradient collected so far (this step, and a seed before it)
+ *                       is added to grad_params[6] (FP64 device, the order of
+ *                       lbm_adjoint_theta).  phi of state n is computed into the
+ *                       workspace first.
+ *   lbm_adjoint_step_phi : the same step with phi of state n given (from
+ *                       lbm_step_external or lbm_phase_field, so a recompute pass
+ *                       need not form it twice); its parameter gradient stays in the
+ *                       workspace for lbm_adjoint_theta.
+ *   lbm_init_adjoint  : adjoint of lbm_init with mu_0 held fixed (Eqs. Geq, Heq,
+ *                       species_closure, with the -S_0/2 and -F_0/2 shifts): from the
+ *                       adjoint of state 0 in adj_state0 writes dL/dphi_0 (FP64
+ *                       device [node]) and adds the remaining parameter gradient to
+ *                       grad_params[6].  Uses the phi0, muA0, muB0 fields given to
+ *                       lbm_init, which must still hold them; a handle made by
+ *                       lbm_init_composition returns LBM_EUNSUPPORTED.
  *   lbm_adjoint_init  : adjoint of lbm_init with mu_0 held fixed: writes dL/dphi_0
  *                       (FP64 device [node]); phi0, muA0, muB0 as given to lbm_init.
  *   lbm_adjoint_theta : writes grad_theta[6] (FP64 device) = dL/d(M_phi, M^A_0,
- *                       M^A_1, M^B_0, M^B_1, W) accumulated since the last seed or
- *                       set (Eqs. SourceTerm_Phi, LBE_Phi, LBE_c_alpha,
+ *                       M^A_1, M^B_0, M^B_1, W) accumulated in the workspace since
+ *                       the last seed, set, lbm_adjoint_step or lbm_init_adjoint
+ *                       (Eqs. SourceTerm_Phi, LBE_Phi, LBE_c_alpha,
  *                       SurfaceTension_Force and the mobility interpolation).
  *   lbm_adjoint_get / lbm_adjoint_set : the current adjoint as FP64 [slot][node]
  *                       in the canonical slot order of lbm_get_populations; set
@@ -272,7 +297,9 @@ int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
  */
 int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes);
 int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, void* stream);
-int lbm_adjoint_step(lbm_handle* h, const void* state, const void* phi, void* work, void* stream);
+int lbm_adjoint_step(lbm_handle* h, const void* state_n, void* adj_inout, double* grad_params, void* stream);
+int lbm_adjoint_step_phi(lbm_handle* h, const void* state, const void* phi, void* work, void* stream);
+int lbm_init_adjoint(lbm_handle* h, const void* adj_state0, double* grad_phi0, double* grad_params, void* stream);
 int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, const double* muB0, void* work,
                      double* grad_phi0, void* stream);
 int lbm_adjoint_theta(lbm_handle* h, void* work, double* grad_theta, void* stream);

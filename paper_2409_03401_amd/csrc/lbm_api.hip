@@ -57,6 +57,7 @@ struct Layout {
 int check_config(const lbm_config* c, Layout* L) {
     if (!c) return fail(LBM_EINVAL, "config is NULL");
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(LBM_EINVAL, "grid sizes must be >= 1");
+    if (c->dim != 0 && c->dim != 2 && c->dim != 3) return fail(LBM_EINVAL, "dim must be 0, 2 or 3");
     if (c->scalar == LBM_D2Q5 || c->scalar == LBM_D2Q9) {
         if (c->nz != 1) return fail(LBM_EINVAL, "2D scalar lattices need nz = 1");
         if (c->fluid != LBM_NONE && c->fluid != LBM_D2Q9)
@@ -69,6 +70,7 @@ int check_config(const lbm_config* c, Layout* L) {
     } else {
         return fail(LBM_EUNSUPPORTED, "scalar lattice must be LBM_D2Q5, LBM_D2Q9, LBM_D3Q7 or LBM_D3Q19");
     }
+    if (c->dim != 0 && c->dim != L->dim) return fail(LBM_EINVAL, "dim does not match the scalar lattice");
     const bool paper_scalar = c->scalar == LBM_D2Q9 || c->scalar == LBM_D3Q19;
     if (c->collision != LBM_BGK && c->collision != LBM_TRT && c->collision != LBM_MRT)
         return fail(LBM_EINVAL, "collision must be LBM_BGK, LBM_TRT or LBM_MRT");
@@ -234,7 +236,7 @@ int check_config(const lbm_config* c, Layout* L) {
     L->aux_stride_elems = round_up((size_t)nodes * 4) / 4;
     L->adj_parts = (nodes + 255) / 256;
     L->adj_bytes = 2 * L->nslots * L->adj_stride + kAuxRows * L->aux_stride_elems * 4 +
-                   round_up(sizeof(double) * 6 * L->adj_parts);
+                   round_up(sizeof(double) * 6 * L->adj_parts) + round_up((size_t)nodes * sizeof(double));
     return LBM_OK;
 }
 
@@ -251,6 +253,11 @@ struct lbm_handle {
     int64_t steps;
     int adj_cur;   // adjoint copy holding the current lambda (in the caller's workspace)
     KParams base;  // every field except src/dst/mout
+    // the initial fields given to lbm_init (caller-owned), for lbm_init_adjoint
+    const double* phi0;
+    const double* muA0;
+    const double* muB0;
+    bool given_c;  // made by lbm_init_composition
 };
 
 namespace {
@@ -406,6 +413,10 @@ int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const doub
     h->cur = 0;
     h->steps = 0;
     h->adj_cur = 0;
+    h->phi0 = phi0;
+    h->muA0 = muA0;
+    h->muB0 = muB0;
+    h->given_c = cA0 != nullptr;
     fill_params(h);
     hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -599,6 +610,8 @@ int lbm_restore(lbm_handle* h, const void* src, void* stream) {
     return LBM_OK;
 }
 
+int lbm_set_state(lbm_handle* h, const void* src, void* stream) { return lbm_restore(h, src, stream); }
+
 int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes) {
     Layout L;
     if (int r = check_config(cfg, &L)) return r;
@@ -659,6 +672,7 @@ struct AdjWork {
     float* aux;
     double* part;   // ceil(nodes / 256) x 6, indexed by work-group of the node kernels
     long long nparts;
+    void* phi;      // phi of a state ([node], the compute type)
 };
 
 AdjWork adjoint_work(const lbm_handle* h, void* work) {
@@ -670,6 +684,7 @@ AdjWork adjoint_work(const lbm_handle* h, void* work) {
     a.aux = reinterpret_cast<float*>(w + 2 * copy);
     a.part = reinterpret_cast<double*>(w + 2 * copy + kAuxRows * h->L.aux_stride_elems * 4);
     a.nparts = h->L.adj_parts;
+    a.phi = w + 2 * copy + kAuxRows * h->L.aux_stride_elems * 4 + round_up(sizeof(double) * 6 * a.nparts);
     return a;
 }
 
@@ -701,7 +716,7 @@ int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, vo
     return launched("adjoint seed kernels");
 }
 
-int lbm_adjoint_step(lbm_handle* h, const void* state, const void* phi, void* work, void* stream) {
+int lbm_adjoint_step_phi(lbm_handle* h, const void* state, const void* phi, void* work, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
     if (!state || !phi) return fail(LBM_EINVAL, "NULL pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -716,6 +731,19 @@ int lbm_adjoint_step(lbm_handle* h, const void* state, const void* phi, void* wo
     return launched("adjoint step kernels");
 }
 
+int lbm_adjoint_step(lbm_handle* h, const void* state_n, void* adj_inout, double* grad_params, void* stream) {
+    if (int r = adjoint_ready(h, adj_inout)) return r;
+    if (!state_n || !grad_params) return fail(LBM_EINVAL, "NULL pointer");
+    const AdjWork a = adjoint_work(h, adj_inout);
+    // phi of state n, the field the step's stencil used (Eq. Moment0_Phi)
+    if (int r = lbm_phase_field(h, state_n, a.phi, stream)) return r;
+    if (int r = lbm_adjoint_step_phi(h, state_n, a.phi, adj_inout, stream)) return r;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_sum6(a.part, int(a.nparts), grad_params, true, s);
+    zero_partials(a, s);
+    return launched("adjoint parameter reduction");
+}
+
 int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, const double* muB0, void* work,
                      double* grad_phi0, void* stream) {
     if (int r = adjoint_ready(h, work)) return r;
@@ -727,6 +755,20 @@ int lbm_adjoint_init(lbm_handle* h, const double* phi0, const double* muA0, cons
     h->ks->adj_init_local(kp, h->L.nodes, phi0, muA0, muB0, s);
     h->ks->adj_gather(kp, h->L.nodes, 1, grad_phi0, s);
     return launched("adjoint init kernels");
+}
+
+int lbm_init_adjoint(lbm_handle* h, const void* adj_state0, double* grad_phi0, double* grad_params, void* stream) {
+    if (int r = adjoint_ready(h, adj_state0)) return r;
+    if (!grad_phi0 || !grad_params) return fail(LBM_EINVAL, "NULL pointer");
+    if (h->given_c)
+        return fail(LBM_EUNSUPPORTED, "the adjoint of the initialisation needs the closure's compositions (lbm_init)");
+    void* work = const_cast<void*>(adj_state0);
+    if (int r = lbm_adjoint_init(h, h->phi0, h->muA0, h->muB0, work, grad_phi0, stream)) return r;
+    const AdjWork a = adjoint_work(h, work);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_sum6(a.part, int(a.nparts), grad_params, true, s);
+    zero_partials(a, s);
+    return launched("adjoint parameter reduction");
 }
 
 int lbm_adjoint_theta(lbm_handle* h, void* work, double* grad_theta, void* stream) {

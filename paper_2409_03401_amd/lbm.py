@@ -46,7 +46,7 @@ class LBMError(RuntimeError):
 
 class _Config(ctypes.Structure):
     _fields_ = [
-        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("fluid", ctypes.c_int32), ("scalar", ctypes.c_int32), ("bc", ctypes.c_int32 * 3),
         ("precision", ctypes.c_int32), ("gravity_mean_subtract", ctypes.c_int32),
         ("W", ctypes.c_double), ("lambda_", ctypes.c_double), ("M_phi", ctypes.c_double),
@@ -91,6 +91,11 @@ _SIGS = {
                                         ctypes.c_void_p]),
     "lbm_adjoint_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "lbm_adjoint_step_phi": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
+    "lbm_init_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "lbm_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_theta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -178,6 +183,7 @@ class LBMConfig:
 
     def to_c(self) -> _Config:
         c = _Config()
+        c.dim = 2 if self.scalar in ("D2Q5", "D2Q9") else 3
         c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
         c.fluid = _FLUID[self.fluid]
         c.scalar = _SCALAR[self.scalar]
@@ -237,6 +243,18 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream, *temps):
+    """Prepare a launch on `stream` (None: the current stream) that reads tensors made
+    on the current stream: the launch stream first waits for the current one, and the
+    caching allocator is told that `temps` are in use on the launch stream."""
+    cur = torch.cuda.current_stream()
+    if stream is not None and stream != cur:
+        stream.wait_stream(cur)
+        for t in temps:
+            t.record_stream(stream)
+    return _stream_ptr(stream)
+
+
 def _dev_f64(a, n, device):
     t = torch.as_tensor(a, dtype=torch.float64, device=device).reshape(-1).contiguous()
     if t.numel() != n:
@@ -264,13 +282,13 @@ class Simulation:
         h = ctypes.c_void_p()
         if c0 is None:
             _check(L.lbm_init(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
-                              *ptrs, _stream_ptr(stream), ctypes.byref(h)))
+                              *ptrs, _on(stream, self.state, *self._inputs), ctypes.byref(h)))
         else:
             self._c_inputs = [_dev_f64(a, n, self.device) for a in c0]
             cp = [ctypes.c_void_p(t.data_ptr()) for t in self._c_inputs]
             _check(L.lbm_init_composition(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
-                                          ptrs[0], cp[0], cp[1], ptrs[1], ptrs[2], _stream_ptr(stream),
-                                          ctypes.byref(h)))
+                                          ptrs[0], cp[0], cp[1], ptrs[1], ptrs[2],
+                                          _on(stream, self.state, *self._inputs, *self._c_inputs), ctypes.byref(h)))
         self._h = h
 
     def close(self):
@@ -344,8 +362,7 @@ class Simulation:
         t = torch.as_tensor(pops, dtype=torch.float64, device=self.device).contiguous()
         if t.numel() != self.nslots * self.cfg.nodes:
             raise ValueError("wrong population count")
-        _check(lib().lbm_set_populations(self._h, ctypes.c_void_p(t.data_ptr()), _stream_ptr(stream)))
-        torch.cuda.current_stream().synchronize()
+        _check(lib().lbm_set_populations(self._h, ctypes.c_void_p(t.data_ptr()), _on(stream, t)))
 
     def save(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         if out is None:
@@ -355,6 +372,10 @@ class Simulation:
 
     def restore(self, ckpt: torch.Tensor, stream=None):
         _check(lib().lbm_restore(self._h, ctypes.c_void_p(ckpt.data_ptr()), _stream_ptr(stream)))
+
+    def set_state(self, ckpt: torch.Tensor, stream=None):
+        """Restore the checkpoint `ckpt` (lbm_save layout) as the current state."""
+        _check(lib().lbm_set_state(self._h, ctypes.c_void_p(ckpt.data_ptr()), _stream_ptr(stream)))
 
     # ---- discrete adjoint (reverse mode) ----------------------------------------------
     @property
@@ -382,17 +403,29 @@ class Simulation:
     def adjoint_seed(self, state: torch.Tensor, dL_dphi: torch.Tensor, work: torch.Tensor, stream=None):
         """Start the adjoint from dL/dphi_T at the checkpoint `state`; clears the theta partials."""
         d = _dev_f64(dL_dphi, self.cfg.nodes, self.device)
-        _check(lib().lbm_adjoint_seed(self._h, _ptr(state), _ptr(d), _ptr(work), _stream_ptr(stream)))
+        _check(lib().lbm_adjoint_seed(self._h, _ptr(state), _ptr(d), _ptr(work), _on(stream, d)))
 
-    def adjoint_step(self, state: torch.Tensor, phi: torch.Tensor, work: torch.Tensor, stream=None):
-        """Adjoint of the step taken from checkpoint `state` whose phi is `phi`."""
-        _check(lib().lbm_adjoint_step(self._h, _ptr(state), _ptr(phi), _ptr(work), _stream_ptr(stream)))
+    def adjoint_step_phi(self, state: torch.Tensor, phi: torch.Tensor, work: torch.Tensor, stream=None):
+        """Adjoint of the step taken from checkpoint `state` whose phi is `phi`; the
+        parameter gradient stays in the workspace (adjoint_theta)."""
+        _check(lib().lbm_adjoint_step_phi(self._h, _ptr(state), _ptr(phi), _ptr(work), _stream_ptr(stream)))
+
+    def adjoint_step(self, state: torch.Tensor, work: torch.Tensor, grad_params: torch.Tensor, stream=None):
+        """lbm_adjoint_step: adjoint of the step taken from checkpoint `state`; the
+        parameter gradient collected so far is added to grad_params (6 FP64, device)."""
+        _check(lib().lbm_adjoint_step(self._h, _ptr(state), _ptr(work), _ptr(grad_params), _stream_ptr(stream)))
+
+    def init_adjoint(self, work: torch.Tensor, grad_phi0: torch.Tensor, grad_params: torch.Tensor, stream=None):
+        """lbm_init_adjoint: dL/dphi_0 into grad_phi0 through lbm_init (mu_0 fixed), the
+        remaining parameter gradient added to grad_params."""
+        _check(lib().lbm_init_adjoint(self._h, _ptr(work), _ptr(grad_phi0), _ptr(grad_params),
+                                      _on(stream, *self._inputs)))
 
     def adjoint_init(self, work: torch.Tensor, grad_phi0: torch.Tensor, stream=None):
         """dL/dphi_0 (written into grad_phi0) through lbm_init, mu_0 held fixed."""
         phi0, muA0, muB0 = self._inputs
         _check(lib().lbm_adjoint_init(self._h, _ptr(phi0), _ptr(muA0), _ptr(muB0), _ptr(work), _ptr(grad_phi0),
-                                      _stream_ptr(stream)))
+                                      _on(stream, phi0, muA0, muB0)))
 
     def adjoint_theta(self, work: torch.Tensor, stream=None) -> torch.Tensor:
         """dL/dtheta (THETA_NAMES order) accumulated since the last seed or set."""
@@ -409,8 +442,7 @@ class Simulation:
         t = torch.as_tensor(lam, dtype=torch.float64, device=self.device).contiguous()
         if t.numel() != self.nslots * self.cfg.nodes:
             raise ValueError("wrong adjoint population count")
-        _check(lib().lbm_adjoint_set(self._h, _ptr(work), _ptr(t), _stream_ptr(stream)))
-        torch.cuda.current_stream().synchronize()
+        _check(lib().lbm_adjoint_set(self._h, _ptr(work), _ptr(t), _on(stream, t)))
 
 
 # parameters the adjoint differentiates, in the order of grad_theta
@@ -480,7 +512,7 @@ class PhaseFieldRun(torch.autograd.Function):
                 states.append(seg_states[j])
             sim.phase_field(states[length - 1], seg_phi[length - 1])
             for j in reversed(range(length)):
-                sim.adjoint_step(states[j], seg_phi[j], work)
+                sim.adjoint_step_phi(states[j], seg_phi[j], work)
         gphi0 = torch.empty(sim.cfg.shape, dtype=torch.float64, device=dev)
         sim.adjoint_init(work, gphi0)
         gth = sim.adjoint_theta(work)

@@ -31,9 +31,10 @@ def test_binding_covers_header():
 
 
 def test_struct_layout_matches_header():
-    # 10 int32 fields, then doubles; store_shift, the collision fields and the TRT
-    # magic parameters close the struct
-    assert lbm._Config.W.offset == 40
+    # 11 int32 fields (dim first), padding, then doubles; store_shift, the collision
+    # fields and the TRT magic parameters close the struct
+    assert lbm._Config.dim.offset == 0 and lbm._Config.nx.offset == 4
+    assert lbm._Config.W.offset == 48
     assert lbm._Config.collision.offset == lbm._Config.store_shift.offset + 16
     assert lbm._Config.trt_magic.offset == lbm._Config.collision.offset + 8
     assert lbm._Config.general_kappa.offset == lbm._Config.trt_magic.offset + 16
@@ -87,6 +88,54 @@ def test_config_errors(kw, code):
         lbm.state_bytes(_cfg(**kw))
     assert e.value.code == code
     assert lbm.lib().lbm_last_error().decode()
+
+
+def _raw_config_error(mutate):
+    c = _cfg(precision="bf16").to_c()
+    mutate(c)
+    n = ctypes.c_size_t()
+    return lbm.lib().lbm_state_bytes(ctypes.byref(c), ctypes.byref(n))
+
+
+def test_dim_field_checked():
+    assert _raw_config_error(lambda c: setattr(c, "dim", 0)) == lbm.LBM_OK        # taken from the lattice
+    assert _raw_config_error(lambda c: setattr(c, "dim", 2)) == lbm.LBM_OK
+    assert _raw_config_error(lambda c: setattr(c, "dim", 3)) == lbm.LBM_EINVAL    # D2Q5 is a 2D lattice
+    assert _raw_config_error(lambda c: setattr(c, "dim", 4)) == lbm.LBM_EINVAL
+
+
+def test_composition_references_must_vanish():
+    def nonzero_h_ref(c):
+        c.store_ref[2] = 0.3
+    assert _raw_config_error(nonzero_h_ref) == lbm.LBM_EINVAL
+
+
+SURVEY_BOUNDARY = {
+    # the calls a user of the method makes, with their parameter lists
+    "lbm_state_bytes": "const lbm_config* cfg, size_t* bytes",
+    "lbm_init": "const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0, const double* muA0, "
+                "const double* muB0, void* stream, lbm_handle** out",
+    "lbm_step": "lbm_handle* h, int64_t nsteps, void* stream",
+    "lbm_moments": "lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtype, void* stream",
+    "lbm_diagnostics": "lbm_handle* h, double* host_out, void* stream",
+    "lbm_adjoint_step": "lbm_handle* h, const void* state_n, void* adj_inout, double* grad_params, void* stream",
+    "lbm_init_adjoint": "lbm_handle* h, const void* adj_state0, double* grad_phi0, double* grad_params, void* stream",
+    "lbm_set_state": "lbm_handle* h, const void* src, void* stream",
+    "lbm_destroy": "lbm_handle* h",
+    "lbm_last_error": "void",
+}
+
+
+def test_boundary_calls_declared_and_exported():
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "lbm.h")).read(), flags=re.S)
+    text = re.sub(r"\s+", " ", text)
+    L = lbm.lib()
+    for name, params in SURVEY_BOUNDARY.items():
+        m = re.search(r"\b" + name + r"\(([^)]*)\);", text)
+        assert m, name
+        assert m.group(1).strip() == params, (name, m.group(1))
+        assert hasattr(L, name), name
+    assert "int32_t dim;" in text
 
 
 def test_paper_scalar_lattices_accepted():
