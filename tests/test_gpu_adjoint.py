@@ -164,7 +164,7 @@ def test_adjoint_step_entrywise(name):
 
 
 DOT_CASES = {
-    # grids spanning several tiles and a ragged edge
+    # grids spanning many 256-node work-groups of the adjoint kernels, with a ragged edge
     "d2q9_walls_y_150x77": (dict(nx=150, ny=77, fluid="D2Q9", scalar="D2Q5", bc=("periodic", "walls", "periodic"),
                                  W=4.0, lam=inputs.LAMBDA_TIE, M_phi=0.1, M_A=(0.1, 0.07), M_B=(0.05, 0.09),
                                  drho=0.5, g=(0.0, -1e-4, 0.0), sigma=0.01, nu=(0.1, 0.05)), "fp64"),

@@ -2,7 +2,7 @@
 h^A, h^B), against complex-step derivatives of the FP64 oracle, with the bars of the
 reduced-lattice adjoint tests: every column of J^T lambda (2D) or sampled columns
 (3D) within 2e-6 (FP64), <lambda, J v> = <J^T lambda, v> within 1e-5 on a grid
-spanning several tiles, and the gradient of a phase-field loss through the
+spanning many adjoint work-groups, and the gradient of a phase-field loss through the
 differentiable run in M_phi, W and a direction of phi_0."""
 
 import numpy as np

@@ -45,7 +45,7 @@ CASES = {
     "3d_walls_on_one_node_axis": ((17, 1, 9), dict(bc=("periodic", "walls", "walls"), **FLOW3), 8),
     "2d_walls_two_rows": ((70, 2, 1), dict(bc=("periodic", "walls", "periodic"), **FLOW2), 12),
     "2d_one_column": ((1, 50, 1), dict(bc=("periodic", "walls", "periodic"), **FLOW2), 12),
-    "2d_tile_plus_one_noflow": ((65, 3, 1), dict(bc=("walls", "periodic", "periodic")), 12),
+    "2d_segment_plus_one_noflow": ((257, 3, 1), dict(bc=("walls", "periodic", "periodic")), 12),
 }
 
 

@@ -45,8 +45,9 @@ def _gpu_run(p, precision, phi0, muA0, muB0, steps):
 
 
 # ----------------------------------------------------------------------------------------
-# small cases the oracle finishes in seconds; sizes are ragged with respect to the
-# 64-wide (2D) and 32 x 8 (3D) work-group tiles
+# small cases the oracle finishes in seconds; 3D sizes are ragged with respect to the
+# 64 x 4 work-group tiles (2D cases wider than one 256-node row segment are in
+# test_gpu_2d_tiles.py)
 
 def _drops2d(shape, n, rmin, rmax, W, seed, wall_axes=()):
     rng = np.random.default_rng(seed)
