@@ -296,6 +296,20 @@ int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream);
  *                       also clears the parameter partials.
  */
 int lbm_adjoint_bytes(const lbm_config* cfg, size_t* bytes);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): lbm_adjoint_step without the
+ * workspace's scratch part.  adj_state holds only the adjoint state: two FP32 copies
+ * of Q_tot = Q_f + 3 Q_s adjoint slots followed by three FP32 rows of c_F, each slot
+ * and row round_up(4 nodes, 256) bytes (the leading part of an lbm_adjoint_bytes
+ * workspace, so one seeded by lbm_adjoint_seed or lbm_adjoint_set may be passed).
+ * The per-step scratch (about 36 bytes per node) is a 32 MiB device array inside the
+ * library, one per GPU, held until the process ends; larger grids return LBM_ESIZE.
+ * The call allocates nothing.  The gradient of this step alone is added to
+ * grad_params[6].  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams, other threads) race. */
+int lbm_adjoint_step_noalloc(lbm_handle* h, const void* state_n, void* adj_state, double* grad_params,
+                             void* stream);
 int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, void* work, void* stream);
 int lbm_adjoint_step(lbm_handle* h, const void* state_n, void* adj_inout, double* grad_params, void* stream);
 int lbm_adjoint_step_phi(lbm_handle* h, const void* state, const void* phi, void* work, void* stream);

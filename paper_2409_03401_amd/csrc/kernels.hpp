@@ -1297,7 +1297,7 @@ __global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, 
 
 // ---------------------------------------------------------------------------
 // adjoint kernels.  The adjoint of the arriving population X_s(x) is lambda_s(x)
-// (FP32 [slot][node], P.adj_in / P.adj_out) plus c_F(x) (aux rows 7..9) when s is a
+// (FP32 [slot][node], P.adj_in / P.adj_out) plus c_F(x) (rows of P.auxc) when s is a
 // scalar population of field F.  Kernels over nodes use 256-thread work-groups; their
 // theta partials accumulate in P.partials + 6 * blockIdx.x.
 
@@ -1372,7 +1372,7 @@ k_adj_node(const KParams P, long long nodes, const typename Stor<PREC>::C* __res
                 Nsum += v;
             });
         }
-        const float* cin = P.aux + kAuxC * P.aux_stride;
+        const float* cin = P.auxc;
         const unsigned own = voff(idx * 4u);
         const bool lo[3] = {P.wall_x && x == 0, P.wall_y && y == 0, P.wall_z && z == 0};
         const bool hi[3] = {P.wall_x && x == P.nx - 1, P.wall_y && y == P.ny - 1, P.wall_z && z == P.nz - 1};
@@ -1481,7 +1481,7 @@ __global__ void __launch_bounds__(256) k_adj_seed(const KParams P, long long nod
         const PhiSens ds = phi_sensitivities(ps, cA, cB, P);
         const double s = dL_dphi[i];
         for (int k = 0; k < SLOTS::N; ++k) *adj_at<SL, FL>(P.adj_out, P, k, i) = 0.0f;
-        float* c = P.aux + kAuxC * P.aux_stride;
+        float* c = P.auxc;
         c[0 * P.aux_stride + i] = float(s * ds.d0);
         c[1 * P.aux_stride + i] = float(s * ds.q * (P.c1A - P.c0A));
         c[2 * P.aux_stride + i] = float(s * ds.q * (P.c1B - P.c0B));
@@ -1563,7 +1563,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(const KParams P, long long n
             grad_phi0[i] = double(at(4, i)) + double(psi);
         } else {
             const float q = at(5, i);
-            char* cbase = reinterpret_cast<char*>(P.aux + kAuxC * as);
+            char* cbase = reinterpret_cast<char*>(P.auxc);
             const unsigned o = voff(i * 4u);
             *reinterpret_cast<float*>(cbase + o) = psi * at(4, i);
             *reinterpret_cast<float*>(cbase + as * 4u + o) = psi * q * float(P.c1A - P.c0A);
@@ -1590,7 +1590,7 @@ __global__ void __launch_bounds__(256) k_adj_init_local(const KParams P, long lo
     if (i < nodes) {
         const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
         const unsigned long long as = P.aux_stride;
-        const float* c = P.aux + kAuxC * as;
+        const float* c = P.auxc;
         const double cg = c[0 * as + i], cAa = c[1 * as + i], cBb = c[2 * as + i];
         const double phi = phi0[i], muA = muA0[i], muB = muB0[i];
         const double dA = P.c1A - P.c0A, dB = P.c1B - P.c0B;
@@ -1659,7 +1659,7 @@ __global__ void __launch_bounds__(256) k_adj_copy(const KParams P, long long nod
     const int s = blockIdx.y;
     if (i >= nodes || s >= SLOTS::N) return;
     const int F = s < SLOTS::G0 ? -1 : (s - SLOTS::G0) / SL::Q;
-    float* c = P.aux + kAuxC * P.aux_stride;
+    float* c = P.auxc;
     if constexpr (SET) {
         *adj_at<SL, FL>(P.adj_out, P, s, i) = float(buf[s * nodes + i]);
         if (s == 0) {

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "dispatch.hpp"
@@ -48,9 +49,11 @@ struct Layout {
     size_t aux_bytes;
     size_t mask_off;  // diagnostics mask (1 byte per node) after the aux area
     size_t state_bytes;
-    // adjoint workspace: two FP32 lambda copies, kAuxRows FP32 rows, theta partials of
-    // the adjoint kernels (6 per 256-node work-group)
+    // adjoint workspace: the adjoint state (two FP32 lambda copies, kAuxCRows FP32 rows of
+    // c_F), then the per-step scratch (kAuxRows FP32 rows, theta partials of the adjoint
+    // kernels (6 per 256-node work-group), phi of a state)
     size_t adj_stride, aux_stride_elems, adj_bytes;
+    size_t adj_state_bytes, adj_scratch_bytes;  // the two parts of adj_bytes
     long long adj_parts;
 };
 
@@ -235,8 +238,11 @@ int check_config(const lbm_config* c, Layout* L) {
     L->adj_stride = round_up((size_t)nodes * 4);
     L->aux_stride_elems = round_up((size_t)nodes * 4) / 4;
     L->adj_parts = (nodes + 255) / 256;
-    L->adj_bytes = 2 * L->nslots * L->adj_stride + kAuxRows * L->aux_stride_elems * 4 +
-                   round_up(sizeof(double) * 6 * L->adj_parts) + round_up((size_t)nodes * sizeof(double));
+    // adjoint state first (two lambda copies, the c_F rows), then the per-step scratch
+    L->adj_state_bytes = 2 * L->nslots * L->adj_stride + kAuxCRows * L->aux_stride_elems * 4;
+    L->adj_scratch_bytes = kAuxRows * L->aux_stride_elems * 4 + round_up(sizeof(double) * 6 * L->adj_parts) +
+                           round_up((size_t)nodes * sizeof(double));
+    L->adj_bytes = L->adj_state_bytes + L->adj_scratch_bytes;
     return LBM_OK;
 }
 
@@ -387,6 +393,8 @@ int lbm_checkpoint_bytes(const lbm_config* cfg, size_t* bytes) {
 
 namespace {
 
+int scratch_for_current_device(void** out);  // the scratch of lbm_adjoint_step_noalloc
+
 int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
               const double* cA0, const double* cB0, const double* muA0, const double* muB0, void* stream,
               lbm_handle** out) {
@@ -421,6 +429,11 @@ int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const doub
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     auto bail = [&](int r) { delete h; return r; };
+    {
+        // set-up of the no-alloc adjoint step's scratch on this device (once per device)
+        void* t = nullptr;
+        if (int r = scratch_for_current_device(&t)) return bail(r);
+    }
     if (hipMemsetAsync(h->aux, 0, kAuxHead * sizeof(double), s) != hipSuccess)
         return bail(fail(LBM_EHIP, "hipMemsetAsync of the aux area failed"));
     if (cfg->gravity_mean_subtract) {
@@ -669,23 +682,32 @@ int adjoint_ready(const lbm_handle* h, const void* work) {
 // workspace pieces
 struct AdjWork {
     char* lam[2];
-    float* aux;
+    float* auxc;    // c_F rows (adjoint state)
+    float* aux;     // per-step scratch rows
     double* part;   // ceil(nodes / 256) x 6, indexed by work-group of the node kernels
     long long nparts;
     void* phi;      // phi of a state ([node], the compute type)
 };
 
-AdjWork adjoint_work(const lbm_handle* h, void* work) {
-    char* w = static_cast<char*>(work);
-    const size_t copy = h->L.nslots * h->L.adj_stride;
+// the pieces of an adjoint state buffer `state` and a scratch area `scratch` (which
+// directly follows the state in an lbm_adjoint_bytes workspace)
+AdjWork adjoint_parts(const lbm_handle* h, void* state, void* scratch) {
+    char* w = static_cast<char*>(state);
+    const size_t copy = h->L.nslots * h->L.adj_stride, row = h->L.aux_stride_elems * 4;
     AdjWork a;
     a.lam[0] = w;
     a.lam[1] = w + copy;
-    a.aux = reinterpret_cast<float*>(w + 2 * copy);
-    a.part = reinterpret_cast<double*>(w + 2 * copy + kAuxRows * h->L.aux_stride_elems * 4);
+    a.auxc = reinterpret_cast<float*>(w + 2 * copy);
+    char* t = static_cast<char*>(scratch);
+    a.aux = reinterpret_cast<float*>(t);
+    a.part = reinterpret_cast<double*>(t + kAuxRows * row);
     a.nparts = h->L.adj_parts;
-    a.phi = w + 2 * copy + kAuxRows * h->L.aux_stride_elems * 4 + round_up(sizeof(double) * 6 * a.nparts);
+    a.phi = t + kAuxRows * row + round_up(sizeof(double) * 6 * a.nparts);
     return a;
+}
+
+AdjWork adjoint_work(const lbm_handle* h, void* work) {
+    return adjoint_parts(h, work, static_cast<char*>(work) + h->L.adj_state_bytes);
 }
 
 // adjoint fields of a KParams: lambda copy `in` -> `out`
@@ -694,6 +716,7 @@ void adjoint_params(const lbm_handle* h, KParams& kp, const AdjWork& a, int in, 
     kp.adj_out = out >= 0 ? a.lam[out] : nullptr;
     kp.adj_stride = h->L.adj_stride;
     kp.aux = a.aux;
+    kp.auxc = a.auxc;
     kp.aux_stride = h->L.aux_stride_elems;
     kp.partials = a.part;
 }
@@ -716,11 +739,10 @@ int lbm_adjoint_seed(lbm_handle* h, const void* state, const double* dL_dphi, vo
     return launched("adjoint seed kernels");
 }
 
-int lbm_adjoint_step_phi(lbm_handle* h, const void* state, const void* phi, void* work, void* stream) {
-    if (int r = adjoint_ready(h, work)) return r;
-    if (!state || !phi) return fail(LBM_EINVAL, "NULL pointer");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const AdjWork a = adjoint_work(h, work);
+namespace {
+
+// node and gather kernels of one adjoint step on the pieces `a`, phi of the state given
+int adjoint_step_parts(lbm_handle* h, const void* state, const void* phi, const AdjWork& a, hipStream_t s) {
     KParams kp = h->base;
     set_slots(h, kp, static_cast<const char*>(state), nullptr);
     kp.phi_ref = reinterpret_cast<const double*>(static_cast<const char*>(state) + h->L.copy_bytes);
@@ -729,6 +751,14 @@ int lbm_adjoint_step_phi(lbm_handle* h, const void* state, const void* phi, void
     h->ks->adj_gather(kp, h->L.nodes, 0, nullptr, s);
     h->adj_cur = 1 - h->adj_cur;
     return launched("adjoint step kernels");
+}
+
+}  // namespace
+
+int lbm_adjoint_step_phi(lbm_handle* h, const void* state, const void* phi, void* work, void* stream) {
+    if (int r = adjoint_ready(h, work)) return r;
+    if (!state || !phi) return fail(LBM_EINVAL, "NULL pointer");
+    return adjoint_step_parts(h, state, phi, adjoint_work(h, work), static_cast<hipStream_t>(stream));
 }
 
 int lbm_adjoint_step(lbm_handle* h, const void* state_n, void* adj_inout, double* grad_params, void* stream) {
@@ -741,6 +771,57 @@ int lbm_adjoint_step(lbm_handle* h, const void* state_n, void* adj_inout, double
     hipStream_t s = static_cast<hipStream_t>(stream);
     launch_sum6(a.part, int(a.nparts), grad_params, true, s);
     zero_partials(a, s);
+    return launched("adjoint parameter reduction");
+}
+
+// ---- the adjoint step for callers that cannot allocate ----------------------------
+// Its per-step scratch (kAuxRows rows, theta partials, phi of the state) lives in a
+// file-scope device array of kNoallocScratch bytes, one per GPU, kept until the
+// process ends.  Host code takes the array's device address per device with
+// hipGetSymbolAddress (the array's name is a host-side stand-in, not that address).
+
+namespace {
+
+constexpr size_t kNoallocScratch = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoallocScratch];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the scratch array's address on the current device (looked up once per device)
+int scratch_for_current_device(void** out) {
+    int dev = -1;
+    LBM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        LBM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_adjoint_step_noalloc(lbm_handle* h, const void* state_n, void* adj_state, double* grad_params,
+                             void* stream) {
+    if (int r = adjoint_ready(h, adj_state)) return r;
+    if (!state_n || !grad_params) return fail(LBM_EINVAL, "NULL pointer");
+    if (h->L.adj_scratch_bytes > kNoallocScratch)
+        return fail(LBM_ESIZE, "grid too large for the 32 MiB scratch of lbm_adjoint_step_noalloc "
+                               "(about 36 bytes per node)");
+    void* t = nullptr;
+    if (int r = scratch_for_current_device(&t)) return r;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const AdjWork a = adjoint_parts(h, adj_state, t);
+    // the scratch keeps the previous call's contents: clear it (a kernel, no memset)
+    launch_zero(reinterpret_cast<double*>(t), (long long)(h->L.adj_scratch_bytes / sizeof(double)), s);
+    if (int r = lbm_phase_field(h, state_n, a.phi, stream)) return r;
+    if (int r = adjoint_step_parts(h, state_n, a.phi, a, s)) return r;
+    launch_sum6(a.part, int(a.nparts), grad_params, true, s);
     return launched("adjoint parameter reduction");
 }
 

@@ -91,13 +91,15 @@ struct KParams {
     const double* init_c[2];
     // adjoint kernels.  The adjoint of the arriving
     // population X_s(x) is lambda_s(x) plus, for a scalar population of field F
-    // (g, h^A, h^B), the field-wide term c_F(x) (aux rows 7..9).  lambda is FP32
-    // [slot][node] with slot stride adj_stride bytes.  aux is FP32 [row][node]:
-    // rows 0-2 dL/dG, 3 dL/dN, 4 dphi/dphi*, 5 q of dphi/dc, 6 dphi/dK, 7-9 c_F.
+    // (g, h^A, h^B), the field-wide term c_F(x) (row F - 1 of auxc).  lambda is FP32
+    // [slot][node] with slot stride adj_stride bytes.  aux holds the per-step FP32
+    // [row][node] scratch: rows 0-2 dL/dG, 3 dL/dN, 4 dphi/dphi*, 5 q of dphi/dc,
+    // 6 dphi/dK; auxc the three c_F rows (part of the adjoint state), same row stride.
     const char* adj_in;
     char* adj_out;
     unsigned long long adj_stride;
     float* aux;
+    float* auxc;
     unsigned long long aux_stride;  // elements per aux row
     // MODE_STEP: when set, receives *phi_ref (steps between caller checkpoints)
     double* ref_copy;
@@ -111,8 +113,8 @@ struct KParams {
     char* dst_slot[kMaxSlots];
 };
 
-constexpr int kAuxRows = 10;
-constexpr int kAuxC = 7;  // first row of c_F
+constexpr int kAuxRows = 7;  // per-step scratch rows of the adjoint (c_F rows apart)
+constexpr int kAuxCRows = 3;
 
 // Euler characteristic of the closed cells of a node mask (droplet count of
 // Section 4.2.2).  Only the d active axes of the run are listed: axis i has n[i]

@@ -96,6 +96,8 @@ _SIGS = {
     "lbm_init_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "lbm_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "lbm_adjoint_step_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
     "lbm_adjoint_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "lbm_adjoint_theta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -414,6 +416,19 @@ class Simulation:
         """lbm_adjoint_step: adjoint of the step taken from checkpoint `state`; the
         parameter gradient collected so far is added to grad_params (6 FP64, device)."""
         _check(lib().lbm_adjoint_step(self._h, _ptr(state), _ptr(work), _ptr(grad_params), _stream_ptr(stream)))
+
+    def adjoint_step_noalloc(self, state: torch.Tensor, adj_state: torch.Tensor, grad_params: torch.Tensor,
+                             stream=None):
+        """lbm_adjoint_step_noalloc: the adjoint step with its scratch inside the library
+        (adj_state: the adjoint state part of a workspace, adjoint_state_bytes)."""
+        _check(lib().lbm_adjoint_step_noalloc(self._h, _ptr(state), _ptr(adj_state), _ptr(grad_params),
+                                              _stream_ptr(stream)))
+
+    @property
+    def adjoint_state_bytes(self):
+        """Bytes of the adjoint state (two copies of the adjoint slots, three c_F rows)."""
+        row = (4 * self.cfg.nodes + 255) // 256 * 256
+        return (2 * self.nslots + 3) * row
 
     def init_adjoint(self, work: torch.Tensor, grad_phi0: torch.Tensor, grad_params: torch.Tensor, stream=None):
         """lbm_init_adjoint: dL/dphi_0 into grad_phi0 through lbm_init (mu_0 fixed), the
