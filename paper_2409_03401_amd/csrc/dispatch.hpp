@@ -13,7 +13,8 @@ struct KernelSet {
                  hipStream_t s);
     void (*get_pops)(const KParams& kp, int nslots, long long nodes, double* out, hipStream_t s);
     void (*set_pops)(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s);
-    // bounce-back fix-up on the two faces of one wall axis (0 x, 1 y, 2 z), after a step
+    // bounce-back fix-up on the two faces of one wall axis (0 x, 1 y), after a step (z
+    // walls bounce back when the next step pulls)
     void (*walls)(const KParams& kp, int axis, hipStream_t s);
     // adjoint: nullptr when the storage precision has no adjoint (16-bit formats)
     void (*adj_step)(const KParams& kp, long long nodes, const void* phi, hipStream_t s);

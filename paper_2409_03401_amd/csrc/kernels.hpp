@@ -10,8 +10,13 @@
 // write the other), so ring reads never race with writes.  Streaming is a pull:
 // a copy holds post-collision populations; each node gathers X_k from x - e_k
 // (periodic wrap), collides, and writes its post-collision populations to its
-// own slots, so every store is aligned.  Half-way bounce-back at walls is a
-// small fix-up kernel after the step (k_walls).
+// own slots, so every store is aligned.  Half-way bounce-back at the z walls (the
+// kernel frame's marching axis; the user's y axis in 2D) is taken when pulling: after
+// a step a copy holds each node's raw post-collision populations, and a population
+// X_k(x) whose source x - e_k lies beyond a z wall is read from the node's own slot
+// opp(k) instead (zbounce).  Every reader of a state (step, moments, initialisation,
+// population access, adjoint) follows this rule.  Walls on x and y are a small fix-up
+// kernel after the step (k_walls).
 //
 // Memory layout of one copy: a sequence of slots, one [node] array per
 // (field, direction) in the canonical order f_0.., g_0.., hA_0.., hB_0...  Every
@@ -117,6 +122,16 @@ __device__ __forceinline__ int push_offset(const Nbr& n) {
     return pull_offset<-EX, -EY, -EZ>(n);
 }
 
+// does the pull of a population moving along z-component EZ at a node on the low
+// (zlo) or high (zhi) z wall plane cross the wall?  Then it bounces back: the node's
+// own population of the opposite direction (Section 4.2.4, half-way bounce-back).
+template <int EZ>
+__device__ __forceinline__ bool zbounce(bool zlo, bool zhi) {
+    if constexpr (EZ > 0) return zlo;
+    else if constexpr (EZ < 0) return zhi;
+    else return false;
+}
+
 // ---------------------------------------------------------------------------
 // population storage
 
@@ -140,6 +155,20 @@ template <class SLOTS, int S>
 __device__ __forceinline__ unsigned long long slot_offset(const KParams& P) {
     constexpr int rb = SLOTS::rest_before(S);
     return (unsigned long long)(S - rb) * P.stride_m + (unsigned long long)rb * P.stride_r;
+}
+
+// where a reader finds X_k(x) (slot S = direction k of lattice L of a field): slot S at
+// the pull source x - e_k, or the node's own slot of opp(k) when that crosses a z wall
+// (zbounce).  Returns the slot base in `base`'s copy and the node index in t.
+template <class SLOTS, class L, int S, int K>
+__device__ __forceinline__ const char* pull_src(const char* base, const KParams& P, int z, unsigned idx,
+                                                const Nbr& nb, unsigned& t) {
+    if (zbounce<L::ez(K)>(P.wall_z && z == 0, P.wall_z && z == P.nz - 1)) {
+        t = idx;
+        return base + slot_offset<SLOTS, S - K + L::opp(K)>(P);
+    }
+    t = unsigned(int(idx) + pull_offset<L::ex(K), L::ey(K), L::ez(K)>(nb));
+    return base + slot_offset<SLOTS, S>(P);
 }
 
 // load one population at node idx and decode it to the compute type
@@ -477,15 +506,22 @@ k_lbm(const KParams P) {
         else return res;
     };
 
-    // scalar populations arriving at node idx (pull from idx - e_k)
-    auto load_scalars = [&](unsigned idx, const Nbr& nb, C (&gg)[QS], C (&aa)[QS], C (&bb)[QS],
-                            double& phis, double& cA, double& cB) __attribute__((always_inline)) {
+    // scalar populations arriving at node idx (pull from idx - e_k; the node's own
+    // opposite population where that crosses a z wall: zlo / zhi, wave-uniform)
+    auto load_scalars = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, C (&gg)[QS], C (&aa)[QS],
+                            C (&bb)[QS], double& phis, double& cA, double& cB) __attribute__((always_inline)) {
         static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
-            constexpr int k = decltype(kc)::value;
-            const unsigned src_idx = unsigned(int(idx) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
-            gg[k] = load(IC<G0 + k>{}, kc, SLT{}, src_idx);
-            aa[k] = load(IC<A0 + k>{}, kc, SLT{}, src_idx);
-            bb[k] = load(IC<B0 + k>{}, kc, SLT{}, src_idx);
+            constexpr int k = decltype(kc)::value, o = SL::opp(k);
+            if (zbounce<SL::ez(k)>(zlo, zhi)) {
+                gg[k] = load(IC<G0 + o>{}, IC<o>{}, SLT{}, idx);
+                aa[k] = load(IC<A0 + o>{}, IC<o>{}, SLT{}, idx);
+                bb[k] = load(IC<B0 + o>{}, IC<o>{}, SLT{}, idx);
+            } else {
+                const unsigned src_idx = unsigned(int(idx) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
+                gg[k] = load(IC<G0 + k>{}, kc, SLT{}, src_idx);
+                aa[k] = load(IC<A0 + k>{}, kc, SLT{}, src_idx);
+                bb[k] = load(IC<B0 + k>{}, kc, SLT{}, src_idx);
+            }
         });
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -499,10 +535,11 @@ k_lbm(const KParams P) {
         cB = s2;
     };
 
-    auto node_phi = [&](int xx, int yy, int zz) __attribute__((always_inline)) -> C {
+    auto node_phi = [&](int xx, int yy, int zz, bool zlo, bool zhi) __attribute__((always_inline)) -> C {
         C tg[QS], ta[QS], tb[QS];
         double ps, ca, cb;
-        load_scalars(unsigned((zz * P.ny + yy) * P.nx + xx), neighbours(xx, yy, zz, P), tg, ta, tb, ps, ca, cb);
+        load_scalars(unsigned((zz * P.ny + yy) * P.nx + xx), neighbours(xx, yy, zz, P), zlo, zhi, tg, ta, tb, ps,
+                     ca, cb);
         return C(node_scalars<GK>(ps, ca, cb, P).phi);
     };
 
@@ -511,14 +548,16 @@ k_lbm(const KParams P) {
     double c_ps = 0.0, c_cA = 0.0, c_cB = 0.0, n_ps = 0.0, n_cA = 0.0, n_cB = 0.0;
 
     // phi of plane zz (tile + ring) into LDS slot `slot`; this thread's own node
-    // populations go to the private LDS ring entry `pbuf` when the node is inside
-    auto fill_plane = [&](int zz, int slot, int pbuf, double& ps, double& cA, double& cB)
-                          __attribute__((always_inline)) {
-        const int zm = map_coord(zz, P.nz, P.wall_z);
+    // populations go to the private LDS ring entry `pbuf` when the node is inside.
+    // A z wall plane takes the bounce-back pulls (a separate, uniform branch: the
+    // interior planes keep the plain loads)
+    auto fill_body = [&](int zm, bool zlo, bool zhi, int slot, int pbuf, double& ps, double& cA, double& cB)
+                         __attribute__((always_inline)) {
         if (active) {
             if constexpr (LDS_POPS) {
                 C gg[QS], aa[QS], bb[QS];
-                load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), gg, aa, bb, ps, cA, cB);
+                load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, gg, aa, bb,
+                             ps, cA, cB);
 #pragma unroll
                 for (int k = 0; k < QS; ++k) {
                     spop[pbuf][k][tid] = gg[k];
@@ -526,13 +565,14 @@ k_lbm(const KParams P) {
                     spop[pbuf][2 * QS + k][tid] = bb[k];
                 }
             } else {
-                load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), ng, na, nb, ps, cA, cB);
+                load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, ng, na, nb,
+                             ps, cA, cB);
             }
             sphi[slot][ty + OY][tx + 1] = C(node_scalars<GK>(ps, cA, cB, P).phi);
         } else if (x <= P.nx && y <= P.ny) {
             // ghost column / row just beyond the domain edge
             sphi[slot][ty + OY][tx + 1] = node_phi(map_coord(x, P.nx, P.wall_x),
-                                                   HAS_Y ? map_coord(y, P.ny, P.wall_y) : 0, zm);
+                                                   HAS_Y ? map_coord(y, P.ny, P.wall_y) : 0, zm, zlo, zhi);
         }
         constexpr int NH = HAS_Y ? 2 * LX + 2 * TY : 2;
         for (int i = tid; i < NH; i += NT) {
@@ -550,8 +590,15 @@ k_lbm(const KParams P) {
             const int gy = HAS_Y ? by * TY + hy - 1 : 0;
             if (gx > P.nx || gy > P.ny) continue;  // beyond the ghost layer: never read
             sphi[slot][hy][hx] = node_phi(map_coord(gx, P.nx, P.wall_x),
-                                          HAS_Y ? map_coord(gy, P.ny, P.wall_y) : 0, zm);
+                                          HAS_Y ? map_coord(gy, P.ny, P.wall_y) : 0, zm, zlo, zhi);
         }
+    };
+    auto fill_plane = [&](int zz, int slot, int pbuf, double& ps, double& cA, double& cB)
+                          __attribute__((always_inline)) {
+        const int zm = map_coord(zz, P.nz, P.wall_z);
+        const bool zlo = P.wall_z && zm == 0, zhi = P.wall_z && zm == P.nz - 1;
+        if (zlo || zhi) fill_body(zm, zlo, zhi, slot, pbuf, ps, cA, cB);
+        else fill_body(zm, false, false, slot, pbuf, ps, cA, cB);
     };
 
     constexpr int NACC = (MODE == MODE_DIAG) ? 8 : 1;
@@ -587,15 +634,23 @@ k_lbm(const KParams P) {
         const unsigned idx = unsigned((z * P.ny + y) * P.nx + x);
         const Nbr nbr = neighbours(x, y, z, P);
         C fpop[QF > 0 ? QF : 1];
+        auto load_f_body = [&](bool zlo, bool zhi) __attribute__((always_inline)) {
+            static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                constexpr int k = decltype(kc)::value, o = FL::opp(k);
+                if (zbounce<FL::ez(k)>(zlo, zhi)) {
+                    fpop[k] = load_once(IC<o>{}, IC<o>{}, FLT{}, idx);
+                } else {
+                    const unsigned src_idx = unsigned(int(idx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(nbr));
+                    fpop[k] = load_once(kc, kc, FLT{}, src_idx);
+                }
+            });
+        };
         auto load_f = [&]() __attribute__((always_inline)) {
             if constexpr (FLOW) {
                 if (active) {
-                    static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
-                        constexpr int k = decltype(kc)::value;
-                        const unsigned src_idx =
-                            unsigned(int(idx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(nbr));
-                        fpop[k] = load_once(kc, kc, FLT{}, src_idx);
-                    });
+                    const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
+                    if (zlo || zhi) load_f_body(zlo, zhi);
+                    else load_f_body(false, false);
                 }
             }
         };
@@ -620,7 +675,11 @@ k_lbm(const KParams P) {
                 }
             }
         } else {
-            if (active) load_scalars(idx, nbr, cg, ca, cb, c_ps, c_cA, c_cB);
+            if (active) {
+                const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
+                if (zlo || zhi) load_scalars(idx, nbr, zlo, zhi, cg, ca, cb, c_ps, c_cA, c_cB);
+                else load_scalars(idx, nbr, false, false, cg, ca, cb, c_ps, c_cA, c_cB);
+            }
         }
         if constexpr (!LBM_EARLY_F) load_f();
         const C(&g)[QS] = cg;
@@ -1098,15 +1157,18 @@ __global__ void __launch_bounds__(256) k_walls(const KParams P, int axis) {
     const long long r = t % face;
     c[ab] = int(r % n[ab]);
     c[ac] = int(r / n[ab]);
-    const int wall[3] = {P.wall_x, P.wall_y, P.wall_z};
+    // walls on x and y only: the z walls bounce back when the next step pulls
+    const int wall[3] = {P.wall_x, P.wall_y, 0};
     // skip nodes owned by the face of a lower wall axis
     for (int a = 0; a < axis; ++a)
         if (wall[a] && (c[a] == 0 || c[a] == n[a] - 1)) return;
     if (n[axis] == 1 && t >= face) return;  // both faces are the same plane
     const int idx = (c[2] * P.ny + c[1]) * P.nx + c[0];
 
-    // does x - e lie across a wall?
+    // does x - e lie across an x or y wall (and not across a z wall, which the pull
+    // handles)?
     auto crosses = [&](int ex, int ey, int ez) {
+        if (P.wall_z && ez != 0 && (c[2] - ez < 0 || c[2] - ez >= n[2])) return false;
         const int e[3] = {ex, ey, ez};
         for (int a = 0; a < 3; ++a)
             if (wall[a] && e[a] != 0 && (c[a] - e[a] < 0 || c[a] - e[a] >= n[a])) return true;
@@ -1211,8 +1273,8 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
         using L = typename decltype(lat_)::type;
         constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
         constexpr int F = SLOTS::field(S);
-        char* slot = P.dst_base + slot_offset<SLOTS, S>(P);
-        const unsigned t = unsigned(idx + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
+        unsigned t;
+        char* slot = const_cast<char*>(pull_src<SLOTS, L, S, k>(P.dst_base, P, z, unsigned(idx), nb, t));
         return v - double(st_at_r<PREC, SLOTS::rest(S)>(slot, t, float(L::w(k)) * P.fref[F], P.fscale[F],
                                                          P.finv[F], C(v)));
     };
@@ -1276,13 +1338,12 @@ __global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, 
         using L = typename decltype(lat_)::type;
         constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
         const float wref = float(L::w(k)) * P.fref[SLOTS::field(S)];
+        unsigned t;
         if constexpr (SET) {
-            char* slot = P.dst_base + slot_offset<SLOTS, S>(P);
-            const unsigned t = unsigned(int(i) + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
+            char* slot = const_cast<char*>(pull_src<SLOTS, L, S, k>(P.dst_base, P, z, unsigned(i), nb, t));
             st_at<PREC, SLOTS::rest(S)>(slot, t, wref, P.fscale[SLOTS::field(S)], C(buf[S * nodes + i]));
         } else {
-            const char* slot = P.src_base + slot_offset<SLOTS, S>(P);
-            const unsigned t = unsigned(int(i) + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nb));
+            const char* slot = pull_src<SLOTS, L, S, k>(P.src_base, P, z, unsigned(i), nb, t);
             buf[S * nodes + i] = double(ld_at<PREC, SLOTS::rest(S)>(slot, t, wref, P.finv[SLOTS::field(S)]));
         }
     };
@@ -1343,9 +1404,10 @@ k_adj_node(const KParams P, long long nodes, const typename Stor<PREC>::C* __res
         auto load = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> C {
             using L = typename decltype(lat_)::type;
             constexpr int S = decltype(s_)::value, k = decltype(k_)::value;
-            const unsigned t = unsigned(int(idx) + pull_offset<L::ex(k), L::ey(k), L::ez(k)>(nbr));
-            return ld_at<PREC, SLOTS::rest(S)>(P.src_base + slot_offset<SLOTS, S>(P), t,
-                                               float(L::w(k)) * P.fref[SLOTS::field(S)], P.finv[SLOTS::field(S)]);
+            unsigned t;
+            const char* slot = pull_src<SLOTS, L, S, k>(P.src_base, P, z, idx, nbr, t);
+            return ld_at<PREC, SLOTS::rest(S)>(slot, t, float(L::w(k)) * P.fref[SLOTS::field(S)],
+                                               P.finv[SLOTS::field(S)]);
         };
         C fpop[QF > 0 ? QF : 1], g[QS], a[QS], b[QS];
         static_for<0, QF>([&](auto kc) __attribute__((always_inline)) { fpop[kc.value] = load(kc, kc, FLT{}); });
@@ -1470,13 +1532,13 @@ __global__ void __launch_bounds__(256) k_adj_seed(const KParams P, long long nod
         double ps = 0.0, cA = 0.0, cB = 0.0;
         static_for<0, SL::Q>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const unsigned t = unsigned(int(i) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
-            ps += double(ld_at<PREC, SLOTS::rest(SLOTS::G0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::G0 + k>(P), t,
-                                                                    float(SL::w(k)) * P.fref[1], P.finv[1]));
-            cA += double(ld_at<PREC, SLOTS::rest(SLOTS::A0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::A0 + k>(P), t,
-                                                                    float(SL::w(k)) * P.fref[2], P.finv[2]));
-            cB += double(ld_at<PREC, SLOTS::rest(SLOTS::B0 + k)>(P.src_base + slot_offset<SLOTS, SLOTS::B0 + k>(P), t,
-                                                                    float(SL::w(k)) * P.fref[3], P.finv[3]));
+            unsigned t;
+            const char* sg = pull_src<SLOTS, SL, SLOTS::G0 + k, k>(P.src_base, P, z, unsigned(i), nb, t);
+            const char* sa = pull_src<SLOTS, SL, SLOTS::A0 + k, k>(P.src_base, P, z, unsigned(i), nb, t);
+            const char* sb = pull_src<SLOTS, SL, SLOTS::B0 + k, k>(P.src_base, P, z, unsigned(i), nb, t);
+            ps += double(ld_at<PREC, SLOTS::rest(SLOTS::G0 + k)>(sg, t, float(SL::w(k)) * P.fref[1], P.finv[1]));
+            cA += double(ld_at<PREC, SLOTS::rest(SLOTS::A0 + k)>(sa, t, float(SL::w(k)) * P.fref[2], P.finv[2]));
+            cB += double(ld_at<PREC, SLOTS::rest(SLOTS::B0 + k)>(sb, t, float(SL::w(k)) * P.fref[3], P.finv[3]));
         });
         const PhiSens ds = phi_sensitivities(ps, cA, cB, P);
         const double s = dL_dphi[i];

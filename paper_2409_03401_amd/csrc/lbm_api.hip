@@ -477,10 +477,11 @@ int lbm_step(lbm_handle* h, int64_t nsteps, void* stream) {
     KParams kp[2] = {h->base, h->base};
     set_slots(h, kp[0], h->copy[0], h->copy[1]);
     set_slots(h, kp[1], h->copy[1], h->copy[0]);
-    const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
+    // walls on x and y: the fix-up kernel; z walls bounce back when the next step pulls
+    const int walls[2] = {h->base.wall_x, h->base.wall_y};
     for (int64_t i = 0; i < nsteps; ++i) {
         h->ks->fused(MODE_STEP, h->L.grid, kp[h->cur], s);
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 2; ++a)
             if (walls[a]) h->ks->walls(kp[h->cur], a, s);
         if (h->cfg.gravity_mean_subtract)
             launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), h->aux, s);
@@ -646,8 +647,8 @@ int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, 
     // the buffered <phi> is recomputed with the mean subtraction, else carried over
     kp.ref_copy = h->cfg.gravity_mean_subtract ? nullptr : ref_out;
     h->ks->fused(phi_src ? MODE_STEP_PHI : MODE_STEP, h->L.grid, kp, s);
-    const int walls[3] = {h->base.wall_x, h->base.wall_y, h->base.wall_z};
-    for (int a = 0; a < 3; ++a)
+    const int walls[2] = {h->base.wall_x, h->base.wall_y};
+    for (int a = 0; a < 2; ++a)
         if (walls[a]) h->ks->walls(kp, a, s);
     if (h->cfg.gravity_mean_subtract)
         launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
