@@ -481,8 +481,10 @@ class PhaseFieldRun(torch.autograd.Function):
     backward recomputes each segment from its checkpoint into `segment` state
     buffers (keeping phi of each state, which the step computes anyway) and runs
     the adjoint steps through it in reverse, then the adjoint of the
-    initialisation.  Peak memory: about (steps / segment + segment) checkpoints.
-    mu_0 enters as a constant."""
+    initialisation.  The recompute of a segment runs on a second stream, overlapped with
+    the adjoint steps of the segment after it (two sets of segment buffers).  Peak
+    memory: about (steps / segment + 2 segment) checkpoints.  mu_0 enters as a
+    constant."""
 
     @staticmethod
     def forward(ctx, phi0, theta, cfg, steps, muA0, muB0, segment=None):
@@ -512,25 +514,51 @@ class PhaseFieldRun(torch.autograd.Function):
     def backward(ctx, grad_phiT):
         sim = ctx.sim
         dev = sim.device
+        main = torch.cuda.current_stream(dev)
+        side = torch.cuda.Stream(device=dev)        # default priority
         work = sim.adjoint_workspace()
         sim.adjoint_seed(ctx.final, grad_phiT.detach().to(torch.float64).contiguous(), work)
         nbytes = ctx.final.numel()
         width = min(ctx.seg, ctx.steps)
-        seg_states = [None] + [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(width - 1)]
-        seg_phi = [torch.empty(sim.cfg.nodes, dtype=sim.phi_dtype, device=dev) for _ in range(width)]
-        for s in reversed(range(len(ctx.ckpts))):
+        nseg = len(ctx.ckpts)
+        # two sets of segment buffers: the side stream recomputes segment s - 1 into one
+        # while the adjoint steps of segment s run on the main stream from the other
+        nbuf = 2 if nseg > 1 else 1
+        seg_states = [[None] + [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(width - 1)]
+                      for _ in range(nbuf)]
+        seg_phi = [[torch.empty(sim.cfg.nodes, dtype=sim.phi_dtype, device=dev) for _ in range(width)]
+                   for _ in range(nbuf)]
+        ready = [torch.cuda.Event() for _ in range(nbuf)]
+        free = [torch.cuda.Event() for _ in range(nbuf)]
+        side.wait_stream(main)                      # checkpoints and the seed are done
+
+        def recompute(s, b):
             n0 = s * ctx.seg
             length = min(ctx.seg, ctx.steps - n0)
-            states = [ctx.ckpts[s]]
+            states = [ctx.ckpts[s]] + seg_states[b][1:length]
+            side.wait_event(free[b])                # the adjoint that read buffer b is done
             for j in range(1, length):
-                sim.step_external(states[j - 1], seg_states[j], seg_phi[j - 1])
-                states.append(seg_states[j])
-            sim.phase_field(states[length - 1], seg_phi[length - 1])
-            for j in reversed(range(length)):
-                sim.adjoint_step_phi(states[j], seg_phi[j], work)
+                sim.step_external(states[j - 1], states[j], seg_phi[b][j - 1], stream=side)
+            sim.phase_field(states[length - 1], seg_phi[b][length - 1], stream=side)
+            ready[b].record(side)
+            return states
+
+        pending = recompute(nseg - 1, 0)
+        for i, s in enumerate(reversed(range(nseg))):
+            b = i % nbuf
+            states = pending
+            if s > 0:
+                pending = recompute(s - 1, (i + 1) % nbuf)
+            main.wait_event(ready[b])
+            for j in reversed(range(len(states))):
+                sim.adjoint_step_phi(states[j], seg_phi[b][j], work)
+            free[b].record(main)
         gphi0 = torch.empty(sim.cfg.shape, dtype=torch.float64, device=dev)
         sim.adjoint_init(work, gphi0)
         gth = sim.adjoint_theta(work)
+        main.wait_stream(side)
+        for t in ctx.ckpts + [x for buf in seg_states for x in buf[1:]] + [x for buf in seg_phi for x in buf]:
+            t.record_stream(side)                   # used on the side stream as well
         ctx.sim = ctx.ckpts = ctx.final = None
         return (gphi0.reshape(ctx.phi_shape).to(ctx.phi_dtype), gth.to(ctx.theta_device, ctx.theta_dtype),
                 None, None, None, None, None)
