@@ -72,10 +72,19 @@ class Params:
     # None is the paper's K_pi = K identity
     kappa: Optional[Tuple[Tuple[float, float, float], Tuple[float, float, float]]] = None
     trt_magic: Tuple[float, float] = (3.0 / 16.0, 0.25)   # TRT Lambda of (f, the scalar lattices)
+    # N components (the conclusion's extension, same quadratic free energies): mobilities
+    # (phase 0, phase 1) of the compositions beyond A and B, named C, D, ...; c_eq then
+    # lists 2 + len(M_x) compositions per phase
+    M_x: Tuple[Tuple[float, float], ...] = ()
 
     @property
     def shape(self):
         return (self.nz, self.ny, self.nx)
+
+    @property
+    def ncomp(self):
+        """Number of independent compositions (2 for the ternary fluid)."""
+        return 2 + len(self.M_x)
 
     @property
     def dim(self):
@@ -105,10 +114,12 @@ class State:
     f: Optional[np.ndarray] = None  # [Qf][z][y][x] or None without flow
     phi_ref: complex = 0.0
     step: int = 0
+    hx: Tuple[np.ndarray, ...] = ()  # compositions beyond A, B (C, D, ...)
 
     def copy(self):
         return State(self.g.copy(), self.hA.copy(), self.hB.copy(),
-                     None if self.f is None else self.f.copy(), self.phi_ref, self.step)
+                     None if self.f is None else self.f.copy(), self.phi_ref, self.step,
+                     tuple(h.copy() for h in self.hx))
 
 
 # ----------------------------------------------------------------------------------------
@@ -308,17 +319,23 @@ def trt_collide(X, eqs, src, lat, w_sym, w_anti):
 # ----------------------------------------------------------------------------------------
 # moments
 
+COMP_NAMES = "ABCDEFGH"   # compositions in order: A, B (the ternary fluid), then C, D, ...
+
+
 def scalar_moments(st, prm):
     """Pass 1: compositions, phase field (with the predictor), potentials and source."""
-    cA = st.hA.sum(axis=0)                               # Eq. Moment0_c_alpha
-    cB = st.hB.sum(axis=0)
+    c = tuple(h.sum(axis=0) for h in (st.hA, st.hB) + tuple(st.hx))   # Eq. Moment0_c_alpha
     phi_star = st.g.sum(axis=0)                          # sum_k g_k
-    mu_star = model.closure_mu((cA, cB), phi_star, prm.c_eq, prm.kappa)
+    mu_star = model.closure_mu(c, phi_star, prm.c_eq, prm.kappa)
     S_star = model.source_phi(phi_star, mu_star, prm)
     phi = phi_star + 0.5 * S_star                        # Eq. Moment0_Phi (predictor)
-    mu = model.closure_mu((cA, cB), phi, prm.c_eq, prm.kappa)   # Eq. PotChem
+    mu = model.closure_mu(c, phi, prm.c_eq, prm.kappa)   # Eq. PotChem
     S = model.source_phi(phi, mu, prm)                   # Eq. SourceTerm_Phi
-    return dict(phi=phi, phi_star=phi_star, cA=cA, cB=cB, muA=mu[0], muB=mu[1], S=S)
+    out = dict(phi=phi, phi_star=phi_star, S=S)
+    for a in range(len(c)):
+        out["c" + COMP_NAMES[a]] = c[a]
+        out["mu" + COMP_NAMES[a]] = mu[a]
+    return out
 
 
 def force(phi, prm, phi_ref):
@@ -423,28 +440,34 @@ def moments(st, prm):
 # ----------------------------------------------------------------------------------------
 # init and step
 
-def init(phi0, muA0, muB0, prm, phi_ref=None, c0=None):
+def init(phi0, muA0, muB0, prm, phi_ref=None, c0=None, mu_x0=()):
     """Populations at rest from (phi_0, mu_0), with u = 0 and p_h = 0 (Section 4.2.1):
     c from the closure Eq. species_closure, every population set to its equilibrium
     including the -G_k/2 and -F_k/2 shifts, so that the moments of Eqs. Moment0_Phi
     and Velocity give back phi_0 + O(S) and u = 0.  c0 = (c^A, c^B) gives the
     compositions instead of the closure (the paper's own initial condition, Eq.
-    Compos_Init with mu = 0, is not in equilibrium with the closure)."""
+    Compos_Init with mu = 0, is not in equilibrium with the closure).  mu_x0 holds the
+    initial potentials of the compositions beyond A and B (N components); c0 then lists
+    every composition."""
     phi0 = np.asarray(phi0)
     shape = prm.shape
     phi0 = phi0.reshape(shape)
-    mu0 = (np.asarray(muA0).reshape(shape), np.asarray(muB0).reshape(shape))
+    mu0 = (np.asarray(muA0).reshape(shape), np.asarray(muB0).reshape(shape)) + tuple(
+        np.asarray(m).reshape(shape) for m in mu_x0)
+    if len(mu0) != prm.ncomp:
+        raise ValueError(f"{prm.ncomp} compositions need {prm.ncomp} initial potentials")
     if c0 is None:
         c = model.closure_c(mu0, phi0, prm.c_eq, prm.kappa)
     else:
-        c = (np.asarray(c0[0]).reshape(shape), np.asarray(c0[1]).reshape(shape))
+        c = tuple(np.asarray(ci).reshape(shape) for ci in c0)
     S0 = model.source_phi(phi0, mu0, prm)
     zero = np.zeros_like(phi0 * S0)
     u0 = [zero, zero, zero]
     slat = prm.slat
     g = np.stack([g_equilibrium_k(slat, k, phi0, u0, slat.w[k] * S0) for k in range(slat.Q)])
-    hA = np.stack([h_equilibrium_k(slat, k, c[0], mu0[0], u0) + zero for k in range(slat.Q)])
-    hB = np.stack([h_equilibrium_k(slat, k, c[1], mu0[1], u0) + zero for k in range(slat.Q)])
+    hs = [np.stack([h_equilibrium_k(slat, k, c[a], mu0[a], u0) + zero for k in range(slat.Q)])
+          for a in range(prm.ncomp)]
+    hA, hB = hs[0], hs[1]
     if phi_ref is None:  # buoyancy reference of the initial force (given for a window of a larger box)
         phi_ref = phi0.mean() if prm.gravity_mean_subtract else 0.0
     f = None
@@ -458,7 +481,7 @@ def init(phi0, muA0, muB0, prm, phi_ref=None, c0=None):
             scale = 1.0 / (density(phi0, prm) * flat.cs2)
             f = np.stack([f_equilibrium_k(flat, k, zero, u0, 1.0 / flat.cs2, forcing_k(flat, k, u0, F0) * scale)
                           for k in range(flat.Q)])
-    return State(g=g, hA=hA, hB=hB, f=f, phi_ref=phi_ref, step=0)
+    return State(g=g, hA=hA, hB=hB, f=f, phi_ref=phi_ref, step=0, hx=tuple(hs[2:]))
 
 
 def step(st, prm):
@@ -495,7 +518,11 @@ def step(st, prm):
 
     # h^alpha: Eqs. LBE_c_alpha, Heq with the phase-dependent mobility
     h_post = []
-    for h, c, mu, Mpair in ((st.hA, m["cA"], m["muA"], prm.M_A), (st.hB, m["cB"], m["muB"], prm.M_B)):
+    fields = [(st.hA, m["cA"], m["muA"], prm.M_A), (st.hB, m["cB"], m["muB"], prm.M_B)]
+    for a, (h, Mpair) in enumerate(zip(st.hx, prm.M_x)):
+        name = COMP_NAMES[2 + a]
+        fields.append((h, m["c" + name], m["mu" + name], Mpair))
+    for h, c, mu, Mpair in fields:
         wh = rate(model.mobility(phi, Mpair), slat.cs2)
         if mrt:
             h_post.append(mrt_collide(h, [h_equilibrium_k(slat, k, c, mu, u) for k in range(slat.Q)],
@@ -524,7 +551,8 @@ def step(st, prm):
 
     phi_ref = phi.mean() if prm.gravity_mean_subtract else st.phi_ref
     return State(g=stream(g_post, slat, prm.bc), hA=stream(h_post[0], slat, prm.bc),
-                 hB=stream(h_post[1], slat, prm.bc), f=f_new, phi_ref=phi_ref, step=st.step + 1)
+                 hB=stream(h_post[1], slat, prm.bc), f=f_new, phi_ref=phi_ref, step=st.step + 1,
+                 hx=tuple(stream(h, slat, prm.bc) for h in h_post[2:]))
 
 
 def run(st, prm, nsteps):
@@ -556,11 +584,15 @@ def diagnostics(st, prm):
     u2 = m["ux"] ** 2 + m["uy"] ** 2 + m["uz"] ** 2
     grad = gradient(phi, prm.bc, prm.stencil_lattice)
     g2 = grad[0] ** 2 + grad[1] ** 2 + grad[2] ** 2
-    fe = 0.5 * prm.W ** 2 * g2 + model.omega_dw(phi) + prm.lam * model.bulk_free_energy((m["muA"], m["muB"]), phi,
-                                                                                          prm.kappa)
-    bad = ~(np.isfinite(phi) & np.isfinite(m["cA"]) & np.isfinite(m["cB"]))
+    names = COMP_NAMES[:prm.ncomp]
+    fe = 0.5 * prm.W ** 2 * g2 + model.omega_dw(phi) + prm.lam * model.bulk_free_energy(
+        tuple(m["mu" + a] for a in names), phi, prm.kappa)
+    bad = ~np.isfinite(phi)
+    for a in names:
+        bad |= ~np.isfinite(m["c" + a])
     n_drops = geometry.euler_characteristic(phi.real, prm.bc)
-    return dict(sum_cA=m["cA"].sum(), sum_cB=m["cB"].sum(), sum_phi=phi.sum(),
+    extra = {"sum_c" + a: m["c" + a].sum() for a in names[2:]}
+    return dict(sum_cA=m["cA"].sum(), sum_cB=m["cB"].sum(), sum_phi=phi.sum(), **extra,
                 kinetic_energy=(0.5 * (density(phi, prm) if prm.variable_density else prm.rho0) * u2).sum(),
                 max_u=np.sqrt(u2.real).max(),
                 interface_measure=((4.0 / prm.W) * phi * (1.0 - phi)).sum(),

@@ -33,7 +33,9 @@ def domega_dw(phi):
 def grand_potential(mu, c_eq_pi, kappa_pi=None):
     """Dimensionless grand potential of phase pi, Eq. dimless_grand_potentials:
     omega_pi(mu) = -1/2 sum_alpha (mu_alpha^2 + 2 mu_alpha c_pi^alpha,eq).
-    ``mu`` is a pair (mu_A, mu_B); ``c_eq_pi`` the pair of phase-pi compositions.
+    ``mu`` holds the potentials of the independent compositions (mu_A, mu_B for the
+    ternary fluid; more for the N-component extension of the conclusion, with the same
+    quadratic free energies of Eq. Taylor); ``c_eq_pi`` the phase-pi compositions.
 
     General curvatures (Eq. Taylor with a full matrix K_pi^{alpha beta}): with
     kappa_pi = K (K_pi)^-1 (K the reference curvature that scales mu and omega) the
@@ -41,7 +43,7 @@ def grand_potential(mu, c_eq_pi, kappa_pi=None):
     omega_pi(mu) = -1/2 mu . kappa_pi mu - mu . c_pi^eq; kappa_pi = identity is the
     paper's model.  kappa_pi = (k_AA, k_AB, k_BB), symmetric."""
     if kappa_pi is None:
-        return -0.5 * sum(mu[a] ** 2 + 2.0 * mu[a] * c_eq_pi[a] for a in range(2))
+        return -0.5 * sum(mu[a] ** 2 + 2.0 * mu[a] * c_eq_pi[a] for a in range(len(mu)))
     kAA, kAB, kBB = kappa_pi
     quad = kAA * mu[0] ** 2 + 2.0 * kAB * mu[0] * mu[1] + kBB * mu[1] ** 2
     return -0.5 * quad - (mu[0] * c_eq_pi[0] + mu[1] * c_eq_pi[1])
@@ -64,10 +66,11 @@ def _kappa_phi(phi, kappa):
 def closure_mu(c, phi, c_eq, kappa=None):
     """Inversion of the species closure, Eq. PotChem (Section 2.3/2.5):
     mu^alpha = c^alpha - p(1 - phi) c_0^alpha,eq - p(phi) c_1^alpha,eq.
-    ``c`` is a pair (c_A, c_B); returns the pair (mu_A, mu_B).  With general
-    curvatures c - c^eq(phi) = kappa(phi) mu is solved for mu (a 2 x 2 system)."""
+    ``c`` holds the compositions (c_A, c_B, ...); returns their potentials.  With
+    general curvatures (two compositions) c - c^eq(phi) = kappa(phi) mu is solved for
+    mu (a 2 x 2 system)."""
     if kappa is None:
-        return tuple(c[a] - p(1.0 - phi) * c_eq[0][a] - p(phi) * c_eq[1][a] for a in range(2))
+        return tuple(c[a] - p(1.0 - phi) * c_eq[0][a] - p(phi) * c_eq[1][a] for a in range(len(c)))
     r = [c[a] - p(1.0 - phi) * c_eq[0][a] - p(phi) * c_eq[1][a] for a in range(2)]
     kAA, kAB, kBB = _kappa_phi(phi, kappa)
     det = kAA * kBB - kAB * kAB
@@ -79,7 +82,7 @@ def closure_c(mu, phi, c_eq, kappa=None):
     parabolic grand potentials, i.e. c = mu + p(1 - phi) c_0 + p(phi) c_1; with general
     curvatures c = c^eq(phi) + kappa(phi) mu."""
     if kappa is None:
-        return tuple(mu[a] + p(1.0 - phi) * c_eq[0][a] + p(phi) * c_eq[1][a] for a in range(2))
+        return tuple(mu[a] + p(1.0 - phi) * c_eq[0][a] + p(phi) * c_eq[1][a] for a in range(len(mu)))
     kAA, kAB, kBB = _kappa_phi(phi, kappa)
     return (p(1.0 - phi) * c_eq[0][0] + p(phi) * c_eq[1][0] + kAA * mu[0] + kAB * mu[1],
             p(1.0 - phi) * c_eq[0][1] + p(phi) * c_eq[1][1] + kAB * mu[0] + kBB * mu[1])
@@ -89,7 +92,7 @@ def bulk_free_energy(mu, phi, kappa=None):
     """Bulk free-energy density above the reference equilibrium, in units of K:
     1/2 mu . kappa(phi) mu (|mu|^2 / 2 for the paper's unit curvatures)."""
     if kappa is None:
-        return 0.5 * (mu[0] ** 2 + mu[1] ** 2)
+        return 0.5 * sum(m ** 2 for m in mu)
     kAA, kAB, kBB = _kappa_phi(phi, kappa)
     return 0.5 * (kAA * mu[0] ** 2 + 2.0 * kAB * mu[0] * mu[1] + kBB * mu[1] ** 2)
 
@@ -122,7 +125,7 @@ def lambda_star(W, M_phi, M_alpha, c_eq):
     """Coupling constant that cancels the kinetic coefficient beta of
     Eq. KineticCoeff (Section 2.4):
     beta = (2/3) W / (lambda M_phi) - (19/120) sum_alpha W (c_0 - c_1)^2 / M^alpha = 0."""
-    s = sum((c_eq[0][a] - c_eq[1][a]) ** 2 / M_alpha[a] for a in range(2))
+    s = sum((c_eq[0][a] - c_eq[1][a]) ** 2 / M_alpha[a] for a in range(len(M_alpha)))
     return (2.0 / 3.0) / (M_phi * (19.0 / 120.0) * s)
 
 

@@ -75,14 +75,14 @@ def double_well_d(phi):
 
 
 def potentials(c, phi, prm):
-    """Eq. PotChem with p(1 - phi) = 1 - p(phi)."""
+    """Eq. PotChem with p(1 - phi) = 1 - p(phi), for every composition."""
     q = interp(phi)
-    return [c[a] - (1 - q) * prm["c_eq"][0][a] - q * prm["c_eq"][1][a] for a in range(2)]
+    return [c[a] - (1 - q) * prm["c_eq"][0][a] - q * prm["c_eq"][1][a] for a in range(len(c))]
 
 
 def grand_potential(mu, c_eq_pi):
     """Eq. dimless_grand_potentials: -1/2 sum (mu^2 + 2 mu c_eq)."""
-    return -Fr(1, 2) * sum(mu[a] * mu[a] + 2 * mu[a] * c_eq_pi[a] for a in range(2))
+    return -Fr(1, 2) * sum(mu[a] * mu[a] + 2 * mu[a] * c_eq_pi[a] for a in range(len(mu)))
 
 
 def source(phi, mu, prm):
@@ -120,9 +120,10 @@ def _shift(node, e, shape, bc, mirror):
 def step(state, prm):
     """One step of the map on exact rationals.
 
-    state: dict with 'g', 'hA', 'hB' (and 'f' with flow) mapping to lists over k of dicts
-    node (x, y, z) -> Fraction, and 'phi_ref'.  prm: dict of Fractions and names (see
-    the keys used below).  Returns the new state."""
+    state: dict with 'g', 'hA', 'hB' (and 'f' with flow; 'hx', a list, for compositions
+    beyond A and B) mapping to lists over k of dicts node (x, y, z) -> Fraction, and
+    'phi_ref'.  prm: dict of Fractions and names (see the keys used below; 'M_x' the
+    mobility pairs of the extra compositions).  Returns the new state."""
     shape = prm["shape"]
     bc = prm["bc"]
     nodes = _nodes(shape)
@@ -133,9 +134,11 @@ def step(state, prm):
     stencil = "D2Q9" if dim == 2 else "D3Q19"
 
     # moments, closure, predictor
+    hfields = [state["hA"], state["hB"]] + list(state.get("hx", []))
+    mobil = [prm["M_A"], prm["M_B"]] + list(prm.get("M_x", []))
     mom = {}
     for x in nodes:
-        c = [sum(state["hA"][k][x] for k in range(len(sw))), sum(state["hB"][k][x] for k in range(len(sw)))]
+        c = [sum(h[k][x] for k in range(len(sw))) for h in hfields]
         phi_s = sum(state["g"][k][x] for k in range(len(sw)))
         s_star = source(phi_s, potentials(c, phi_s, prm), prm)
         phi = phi_s + s_star / 2
@@ -170,7 +173,8 @@ def step(state, prm):
     def dot(e, v):
         return e[0] * v[0] + e[1] * v[1] + e[2] * v[2]
 
-    post = {key: [dict() for _ in range(len(sw))] for key in ("g", "hA", "hB")}
+    post = {key: [dict() for _ in range(len(sw))] for key in ("g",)}
+    post["h"] = [[dict() for _ in range(len(sw))] for _ in hfields]
     rate_g = 1 / (prm["M_phi"] / cs2_s + Fr(1, 2))
     for x in nodes:
         phi, S, vel = mom[x]["phi"], mom[x]["S"], u[x]
@@ -179,8 +183,8 @@ def step(state, prm):
             geq = sw[k] * phi * (1 + dot(se[k], vel) / cs2_s) - Gk / 2       # Eq. Geq
             gk = state["g"][k][x]
             post["g"][k][x] = gk - rate_g * (gk - geq) + Gk                  # Eq. LBE_Phi
-        for key, a, Mkey in (("hA", 0, "M_A"), ("hB", 1, "M_B")):
-            M = prm[Mkey][0] * (1 - phi) + prm[Mkey][1] * phi
+        for a, (hf, Mpair) in enumerate(zip(hfields, mobil)):
+            M = Mpair[0] * (1 - phi) + Mpair[1] * phi
             rate_h = 1 / (M / cs2_s + Fr(1, 2))
             c, mu = mom[x]["c"][a], mom[x]["mu"][a]
             for k in range(len(sw)):
@@ -188,8 +192,8 @@ def step(state, prm):
                     heq = c - (1 - sw[0]) * mu                               # Eq. Heq
                 else:
                     heq = sw[k] * mu + sw[k] * c * dot(se[k], vel) / cs2_s
-                hk = state[key][k][x]
-                post[key][k][x] = hk - rate_h * (hk - heq)                   # Eq. LBE_c_alpha
+                hk = hf[k][x]
+                post["h"][a][k][x] = hk - rate_h * (hk - heq)                # Eq. LBE_c_alpha
     if fname:
         post["f"] = [dict() for _ in range(len(fw))]
         for x in nodes:
@@ -207,18 +211,25 @@ def step(state, prm):
                 post["f"][k][x] = fk - rate_f * (fk - feq) + Fk                                        # Eq. LBE_FluidFlow
 
     # streaming: X_k(x + e_k) <- X*_k(x), or back into X_opp(k)(x) across a wall
-    new = {}
-    for key, name in (("g", sname), ("hA", sname), ("hB", sname)) + ((("f", fname),) if fname else ()):
+    def streamed(pops, name):
         e, _ = LATTICES[name]
         out = [dict() for _ in range(len(e))]
         for x in nodes:
             for k in range(len(e)):
                 dest = _shift(x, e[k], shape, bc, False)
                 if dest is None:
-                    out[opposite(name, k)][x] = post[key][k][x]
+                    out[opposite(name, k)][x] = pops[k][x]
                 else:
-                    out[k][dest] = post[key][k][x]
-        new[key] = out
+                    out[k][dest] = pops[k][x]
+        return out
+
+    new = {"g": streamed(post["g"], sname)}
+    hs = [streamed(h, sname) for h in post["h"]]
+    new["hA"], new["hB"] = hs[0], hs[1]
+    if len(hs) > 2:
+        new["hx"] = hs[2:]
+    if fname:
+        new["f"] = streamed(post["f"], fname)
     new["phi_ref"] = (sum(mom[x]["phi"] for x in nodes) / len(nodes) if prm.get("gravity_mean_subtract")
                       else state["phi_ref"])
     return new

@@ -182,3 +182,15 @@ def test_variants_accept_16bit_storage(kw):
     for prec in ("fp16", "bf16"):
         assert lbm.state_bytes(_cfg(precision=prec, fluid="D2Q9", **kw)) > 0
 
+
+
+def test_init_rejects_a_small_state_buffer():
+    """LBM_ESIZE: a state buffer below lbm_state_bytes is refused before any device work."""
+    c = _cfg(fluid="D2Q9")
+    n = lbm.state_bytes(c)
+    h = ctypes.c_void_p()
+    cfg = c.to_c()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the size check comes first
+    r = lbm.lib().lbm_init(ctypes.byref(cfg), fake, n - 1, fake, fake, fake, None, ctypes.byref(h))
+    assert r == lbm.LBM_ESIZE and not h.value
+    assert "smaller" in lbm.lib().lbm_last_error().decode()

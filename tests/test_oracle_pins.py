@@ -611,6 +611,142 @@ def test_whole_map_matches_exact_rational_arithmetic(name):
 
 
 # ----------------------------------------------------------------------------------------
+# N components: the conclusion's extension to more than three components, with the
+# quadratic free energies of Eq. Taylor (unit curvatures) for every independent
+# composition.  Three compositions A, B, C (a quaternary fluid) below.
+
+C_EQ3 = ((0.2, 0.1, 0.15), (0.6, 0.3, 0.05))
+
+
+def _ncomp_case(c_eq=C_EQ3, M_x=((0.08, 0.06),), nx=40, ny=30, seed=41):
+    prm = lbm.Params(nx=nx, ny=ny, fluid="D2Q9", bc=("periodic", "walls", "periodic"), W=4.0, lam=12.0,
+                     M_phi=0.1, M_A=(0.1, 0.07), M_B=(0.05, 0.09), M_x=M_x, c_eq=c_eq, drho=0.5,
+                     g=(0.0, -1e-4, 0.0), sigma=2e-3, nu=(0.1, 0.05))
+    phi0 = _droplet_fields((1, ny, nx), [(20.0, 14.0, 0.0), (8.0, 22.0, 0.0)], [7.0, 4.5], 4.0,
+                           np.random.default_rng(seed))[0]
+    rng = np.random.default_rng(seed + 1)
+    mu = [1e-3 * rng.standard_normal(prm.shape) for _ in range(prm.ncomp)]
+    return prm, phi0, mu
+
+
+def test_ncomp_absent_component_reproduces_ternary():
+    """A fourth component that is absent (zero equilibrium compositions and zero initial
+    potential) stays absent and leaves the ternary run unchanged."""
+    prm3, phi0, mu = _ncomp_case(c_eq=((0.2, 0.1, 0.0), (0.6, 0.3, 0.0)))
+    tern = prm3.with_(M_x=(), c_eq=((0.2, 0.1), (0.6, 0.3)))
+    a = lbm.run(lbm.init(phi0, mu[0], mu[1], tern), tern, 60)
+    b = lbm.run(lbm.init(phi0, mu[0], mu[1], prm3, mu_x0=(0 * mu[2],)), prm3, 60)
+    assert np.all(b.hx[0] == 0.0)
+    for key in ("g", "hA", "hB", "f"):
+        assert np.abs(getattr(a, key) - getattr(b, key)).max() <= 1e-15 * np.abs(getattr(a, key)).max(), key
+
+
+def test_ncomp_relabelling_permutes_the_run():
+    """The model treats every composition alike: relabelling (A, B, C) -> (B, C, A) in the
+    equilibrium compositions, mobilities and initial potentials relabels the run."""
+    prm, phi0, mu = _ncomp_case()
+    st = lbm.run(lbm.init(phi0, mu[0], mu[1], prm, mu_x0=(mu[2],)), prm, 60)
+    perm = (1, 2, 0)
+    mob = (prm.M_A, prm.M_B) + prm.M_x
+    q = prm.with_(c_eq=tuple(tuple(row[i] for i in perm) for row in prm.c_eq), M_A=mob[perm[0]],
+                  M_B=mob[perm[1]], M_x=(mob[perm[2]],))
+    sq = lbm.run(lbm.init(phi0, mu[perm[0]], mu[perm[1]], q, mu_x0=(mu[perm[2]],)), q, 60)
+    h = (st.hA, st.hB, st.hx[0])
+    hq = (sq.hA, sq.hB, sq.hx[0])
+    for j, i in enumerate(perm):
+        assert np.abs(hq[j] - h[i]).max() <= 1e-13 * np.abs(h[i]).max()
+    for key in ("g", "f"):
+        assert np.abs(getattr(sq, key) - getattr(st, key)).max() <= 1e-13 * np.abs(getattr(st, key)).max()
+
+
+def test_ncomp_conserves_every_composition():
+    """Streaming and bounce-back permute populations and every h collision conserves
+    its zeroth moment, so each composition's total is invariant."""
+    prm, phi0, mu = _ncomp_case()
+    st = lbm.init(phi0, mu[0], mu[1], prm, mu_x0=(mu[2],))
+    d0 = lbm.diagnostics(st, prm)
+    st = lbm.run(st, prm, 200)
+    d1 = lbm.diagnostics(st, prm)
+    for k in ("sum_cA", "sum_cB", "sum_cC"):
+        assert abs(d1[k] - d0[k]) <= 1e-12 * abs(d0[k]), k
+    assert d1["nan_count"] == 0
+
+
+def test_ncomp_flat_interface_coexistence():
+    """Three compositions: a flat interface with uniform potentials on the coexistence
+    plane Delta omega = -sum_alpha mu_alpha (c_0 - c_1)_alpha = 0 stays put (all three
+    potentials nonzero); shifted off the plane, phase 1 grows when Delta omega > 0 and
+    shrinks when < 0."""
+    dc = [C_EQ3[0][a] - C_EQ3[1][a] for a in range(3)]
+    muB, muC = 0.01, -0.02
+    muA = -(muB * dc[1] + muC * dc[2]) / dc[0]
+    assert abs(model.delta_omega((muA, muB, muC), C_EQ3)) < 1e-17
+    nx = 48
+    x = np.arange(nx) - (nx - 1) / 2.0
+    phi0 = (0.5 * (1.0 + np.tanh(2.0 * x / 4.0))).reshape(1, 1, nx)
+    prm = lbm.Params(nx=nx, ny=1, bc=("walls", "periodic", "periodic"), W=4.0, lam=2.0, M_phi=0.1,
+                     M_A=(0.1, 0.1), M_B=(0.1, 0.1), M_x=((0.1, 0.1),), c_eq=C_EQ3)
+    moved = {}
+    for shift in (0.0, 0.01, -0.01):
+        st = lbm.init(phi0, np.full_like(phi0, muA + shift), np.full_like(phi0, muB), prm,
+                      mu_x0=(np.full_like(phi0, muC),))
+        s0 = lbm.diagnostics(st, prm)["sum_phi"]
+        st = lbm.run(st, prm, 300)
+        moved[shift] = lbm.diagnostics(st, prm)["sum_phi"] - s0
+    d_plus = model.delta_omega((muA + 0.01, muB, muC), C_EQ3)
+    assert abs(moved[0.0]) < 1e-9
+    assert np.sign(moved[0.01]) == np.sign(d_plus) and abs(moved[0.01]) > 1e3 * abs(moved[0.0]) + 1e-6
+    assert np.sign(moved[-0.01]) == -np.sign(d_plus) and abs(moved[-0.01]) > 1e-6
+
+
+def test_ncomp_whole_map_matches_exact_rational_arithmetic():
+    """The exact rational reference with three compositions: two oracle steps of a 3 x 3
+    grid with flow and walls match it to 1e-14 of each field's largest population."""
+    import exact_map
+    p = _exact_case("2d_flow_walls")
+    p.update(c_eq=((0.25, 0.125, 0.1875), (0.625, 0.3125, 0.0625)), M_x=((0.0625, 0.125),))
+    shape = (p["nz"], p["ny"], p["nx"])
+    nodes = [(x, y, z) for z in range(shape[0]) for y in range(shape[1]) for x in range(shape[2])]
+    rng = np.random.default_rng(6)
+
+    def dyadic(lo, hi, den=4096):
+        return Fr(int(rng.integers(int(lo * den), int(hi * den) + 1)), den)
+
+    _, sw = exact_map.LATTICES[p["scalar"]]
+    _, fw = exact_map.LATTICES[p["fluid"]]
+    phi = {x: dyadic(0.05, 0.95) for x in nodes}
+    st = {"phi_ref": Fr(0)}
+    st["g"] = [{x: sw[k] * phi[x] + dyadic(-0.01, 0.01) for x in nodes} for k in range(len(sw))]
+    cs = [{x: dyadic(lo, hi) for x in nodes} for lo, hi in ((0.2, 0.6), (0.1, 0.3), (0.05, 0.2))]
+    hs = [[{x: (c[x] if k == 0 else 0) + dyadic(-0.01, 0.01) for x in nodes} for k in range(len(sw))] for c in cs]
+    st["hA"], st["hB"], st["hx"] = hs[0], hs[1], [hs[2]]
+    st["f"] = [{x: fw[k] * dyadic(-0.01, 0.01) + dyadic(-0.001, 0.001) for x in nodes} for k in range(len(fw))]
+
+    def arr(pops):
+        a = np.zeros((len(pops),) + shape)
+        for k, d in enumerate(pops):
+            for (x, y, z), v in d.items():
+                a[k, z, y, x] = float(v)
+        return a
+
+    exact_prm = {k: Fr(v) for k, v in p.items() if isinstance(v, float)}
+    exact_prm.update(shape=shape, bc=p["bc"], scalar=p["scalar"], fluid=p["fluid"],
+                     M_A=tuple(map(Fr, p["M_A"])), M_B=tuple(map(Fr, p["M_B"])), nu=tuple(map(Fr, p["nu"])),
+                     M_x=[tuple(map(Fr, m)) for m in p["M_x"]], g=tuple(map(Fr, p["g"])),
+                     c_eq=tuple(tuple(map(Fr, r)) for r in p["c_eq"]))
+    prm = lbm.Params(**p)
+    ost = lbm.State(g=arr(st["g"]), hA=arr(st["hA"]), hB=arr(st["hB"]), f=arr(st["f"]), phi_ref=0.0,
+                    hx=(arr(st["hx"][0]),))
+    for _ in range(2):
+        st = exact_map.step(st, exact_prm)
+        ost = lbm.step(ost, prm)
+        for got, ex in ((ost.g, st["g"]), (ost.hA, st["hA"]), (ost.hB, st["hB"]), (ost.hx[0], st["hx"][0]),
+                        (ost.f, st["f"])):
+            e = arr(ex)
+            assert np.abs(got - e).max() <= 1e-14 * np.abs(e).max()
+
+
+# ----------------------------------------------------------------------------------------
 # flow
 
 @pytest.mark.slow
