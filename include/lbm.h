@@ -79,6 +79,14 @@ extern "C" {
  * predictor velocity sum_k f_k c_k + (F_s + F_b + F_p) / (2 rho)) join the total
  * force.  Buoyancy stays (phi - phi_ref) drho g.  lbm_moments reports p_h. */
 
+/* ncomp = 3 (D2Q5 / D3Q7 scalar lattices, BGK, Boussinesq, any storage precision,
+ * no adjoint): the N-component extension the conclusion names, with one more
+ * independent composition C (four components) and the same quadratic free energies
+ * (Eq. Taylor, unit curvatures).  C has its own h^C populations and mobility M_C;
+ * the closure of Eq. PotChem holds for each composition, and Delta omega =
+ * -sum_alpha mu^alpha (c_0 - c_1)^alpha runs over A, B, C.  Initialise with
+ * lbm_init_multi; populations are ordered f, g, hA, hB, hC. */
+
 #define LBM_PERIODIC 0
 #define LBM_WALLS 1           /* half-way bounce-back walls at both ends of an axis */
 
@@ -100,7 +108,9 @@ extern "C" {
 #define LBM_M_UX (1u << 6)    /* velocity, Eq. Velocity                             */
 #define LBM_M_UY (1u << 7)
 #define LBM_M_UZ (1u << 8)
-#define LBM_NMOM 9
+#define LBM_M_CC (1u << 9)    /* c^C and mu^C of a third composition (ncomp = 3)    */
+#define LBM_M_MUC (1u << 10)
+#define LBM_NMOM 11
 
 /* diagnostics written by lbm_diagnostics, in this order */
 #define LBM_D_SUM_CA 0        /* sum_x c^A                                          */
@@ -110,7 +120,7 @@ extern "C" {
 #define LBM_D_MAX_U 4         /* max_x |u|                                          */
 #define LBM_D_INTERFACE 5     /* sum_x (4/W) phi (1 - phi), integrand of Eq. Rmoy_2D */
 #define LBM_D_FREE_ENERGY 6   /* sum_x [W^2/2 |grad phi|^2 + omega_dw + lambda/2 |mu|^2] */
-#define LBM_D_NAN_COUNT 7     /* nodes whose phi, c^A or c^B is not finite          */
+#define LBM_D_NAN_COUNT 7     /* nodes whose phi or a composition is not finite     */
 /* Section 4.2.2, geometry measurements.  LBM_D_DROPLETS is the Euler
  * characteristic of the union of the closed unit cells of the nodes with
  * phi >= 1/2 (vertices - edges + faces - cubes; periodic axes close on a torus,
@@ -121,7 +131,8 @@ extern "C" {
  * sqrt(I / (4 pi N)) in 3D (spheres), 0 when N <= 0. */
 #define LBM_D_DROPLETS 8
 #define LBM_D_MEAN_RADIUS 9
-#define LBM_NDIAG 10
+#define LBM_D_SUM_CC 10       /* sum_x c^C (ncomp = 3; 0 otherwise)                 */
+#define LBM_NDIAG 11
 
 /*
  * Physical parameters in lattice units (dx = dt = 1).  Section 2 of the paper
@@ -158,9 +169,14 @@ typedef struct lbm_config {
     int32_t variable_density;  /* 0: Boussinesq (the paper's); 1: rho(phi) model    */
     double trt_magic[2];       /* LBM_TRT: Lambda of f and of g, h^A, h^B (> 0)     */
     int32_t general_kappa;     /* 0: the paper's K_pi = K identity; 1: kappa below  */
-    int32_t reserved;          /* 0                                                 */
+    int32_t ncomp;             /* independent compositions: 0 or 2 (A, B: the
+                                  paper's ternary fluid) or 3 (A, B, C)             */
     double kappa[2][3];        /* per phase (k_AA, k_AB, k_BB) = K (K_pi)^-1        */
     double mrt_rates[2][3];    /* LBM_MRT: f (bulk, 3rd, 4th), scalars (2nd, 3rd, 4th) */
+    double c_eq_C[2];          /* ncomp = 3: equilibrium c^C per phase              */
+    double M_C[2];             /* ncomp = 3: scaled mobility of C per phase         */
+    int32_t store_shift_C;     /* ncomp = 3, FP16 storage: shift of h^C (reference 0) */
+    int32_t reserved;          /* 0                                                 */
 } lbm_config;
 
 typedef struct lbm_handle lbm_handle;
@@ -197,13 +213,22 @@ int lbm_init_composition(const lbm_config* cfg, void* state, size_t state_bytes,
                          const double* phi0, const double* cA0, const double* cB0,
                          const double* muA0, const double* muB0, void* stream, lbm_handle** out);
 
+/* Initialisation for any number of compositions (ncomp of the configuration, 2 or
+ * 3): as lbm_init with mu0[a] the FP64 device potential of composition a (A, B, C),
+ * or, when c0 is not NULL, as lbm_init_composition with c0[a] its composition.  mu0
+ * (and c0 when given) are host arrays of ncomp device pointers.  lbm_init and
+ * lbm_init_composition return LBM_EINVAL for ncomp = 3. */
+int lbm_init_multi(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
+                   const double* const* mu0, const double* const* c0, void* stream, lbm_handle** out);
+
 /* Advance nsteps >= 0 time steps (Section 3: moments, forces, BGK collision of
  * f, g, h^A, h^B, streaming with periodic or bounce-back boundaries). */
 int lbm_step(lbm_handle* h, int64_t nsteps, void* stream);
 
 /* Write the macroscopic fields of the current state into out[i] for each bit
  * i set in mask (device arrays of nx*ny*nz elements, LBM_OUT_F64 or
- * LBM_OUT_F32).  Entries of out for unset bits are ignored.  In 2D, uz is 0. */
+ * LBM_OUT_F32).  Entries of out for unset bits are ignored.  In 2D, uz is 0.
+ * LBM_M_CC and LBM_M_MUC need ncomp = 3 (LBM_EINVAL otherwise). */
 int lbm_moments(lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtype,
                 void* stream);
 
@@ -220,8 +245,8 @@ int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream);
 int lbm_run_series(lbm_handle* h, int64_t nsteps, int64_t every, double* host_out, void* stream);
 
 /* Current populations decoded to FP64, canonical order: f_0..f_{Qf-1},
- * g_0..g_{Qs-1}, hA_0.., hB_0.. (paper's direction order), each [node].
- * dst holds (Qf + 3 Qs) * nodes doubles.  set_populations encodes such an
+ * g_0..g_{Qs-1}, hA_0.., hB_0.. (, hC_0..) (paper's direction order), each [node].
+ * dst holds (Qf + (1 + ncomp) Qs) * nodes doubles.  set_populations encodes such an
  * array into the current state (rounding to the storage type). */
 int lbm_get_populations(lbm_handle* h, double* dst, void* stream);
 int lbm_set_populations(lbm_handle* h, const double* src, void* stream);

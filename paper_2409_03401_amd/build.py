@@ -21,7 +21,7 @@ BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["lbm_mrt_3d_q19_flow_fp.hip", "lbm_mrt_3d_q19_flow_16.hip", "lbm_mrt_3d_q19.hip", "lbm_gk_3d.hip",
            "lbm_trt_3d.hip", "lbm_mrt_2d.hip", "lbm_paper_3d.hip", "lbm_3d.hip", "lbm_2d.hip", "lbm_trt_2d.hip",
            "lbm_gk_2d.hip", "lbm_vd_3d.hip", "lbm_mrt_3d.hip", "lbm_paper_2d.hip", "lbm_vd_2d.hip", "lbm_api.hip",
-           "probe.hip"]
+           "probe.hip", "lbm_nc3_3d.hip", "lbm_nc3_2d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

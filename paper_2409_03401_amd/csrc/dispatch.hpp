@@ -8,9 +8,10 @@ namespace lbm {
 struct KernelSet {
     // fused kernel in MODE_STEP / MODE_MOMENTS / MODE_DIAG
     void (*fused)(int mode, dim3 grid, const KParams& kp, hipStream_t s);
-    // equilibrium initialisation, one thread per node
+    // equilibrium initialisation, one thread per node (muC0: the third composition's
+    // potential, families with three compositions only)
     void (*init)(const KParams& kp, const double* phi0, const double* muA0, const double* muB0,
-                 hipStream_t s);
+                 const double* muC0, hipStream_t s);
     void (*get_pops)(const KParams& kp, int nslots, long long nodes, double* out, hipStream_t s);
     void (*set_pops)(const KParams& kp, int nslots, long long nodes, const double* in, hipStream_t s);
     // bounce-back fix-up on the two faces of one wall axis (0 x, 1 y), after a step (z
@@ -46,8 +47,13 @@ const KernelSet* kernels_vd_3d(int scalar, bool trt, int prec);
 // general curvature matrices of the free energies (BGK, Boussinesq): all precisions, no adjoint
 const KernelSet* kernels_gk_2d(int scalar, int fluid, int prec);
 const KernelSet* kernels_gk_3d(int scalar, int fluid, int prec);
+// a third independent composition (N components) on the reduced scalar lattices (D2Q5 /
+// D3Q7), BGK Boussinesq step: all precisions, no adjoint
+const KernelSet* kernels_nc3_2d(int fluid, int prec);
+const KernelSet* kernels_nc3_3d(int fluid, int prec);
 
 void launch_sum_partials(const double* v, long long n, double* partials, int nblocks, hipStream_t s);
+// width 1, 8, or 9 (the diagnostics with a third composition: entry 8 goes to out[10])
 void launch_finalize(const double* partials, int nparts, int width, int maxslot, double scale0,
                      double* out, hipStream_t s);
 // out[0..5] (+)= sum of [nparts][6] partials (parameter gradients)

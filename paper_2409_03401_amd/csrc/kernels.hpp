@@ -135,18 +135,20 @@ __device__ __forceinline__ bool zbounce(bool zlo, bool zhi) {
 // ---------------------------------------------------------------------------
 // population storage
 
-// slot bookkeeping of one lattice family: rest slots (k = 0) are f_0, g_0, hA_0, hB_0
-template <int QF, int QS>
+// slot bookkeeping of one lattice family: f, g, then NC composition fields (hA, hB,
+// and hC with three compositions); rest slots (k = 0) are f_0, g_0, hA_0, hB_0 (, hC_0)
+template <int QF, int QS, int NC = 2>
 struct Slots {
-    static constexpr int G0 = QF, A0 = QF + QS, B0 = QF + 2 * QS, N = QF + 3 * QS;
+    static constexpr int G0 = QF, A0 = QF + QS, B0 = QF + 2 * QS, C0 = QF + 3 * QS, N = QF + (1 + NC) * QS;
     __host__ __device__ static constexpr bool rest(int s) {
-        return (QF > 0 && s == 0) || s == G0 || s == A0 || s == B0;
+        return (QF > 0 && s == 0) || s == G0 || s == A0 || s == B0 || (NC >= 3 && s == C0);
     }
     __host__ __device__ static constexpr int rest_before(int s) {
-        return (QF > 0 && s > 0 ? 1 : 0) + (s > G0 ? 1 : 0) + (s > A0 ? 1 : 0) + (s > B0 ? 1 : 0);
+        return (QF > 0 && s > 0 ? 1 : 0) + (s > G0 ? 1 : 0) + (s > A0 ? 1 : 0) + (s > B0 ? 1 : 0) +
+               (NC >= 3 && s > C0 ? 1 : 0);
     }
     __host__ __device__ static constexpr int field(int s) {
-        return s < G0 ? 0 : (s < A0 ? 1 : (s < B0 ? 2 : 3));
+        return s < G0 ? 0 : (s < A0 ? 1 : (s < B0 ? 2 : (s < C0 ? 3 : 4)));
     }
 };
 
@@ -392,11 +394,11 @@ constexpr int basis_order() { return kBasis<L>.order[I]; }
 template <class L, int I>
 constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBasis<L>.order[I - 1] != 2); }
 
-template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK>
+template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK, int NC = 2>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
 k_lbm(const KParams P) {
     using C = typename Stor<PREC>::C;
-    using SLOTS = Slots<FL::Q, SL::Q>;
+    using SLOTS = Slots<FL::Q, SL::Q, NC>;
     constexpr int QS = SL::Q;
     constexpr int QF = FL::Q;
     constexpr bool FLOW = QF > 0;
@@ -408,7 +410,12 @@ k_lbm(const KParams P) {
     constexpr int OY = HAS_Y ? 1 : 0;
     constexpr int NSLOT = STENCIL ? 3 : 1;
     constexpr int NT = TX * TY;
-    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
+    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0, HC0 = SLOTS::C0;
+    // NC = 3: a third independent composition C (N components), BGK Boussinesq step
+    constexpr bool NC3 = NC == 3;
+    constexpr int QC = NC3 ? QS : 1;
+    static_assert(NC == 2 || (NC == 3 && COLL == COLL_BGK), "a third composition runs with the BGK Boussinesq step");
+    static_assert(SLOTS::N <= kMaxSlots, "slot table too small for this lattice family");
     constexpr C inv_cs2s = C(1.0 / SL::cs2);
     constexpr bool TRTC = (COLL & COLL_TRT) != 0;
     constexpr bool MRTC = (COLL & COLL_MRT) != 0;
@@ -417,12 +424,12 @@ k_lbm(const KParams P) {
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
     // the private LDS ring of scalar populations, unless it would not leave room for
     // a second work-group per compute unit (the paper's D3Q19 scalar lattice)
-    constexpr bool LDS_POPS = LBM_LDS_POPS && 2 * 3 * QS * NT * sizeof(C) <= 96 * 1024;
+    constexpr bool LDS_POPS = LBM_LDS_POPS && 2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024;
 
     __shared__ C sphi[NSLOT][LY][LX];
     // this thread's own scalar populations of the current and the next plane
     // (thread-private ring of two planes, [plane][slot][thread], no barriers needed)
-    __shared__ C spop[(STENCIL && LDS_POPS) ? 2 : 1][(STENCIL && LDS_POPS) ? 3 * QS : 1]
+    __shared__ C spop[(STENCIL && LDS_POPS) ? 2 : 1][(STENCIL && LDS_POPS) ? (1 + NC) * QS : 1]
                      [(STENCIL && LDS_POPS) ? NT : 1];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -509,66 +516,77 @@ k_lbm(const KParams P) {
     // scalar populations arriving at node idx (pull from idx - e_k; the node's own
     // opposite population where that crosses a z wall: zlo / zhi, wave-uniform)
     auto load_scalars = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, C (&gg)[QS], C (&aa)[QS],
-                            C (&bb)[QS], double& phis, double& cA, double& cB) __attribute__((always_inline)) {
+                            C (&bb)[QS], C (&qq)[QC], double& phis, double& cA, double& cB, double& cC)
+                            __attribute__((always_inline)) {
         static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value, o = SL::opp(k);
             if (zbounce<SL::ez(k)>(zlo, zhi)) {
                 gg[k] = load(IC<G0 + o>{}, IC<o>{}, SLT{}, idx);
                 aa[k] = load(IC<A0 + o>{}, IC<o>{}, SLT{}, idx);
                 bb[k] = load(IC<B0 + o>{}, IC<o>{}, SLT{}, idx);
+                if constexpr (NC3) qq[k] = load(IC<HC0 + o>{}, IC<o>{}, SLT{}, idx);
             } else {
                 const unsigned src_idx = unsigned(int(idx) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
                 gg[k] = load(IC<G0 + k>{}, kc, SLT{}, src_idx);
                 aa[k] = load(IC<A0 + k>{}, kc, SLT{}, src_idx);
                 bb[k] = load(IC<B0 + k>{}, kc, SLT{}, src_idx);
+                if constexpr (NC3) qq[k] = load(IC<HC0 + k>{}, kc, SLT{}, src_idx);
             }
         });
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
         for (int k = 0; k < QS; ++k) {
             s0 += double(gg[k]);
             s1 += double(aa[k]);
             s2 += double(bb[k]);
+            if constexpr (NC3) s3 += double(qq[k]);
         }
         phis = s0;
         cA = s1;
         cB = s2;
+        cC = s3;
+    };
+    // phi of a node from its population sums (Eqs. Moment0_Phi, PotChem)
+    auto phi_from = [&](double ps, double sa, double sb, double sc) __attribute__((always_inline)) -> double {
+        if constexpr (NC3) return node_scalars3(ps, sa, sb, sc, P).phi;
+        else return node_scalars<GK>(ps, sa, sb, P).phi;
     };
 
     auto node_phi = [&](int xx, int yy, int zz, bool zlo, bool zhi) __attribute__((always_inline)) -> C {
-        C tg[QS], ta[QS], tb[QS];
-        double ps, ca, cb;
-        load_scalars(unsigned((zz * P.ny + yy) * P.nx + xx), neighbours(xx, yy, zz, P), zlo, zhi, tg, ta, tb, ps,
-                     ca, cb);
-        return C(node_scalars<GK>(ps, ca, cb, P).phi);
+        C tg[QS], ta[QS], tb[QS], tq[QC];
+        double ps, sa, sb, sc;
+        load_scalars(unsigned((zz * P.ny + yy) * P.nx + xx), neighbours(xx, yy, zz, P), zlo, zhi, tg, ta, tb, tq,
+                     ps, sa, sb, sc);
+        return C(phi_from(ps, sa, sb, sc));
     };
 
     // scalar populations and sums of this thread's node: current plane (c*) and next plane (n*)
-    C cg[QS], ca[QS], cb[QS], ng[QS], na[QS], nb[QS];
-    double c_ps = 0.0, c_cA = 0.0, c_cB = 0.0, n_ps = 0.0, n_cA = 0.0, n_cB = 0.0;
+    C cg[QS], ca[QS], cb[QS], ng[QS], na[QS], nb[QS], cq[QC], nq[QC];
+    double c_ps = 0.0, c_cA = 0.0, c_cB = 0.0, n_ps = 0.0, n_cA = 0.0, n_cB = 0.0, c_cC = 0.0, n_cC = 0.0;
 
     // phi of plane zz (tile + ring) into LDS slot `slot`; this thread's own node
     // populations go to the private LDS ring entry `pbuf` when the node is inside.
     // A z wall plane takes the bounce-back pulls (a separate, uniform branch: the
     // interior planes keep the plain loads)
-    auto fill_body = [&](int zm, bool zlo, bool zhi, int slot, int pbuf, double& ps, double& cA, double& cB)
-                         __attribute__((always_inline)) {
+    auto fill_body = [&](int zm, bool zlo, bool zhi, int slot, int pbuf, double& ps, double& cA, double& cB,
+                         double& cC) __attribute__((always_inline)) {
         if (active) {
             if constexpr (LDS_POPS) {
-                C gg[QS], aa[QS], bb[QS];
+                C gg[QS], aa[QS], bb[QS], qq[QC];
                 load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, gg, aa, bb,
-                             ps, cA, cB);
+                             qq, ps, cA, cB, cC);
 #pragma unroll
                 for (int k = 0; k < QS; ++k) {
                     spop[pbuf][k][tid] = gg[k];
                     spop[pbuf][QS + k][tid] = aa[k];
                     spop[pbuf][2 * QS + k][tid] = bb[k];
+                    if constexpr (NC3) spop[pbuf][3 * QS + k][tid] = qq[k];
                 }
             } else {
                 load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, ng, na, nb,
-                             ps, cA, cB);
+                             nq, ps, cA, cB, cC);
             }
-            sphi[slot][ty + OY][tx + 1] = C(node_scalars<GK>(ps, cA, cB, P).phi);
+            sphi[slot][ty + OY][tx + 1] = C(phi_from(ps, cA, cB, cC));
         } else if (x <= P.nx && y <= P.ny) {
             // ghost column / row just beyond the domain edge
             sphi[slot][ty + OY][tx + 1] = node_phi(map_coord(x, P.nx, P.wall_x),
@@ -593,15 +611,16 @@ k_lbm(const KParams P) {
                                           HAS_Y ? map_coord(gy, P.ny, P.wall_y) : 0, zm, zlo, zhi);
         }
     };
-    auto fill_plane = [&](int zz, int slot, int pbuf, double& ps, double& cA, double& cB)
+    auto fill_plane = [&](int zz, int slot, int pbuf, double& ps, double& cA, double& cB, double& cC)
                           __attribute__((always_inline)) {
         const int zm = map_coord(zz, P.nz, P.wall_z);
         const bool zlo = P.wall_z && zm == 0, zhi = P.wall_z && zm == P.nz - 1;
-        if (zlo || zhi) fill_body(zm, zlo, zhi, slot, pbuf, ps, cA, cB);
-        else fill_body(zm, false, false, slot, pbuf, ps, cA, cB);
+        if (zlo || zhi) fill_body(zm, zlo, zhi, slot, pbuf, ps, cA, cB, cC);
+        else fill_body(zm, false, false, slot, pbuf, ps, cA, cB, cC);
     };
 
-    constexpr int NACC = (MODE == MODE_DIAG) ? 8 : 1;
+    // diagnostics: the kNumDiag reductions, then sum c^C with a third composition
+    constexpr int NACC = (MODE == MODE_DIAG) ? (NC3 ? kNumDiag + 1 : kNumDiag) : 1;
     double acc[NACC];
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
@@ -619,11 +638,15 @@ k_lbm(const KParams P) {
 
     if constexpr (STENCIL) {
         if (z0 < z1) {
-            fill_plane(z0 - 1, 0, 1, n_ps, n_cA, n_cB);  // ring only; own entries overwritten next
-            fill_plane(z0, 1, 0, c_ps, c_cA, c_cB);
+            fill_plane(z0 - 1, 0, 1, n_ps, n_cA, n_cB, n_cC);  // ring only; own entries overwritten next
+            fill_plane(z0, 1, 0, c_ps, c_cA, c_cB, c_cC);
             if constexpr (!LDS_POPS) {
 #pragma unroll
                 for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
+                if constexpr (NC3) {
+#pragma unroll
+                    for (int k = 0; k < QS; ++k) cq[k] = nq[k];
+                }
             }
         }
     }
@@ -661,7 +684,7 @@ k_lbm(const KParams P) {
             sm = (z - z0) % 3;
             sc = (z - z0 + 1) % 3;
             sp = (z - z0 + 2) % 3;
-            fill_plane(z + 1, sp, (z - z0 + 1) & 1, n_ps, n_cA, n_cB);
+            fill_plane(z + 1, sp, (z - z0 + 1) & 1, n_ps, n_cA, n_cB, n_cC);
             __syncthreads();
             if constexpr (LDS_POPS) {
                 if (active) {
@@ -671,24 +694,33 @@ k_lbm(const KParams P) {
                         cg[k] = spop[pb][k][tid];
                         ca[k] = spop[pb][QS + k][tid];
                         cb[k] = spop[pb][2 * QS + k][tid];
+                        if constexpr (NC3) cq[k] = spop[pb][3 * QS + k][tid];
                     }
                 }
             }
         } else {
             if (active) {
                 const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
-                if (zlo || zhi) load_scalars(idx, nbr, zlo, zhi, cg, ca, cb, c_ps, c_cA, c_cB);
-                else load_scalars(idx, nbr, false, false, cg, ca, cb, c_ps, c_cA, c_cB);
+                if (zlo || zhi) load_scalars(idx, nbr, zlo, zhi, cg, ca, cb, cq, c_ps, c_cA, c_cB, c_cC);
+                else load_scalars(idx, nbr, false, false, cg, ca, cb, cq, c_ps, c_cA, c_cB, c_cC);
             }
         }
         if constexpr (!LBM_EARLY_F) load_f();
         const C(&g)[QS] = cg;
         const C(&a)[QS] = ca;
         const C(&b)[QS] = cb;
-        const double sA = c_cA, sB = c_cB;
+        const double sA = c_cA, sB = c_cB, sC = c_cC;
 
         if (active) {
-            const Scalars m = node_scalars<GK>(c_ps, sA, sB, P);
+            Scalars m;
+            double muC = 0.0;  // potential of a third composition
+            if constexpr (NC3) {
+                const Scalars3 m3 = node_scalars3(c_ps, sA, sB, sC, P);
+                m = Scalars{m3.phi, m3.muA, m3.muB, m3.S};
+                muC = m3.muC;
+            } else {
+                m = node_scalars<GK>(c_ps, sA, sB, P);
+            }
             const C phi = C(m.phi);
 
             // isotropic gradient and Laplacian, Eqs. Grad and Laplacian (fluid lattice)
@@ -1071,6 +1103,18 @@ k_lbm(const KParams P) {
                     const C wmuA = wA * C(m.muA), wmuB = wB * C(m.muB);
                     const C wcA = wA * C(sA) * inv_cs2s, wcB = wB * C(sB) * inv_cs2s;
                     C resA = C(0), resB = C(0);
+                    // a third composition: the same BGK relaxation with its own mobility
+                    C keepC = C(0), wmuC = C(0), wcC = C(0), resC = C(0);
+                    double pq = 0.0;
+                    if constexpr (NC3) {
+                        const C MC = KC(P.MC0, P.f32.MC0) * (C(1) - phi) + KC(P.MC1, P.f32.MC1) * phi;
+                        const C wC = rcp<C>(MC * inv_cs2s + C(0.5));
+                        pq = double(cq[0]) - double(wC) * (double(cq[0]) - (sC - (1.0 - SL::w(0)) * muC));
+                        if constexpr (!FEEDBACK) push(IC<HC0>{}, IC<0>{}, SLT{}, C(pq));
+                        keepC = C(1) - wC;
+                        wmuC = wC * C(muC);
+                        wcC = wC * C(sC) * inv_cs2s;
+                    }
                     static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
                         constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
@@ -1078,10 +1122,12 @@ k_lbm(const KParams P) {
                         const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
                         push_r(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu), resA);
                         push_r(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu), resB);
+                        if constexpr (NC3) push_r(IC<HC0 + k>{}, kc, SLT{}, keepC * cq[k] + wk * (wmuC + wcC * eu), resC);
                     });
                     if constexpr (FEEDBACK) {
                         push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(fb(IC<2>{}, resA))));
                         push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(fb(IC<3>{}, resB))));
+                        if constexpr (NC3) push(IC<HC0>{}, IC<0>{}, SLT{}, C(pq + double(fb(IC<4>{}, resC))));
                     }
                     }
                 }
@@ -1090,9 +1136,10 @@ k_lbm(const KParams P) {
                 // hydrodynamic pressure: p_h, or rho c_s^2 p* with variable density
                 const double p_out = VD ? double(p_h) / (3.0 * double(irho)) : double(p_h);
                 const double vals[kNumMom] = {m.phi, sA, sB, m.muA, m.muB, p_out,
-                                              double(u[0]), double(u[1]), double(u[2])};
+                                              double(u[0]), double(u[1]), double(u[2]), sC, muC};
+                constexpr int NMOM = NC3 ? kNumMom : kNumMom - 2;
 #pragma unroll
-                for (int i = 0; i < kNumMom; ++i) {
+                for (int i = 0; i < NMOM; ++i) {
                     if (P.mout[i]) {
                         if (P.mout_f32) static_cast<float*>(P.mout[i])[idx] = float(vals[i]);
                         else static_cast<double*>(P.mout[i])[idx] = vals[i];
@@ -1109,8 +1156,15 @@ k_lbm(const KParams P) {
                 acc[3] += 0.5 * (VD ? P.rho0 + P.drho * m.phi : P.rho0) * u2;
                 acc[4] = fmax(acc[4], sqrt(u2));
                 acc[5] += (4.0 / P.W) * m.phi * (1.0 - m.phi);
-                acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) + P.lam * bulk_free_energy<GK>(m.phi, m.muA, m.muB, P);
-                acc[7] += (isfinite(m.phi) && isfinite(sA) && isfinite(sB)) ? 0.0 : 1.0;
+                if constexpr (NC3) {
+                    acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) +
+                              P.lam * 0.5 * (m.muA * m.muA + m.muB * m.muB + muC * muC);
+                    acc[7] += (isfinite(m.phi) && isfinite(sA) && isfinite(sB) && isfinite(sC)) ? 0.0 : 1.0;
+                    acc[NACC - 1] += sC;
+                } else {
+                    acc[6] += 0.5 * P.W * P.W * g2 + dwell(m.phi) + P.lam * bulk_free_energy<GK>(m.phi, m.muA, m.muB, P);
+                    acc[7] += (isfinite(m.phi) && isfinite(sA) && isfinite(sB)) ? 0.0 : 1.0;
+                }
                 P.mask_out[idx] = m.phi >= 0.5 ? 1 : 0;
             }
         }
@@ -1119,14 +1173,18 @@ k_lbm(const KParams P) {
             if constexpr (!LDS_POPS) {
 #pragma unroll
                 for (int k = 0; k < QS; ++k) { cg[k] = ng[k]; ca[k] = na[k]; cb[k] = nb[k]; }
+                if constexpr (NC3) {
+#pragma unroll
+                    for (int k = 0; k < QS; ++k) cq[k] = nq[k];
+                }
             }
-            c_ps = n_ps; c_cA = n_cA; c_cB = n_cB;
+            c_ps = n_ps; c_cA = n_cA; c_cB = n_cB; c_cC = n_cC;
             __syncthreads();
         }
     }
 
     if constexpr (MODE == MODE_DIAG) {
-        block_reduce_store<8, NT>(acc, 4, P.partials + 8 * tile);
+        block_reduce_store<NACC, NT>(acc, 4, P.partials + NACC * tile);
     } else if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_PHI) {
         if (P.mean_subtract) block_reduce_store<1, NT>(acc, -1, P.partials + tile);
     }
@@ -1143,9 +1201,9 @@ k_lbm(const KParams P) {
 // wall node is visited by exactly one thread: the face of its lowest-index wall
 // axis.
 
-template <class SL, class FL, int PREC>
+template <class SL, class FL, int PREC, int NC = 2>
 __global__ void __launch_bounds__(256) k_walls(const KParams P, int axis) {
-    using SLOTS = Slots<FL::Q, SL::Q>;
+    using SLOTS = Slots<FL::Q, SL::Q, NC>;
     // enumerate the two faces of `axis`: (b, c) span the other two axes
     const int n[3] = {P.nx, P.ny, P.nz};
     const int ab = axis == 0 ? 1 : 0, ac = axis == 2 ? 1 : 2;
@@ -1204,8 +1262,9 @@ __global__ void __launch_bounds__(256) k_walls(const KParams P, int axis) {
         lattice(std::common_type<SL>{}, IC<SLOTS::G0>{});
         lattice(std::common_type<SL>{}, IC<SLOTS::A0>{});
         lattice(std::common_type<SL>{}, IC<SLOTS::B0>{});
+        if constexpr (NC >= 3) lattice(std::common_type<SL>{}, IC<SLOTS::C0>{});
     };
-    constexpr int NP = (FL::Q > 0 ? (FL::Q - 1) / 2 : 0) + 3 * ((SL::Q - 1) / 2);
+    constexpr int NP = (FL::Q > 0 ? (FL::Q - 1) / 2 : 0) + (1 + NC) * ((SL::Q - 1) / 2);
     // all loads first, then all stores: the round trips overlap
     Word va[NP], vb[NP];
     bool cr[NP];
@@ -1234,13 +1293,14 @@ __global__ void __launch_bounds__(256) k_walls(const KParams P, int axis) {
 // next step pulls X_k(x) from slot k at wrap(x - e_k).  The equilibrium X_k(x) is
 // therefore written to slot k at wrap(x - e_k).
 
-template <class SL, class FL, int PREC>
+template <class SL, class FL, int PREC, int NC = 2>
 __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __restrict__ phi0,
                                               const double* __restrict__ muA0,
-                                              const double* __restrict__ muB0) {
+                                              const double* __restrict__ muB0,
+                                              const double* __restrict__ muC0) {
     using C = typename Stor<PREC>::C;
-    using SLOTS = Slots<FL::Q, SL::Q>;
-    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0;
+    using SLOTS = Slots<FL::Q, SL::Q, NC>;
+    constexpr int G0 = SLOTS::G0, A0 = SLOTS::A0, B0 = SLOTS::B0, HC0 = SLOTS::C0;
     using STL = typename std::conditional<SL::DIM == 2, D2Q9K, D3Q19K>::type;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
@@ -1265,6 +1325,13 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
     }
     const double cA = P.init_c[0] ? P.init_c[0][idx] : kA + P.c0A + pp * (P.c1A - P.c0A);
     const double cB = P.init_c[1] ? P.init_c[1][idx] : kB + P.c0B + pp * (P.c1B - P.c0B);
+    // a third composition: the same closure, and its share of Delta omega
+    double muC = 0.0, cC = 0.0;
+    if constexpr (NC >= 3) {
+        muC = muC0[idx];
+        cC = P.init_c[2] ? P.init_c[2][idx] : muC + P.c0C + pp * (P.c1C - P.c0C);
+        domega -= muC * (P.c0C - P.c1C);
+    }
     const double S0 = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
 
     // returns the rounding residue (value - stored value); 16-bit storage adds the
@@ -1278,19 +1345,21 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
         return v - double(st_at_r<PREC, SLOTS::rest(S)>(slot, t, float(L::w(k)) * P.fref[F], P.fscale[F],
                                                          P.finv[F], C(v)));
     };
-    double rg = 0.0, ra = 0.0, rb = 0.0;
+    double rg = 0.0, ra = 0.0, rb = 0.0, rc = 0.0;
     static_for<1, SL::Q>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         constexpr double wk = SL::w(k);
         rg += put(IC<G0 + k>{}, kc, std::common_type<SL>{}, wk * phi - 0.5 * wk * S0);
         ra += put(IC<A0 + k>{}, kc, std::common_type<SL>{}, wk * muA);
         rb += put(IC<B0 + k>{}, kc, std::common_type<SL>{}, wk * muB);
+        if constexpr (NC >= 3) rc += put(IC<HC0 + k>{}, kc, std::common_type<SL>{}, wk * muC);
     });
     {
         constexpr double w0 = SL::w(0);
         put(IC<G0>{}, IC<0>{}, std::common_type<SL>{}, w0 * phi - 0.5 * w0 * S0 + rg);
         put(IC<A0>{}, IC<0>{}, std::common_type<SL>{}, cA - (1.0 - w0) * muA + ra);
         put(IC<B0>{}, IC<0>{}, std::common_type<SL>{}, cB - (1.0 - w0) * muB + rb);
+        if constexpr (NC >= 3) put(IC<HC0>{}, IC<0>{}, std::common_type<SL>{}, cC - (1.0 - w0) * muC + rc);
     }
     if constexpr (FL::Q > 0) {
         double grad[3] = {0.0, 0.0, 0.0}, lap = 0.0;
@@ -1326,10 +1395,10 @@ __global__ void __launch_bounds__(256) k_init(const KParams P, const double* __r
 // ---------------------------------------------------------------------------
 // canonical FP64 population access: X_k(x) lives in slot k at wrap(x - e_k)
 
-template <class SL, class FL, int PREC, bool SET>
+template <class SL, class FL, int PREC, bool SET, int NC = 2>
 __global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, double* __restrict__ buf) {
     using C = typename Stor<PREC>::C;
-    using SLOTS = Slots<FL::Q, SL::Q>;
+    using SLOTS = Slots<FL::Q, SL::Q, NC>;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nodes) return;
     const int x = int(i % P.nx), y = int((i / P.nx) % P.ny), z = int(i / ((long long)P.nx * P.ny));
@@ -1353,6 +1422,7 @@ __global__ void __launch_bounds__(256) k_pops(const KParams P, long long nodes, 
         one(IC<SLOTS::G0 + k>{}, kc, std::common_type<SL>{});
         one(IC<SLOTS::A0 + k>{}, kc, std::common_type<SL>{});
         one(IC<SLOTS::B0 + k>{}, kc, std::common_type<SL>{});
+        if constexpr (NC >= 3) one(IC<SLOTS::C0 + k>{}, kc, std::common_type<SL>{});
     });
 }
 
@@ -1752,8 +1822,9 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__
 }
 
 // final fixed-order reduction of per-work-group partials (one work-group).
-// partials are [nparts][N]; out[i] = scale[i] * reduce_i(partials[.][i])
-template <int N, bool ACC = false>
+// partials are [nparts][N]; out[i] = scale[i] * reduce_i(partials[.][i]), except that
+// the last entry goes to out[LAST_AT]
+template <int N, bool ACC = false, int LAST_AT = N - 1>
 __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nparts,
                                                   int maxslot, double scale0, double* __restrict__ out) {
     double acc[N];
@@ -1772,8 +1843,9 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const double v = (i == 0) ? res[i] * scale0 : res[i];
-            if constexpr (ACC) out[i] += v;
-            else out[i] = v;
+            const int o = (i == N - 1) ? LAST_AT : i;
+            if constexpr (ACC) out[o] += v;
+            else out[o] = v;
         }
     }
 }

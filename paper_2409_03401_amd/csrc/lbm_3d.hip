@@ -24,6 +24,9 @@ void launch_finalize(const double* partials, int nparts, int width, int maxslot,
                      double* out, hipStream_t s) {
     if (width == 1)
         hipLaunchKernelGGL((k_finalize<1>), dim3(1), dim3(256), 0, s, partials, nparts, maxslot, scale0, out);
+    else if (width == 9)
+        hipLaunchKernelGGL((k_finalize<9, false, 10>), dim3(1), dim3(256), 0, s, partials, nparts, maxslot, scale0,
+                           out);
     else
         hipLaunchKernelGGL((k_finalize<8>), dim3(1), dim3(256), 0, s, partials, nparts, maxslot, scale0, out);
 }

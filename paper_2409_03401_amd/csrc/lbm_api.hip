@@ -37,6 +37,7 @@ size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     const KernelSet* ks;
     int dim, qf, qs, nslots, prec;
+    int nc;  // independent compositions (2: the ternary fluid, 3: A, B, C)
     int NX, NY, NZ;  // kernel frame
     long long nodes;
     size_t slot_off[kMaxSlots];
@@ -141,6 +142,21 @@ int check_config(const lbm_config* c, Layout* L) {
         for (double v : {c->drho, c->g[0], c->g[1], c->g[2], c->sigma})
             if (!finite(v)) return fail(LBM_EINVAL, "flow parameters must be finite");
     }
+    if (c->ncomp != 0 && c->ncomp != 2 && c->ncomp != 3)
+        return fail(LBM_EUNSUPPORTED, "ncomp must be 0 or 2 (the ternary fluid) or 3 (a third composition)");
+    const int nc = c->ncomp == 3 ? 3 : 2;
+    if (nc == 3) {
+        for (int pi = 0; pi < 2; ++pi) {
+            if (!finite(c->c_eq_C[pi])) return fail(LBM_EINVAL, "c_eq_C must be finite");
+            if (!(c->M_C[pi] > 0)) return fail(LBM_EUNSTABLE, "M_C must be > 0 (rate outside (0, 2))");
+        }
+        if (c->store_shift_C < -30 || c->store_shift_C > 30)
+            return fail(LBM_EINVAL, "store_shift_C out of [-30, 30]");
+        if (trt || mrt || vd || gk)
+            return fail(LBM_EUNSUPPORTED, "a third composition runs with the BGK Boussinesq step");
+        if (paper_scalar)
+            return fail(LBM_EUNSUPPORTED, "a third composition runs on the D2Q5 / D3Q7 scalar lattices");
+    }
     if (c->precision >= LBM_FP32_FP16STORE)
         for (int i = 0; i < 4; ++i) {
             if (!finite(c->store_ref[i])) return fail(LBM_EINVAL, "store_ref must be finite");
@@ -153,7 +169,8 @@ int check_config(const lbm_config* c, Layout* L) {
     L->prec = c->precision;
     L->qf = c->fluid;
     L->qs = c->scalar;
-    L->nslots = L->qf + 3 * L->qs;
+    L->nc = nc;
+    L->nslots = L->qf + (1 + nc) * L->qs;
     L->nodes = nodes;
     if (L->dim == 2) {  // user (x, y) -> kernel (x, z)
         L->NX = c->nx; L->NY = 1; L->NZ = c->ny;
@@ -181,6 +198,9 @@ int check_config(const lbm_config* c, Layout* L) {
     if (mrt) {
         L->ks = L->dim == 2 ? kernels_mrt_2d(L->qs, L->qf, L->prec) : kernels_mrt_3d(L->qs, L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "no MRT kernel for this lattice / precision");
+    } else if (nc == 3) {
+        L->ks = L->dim == 2 ? kernels_nc3_2d(L->qf, L->prec) : kernels_nc3_3d(L->qf, L->prec);
+        if (!L->ks) return fail(LBM_EUNSUPPORTED, "no kernel with a third composition for this lattice / precision");
     } else if (gk) {
         L->ks = L->dim == 2 ? kernels_gk_2d(L->qs, L->qf, L->prec) : kernels_gk_3d(L->qs, L->qf, L->prec);
         if (!L->ks) return fail(LBM_EUNSUPPORTED, "no general_kappa kernel for this lattice / precision");
@@ -230,8 +250,9 @@ int check_config(const lbm_config* c, Layout* L) {
     L->grid = dim3(unsigned(gx * gy * gz));
     L->nparts = gx * gy * gz;
     // aux: kAuxHead doubles of scalars, then per-work-group partials (8 per group
-    // of the fused kernel, one per group of the Euler characteristic, <= 1024)
-    const long long npart_doubles = std::max<long long>(8 * L->nparts, 1024);
+    // of the fused kernel, 9 with a third composition; one per group of the Euler
+    // characteristic, <= 1024)
+    const long long npart_doubles = std::max<long long>((nc == 3 ? 9 : 8) * L->nparts, 1024);
     L->aux_bytes = round_up(sizeof(double) * (kAuxHead + npart_doubles));
     L->mask_off = 2 * L->copy_bytes + L->aux_bytes;
     L->state_bytes = L->mask_off + round_up((size_t)nodes);
@@ -322,6 +343,12 @@ void fill_params(lbm_handle* h) {
         kp.kap1[i] = c.general_kappa ? c.kappa[1][i] : (i == 1 ? 0.0 : 1.0);
     }
     kp.MA0 = c.M_A[0]; kp.MA1 = c.M_A[1]; kp.MB0 = c.M_B[0]; kp.MB1 = c.M_B[1];
+    if (L.nc == 3) {
+        kp.c0C = c.c_eq_C[0]; kp.c1C = c.c_eq_C[1];
+        kp.MC0 = c.M_C[0]; kp.MC1 = c.M_C[1];
+    }
+    kp.f32.MC0 = float(kp.MC0);
+    kp.f32.MC1 = float(kp.MC1);
     kp.nu0 = c.nu[0]; kp.nu1 = c.nu[1];
     kp.rho0 = L.qf ? c.rho0 : 1.0;
     kp.drho = c.drho;
@@ -345,10 +372,12 @@ void fill_params(lbm_handle* h) {
     kp.f32.MB0 = float(kp.MB0);
     kp.f32.MB1 = float(kp.MB1);
     const bool sixteen = L.prec == LBM_FP32_FP16STORE || L.prec == LBM_FP32_BF16STORE;
-    for (int f = 0; f < 4; ++f) {
-        // BF16 has the exponent range of FP32: its deviations are stored unscaled
-        const int sh = L.prec == LBM_FP32_FP16STORE ? c.store_shift[f] : 0;
-        kp.fref[f] = sixteen ? float(c.store_ref[f]) : 0.0f;
+    for (int f = 0; f < 5; ++f) {
+        // BF16 has the exponent range of FP32: its deviations are stored unscaled.
+        // Field 4 (h^C) takes reference 0, as h^A and h^B
+        const int shf = f < 4 ? c.store_shift[f] : (L.nc == 3 ? c.store_shift_C : 0);
+        const int sh = L.prec == LBM_FP32_FP16STORE ? shf : 0;
+        kp.fref[f] = (sixteen && f < 4) ? float(c.store_ref[f]) : 0.0f;
         kp.fscale[f] = std::ldexp(1.0f, sh);
         kp.finv[f] = std::ldexp(1.0f, -sh);
     }
@@ -395,15 +424,24 @@ namespace {
 
 int scratch_for_current_device(void** out);  // the scratch of lbm_adjoint_step_noalloc
 
-int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
-              const double* cA0, const double* cB0, const double* muA0, const double* muB0, void* stream,
-              lbm_handle** out) {
+// mu[a], c[a]: potential and (optional) composition of composition a (A, B, C)
+int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0, const double* const* c,
+              const double* const* mu, int nc_given, void* stream, lbm_handle** out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     Layout L;
     if (int r = check_config(cfg, &L)) return r;
-    if (!state || !phi0 || !muA0 || !muB0) return fail(LBM_EINVAL, "NULL device pointer");
-    if ((cA0 == nullptr) != (cB0 == nullptr)) return fail(LBM_EINVAL, "give both compositions or neither");
+    if (nc_given != L.nc)
+        return fail(LBM_EINVAL, L.nc == 3 ? "a configuration with ncomp = 3 is initialised with lbm_init_multi"
+                                          : "lbm_init_multi got a different number of compositions");
+    if (!state || !phi0) return fail(LBM_EINVAL, "NULL device pointer");
+    for (int a = 0; a < L.nc; ++a)
+        if (!mu[a]) return fail(LBM_EINVAL, "NULL device pointer");
+    for (int a = 1; a < L.nc; ++a)
+        if ((c[a] == nullptr) != (c[0] == nullptr)) return fail(LBM_EINVAL, "give every composition or none");
+    const double* cA0 = c[0];
+    const double* muA0 = mu[0];
+    const double* muB0 = mu[1];
     if ((reinterpret_cast<uintptr_t>(state) % kAlign) != 0)
         return fail(LBM_EINVAL, "state must be 256-byte aligned");
     if (state_bytes < L.state_bytes)
@@ -445,9 +483,8 @@ int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const doub
     }
     KParams kp = h->base;
     set_slots(h, kp, nullptr, h->copy[0]);
-    kp.init_c[0] = cA0;
-    kp.init_c[1] = cB0;
-    ks->init(kp, phi0, muA0, muB0, s);
+    for (int a = 0; a < L.nc; ++a) kp.init_c[a] = c[a];
+    ks->init(kp, phi0, muA0, muB0, L.nc == 3 ? mu[2] : nullptr, s);
     if (int r = launched("init kernel")) return bail(r);
     *out = h;
     return LBM_OK;
@@ -457,7 +494,25 @@ int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const doub
 
 int lbm_init(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
              const double* muA0, const double* muB0, void* stream, lbm_handle** out) {
-    return init_impl(cfg, state, state_bytes, phi0, nullptr, nullptr, muA0, muB0, stream, out);
+    const double* c[3] = {nullptr, nullptr, nullptr};
+    const double* mu[3] = {muA0, muB0, nullptr};
+    return init_impl(cfg, state, state_bytes, phi0, c, mu, 2, stream, out);
+}
+
+int lbm_init_multi(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
+                   const double* const* mu0, const double* const* c0, void* stream, lbm_handle** out) {
+    if (out) *out = nullptr;
+    if (!cfg) return fail(LBM_EINVAL, "config is NULL");
+    if (!mu0) return fail(LBM_EINVAL, "mu0 is NULL");
+    const int nc = cfg->ncomp == 3 ? 3 : 2;
+    const double* c[3] = {nullptr, nullptr, nullptr};
+    const double* mu[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < nc; ++a) {
+        mu[a] = mu0[a];
+        c[a] = c0 ? c0[a] : nullptr;
+        if (c0 && !c0[a]) return fail(LBM_EINVAL, "NULL device pointer");
+    }
+    return init_impl(cfg, state, state_bytes, phi0, c, mu, nc, stream, out);
 }
 
 int lbm_init_composition(const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0,
@@ -467,7 +522,9 @@ int lbm_init_composition(const lbm_config* cfg, void* state, size_t state_bytes,
         if (out) *out = nullptr;
         return fail(LBM_EINVAL, "NULL device pointer");
     }
-    return init_impl(cfg, state, state_bytes, phi0, cA0, cB0, muA0, muB0, stream, out);
+    const double* c[3] = {cA0, cB0, nullptr};
+    const double* mu[3] = {muA0, muB0, nullptr};
+    return init_impl(cfg, state, state_bytes, phi0, c, mu, 2, stream, out);
 }
 
 int lbm_step(lbm_handle* h, int64_t nsteps, void* stream) {
@@ -503,7 +560,11 @@ int lbm_moments(lbm_handle* h, uint32_t mask, void* const* out, int32_t out_dtyp
     KParams kp = h->base;
     set_slots(h, kp, h->copy[h->cur], nullptr);
     for (int i = 0; i < kNumMom; ++i) kp.mout[i] = nullptr;
+    if ((mask & (LBM_M_CC | LBM_M_MUC)) && h->L.nc != 3)
+        return fail(LBM_EINVAL, "LBM_M_CC / LBM_M_MUC need a third composition (ncomp = 3)");
     for (int i = 0; i < 6; ++i)
+        if (mask >> i & 1u) kp.mout[i] = out[i];
+    for (int i = 9; i < 11; ++i)
         if (mask >> i & 1u) kp.mout[i] = out[i];
     const size_t esize = out_dtype == LBM_OUT_F32 ? 4 : 8;
     if (h->L.dim == 3) {
@@ -554,7 +615,8 @@ int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream) {
     set_slots(h, kp, h->copy[h->cur], nullptr);
     kp.mask_out = h->mask;
     h->ks->fused(MODE_DIAG, h->L.grid, kp, s);
-    launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 8, 4, 1.0, h->aux + 8, s);
+    // 8 reductions (9 with a third composition: sum c^C goes to LBM_D_SUM_CC)
+    launch_finalize(h->aux + kAuxHead, int(h->L.nparts), h->L.nc == 3 ? 9 : 8, 4, 1.0, h->aux + 8, s);
     // droplet count: Euler characteristic of the cells with phi >= 1/2, over the
     // axes of the run (2D runs: user x and y; 3D runs with nz = 1 count as 2D)
     const EulerGeom g = euler_geometry(h);
@@ -562,7 +624,9 @@ int lbm_diagnostics(lbm_handle* h, double* host_out, void* stream) {
     launch_euler(h->mask, g, h->aux + kAuxHead, nb, s);
     launch_finalize(h->aux + kAuxHead, nb, 1, -1, 1.0, h->aux + 8 + LBM_D_DROPLETS, s);
     if (int r = launched("diagnostics kernels")) return r;
-    LBM_HIP(hipMemcpyAsync(host_out, h->aux + 8, LBM_D_MEAN_RADIUS * sizeof(double), hipMemcpyDeviceToHost, s));
+    // entries 0 .. LBM_NDIAG - 1 (the mean radius is set below; sum c^C stays 0 without
+    // a third composition: the aux head is zeroed at initialisation)
+    LBM_HIP(hipMemcpyAsync(host_out, h->aux + 8, LBM_NDIAG * sizeof(double), hipMemcpyDeviceToHost, s));
     LBM_HIP(hipStreamSynchronize(s));
     // mean radius from the interface integral I (Eq. Rmoy_2D, I = 2 pi N <R>; in 3D
     // spheres: I = 4 pi N <R>^2)

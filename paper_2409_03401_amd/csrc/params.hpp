@@ -9,8 +9,12 @@
 
 namespace lbm {
 
-constexpr int kMaxSlots = 19 + 3 * 19;  // D3Q19 fluid + 3 x D3Q19 scalars
-constexpr int kNumMom = 9;
+// D3Q19 fluid + 3 x D3Q19 scalars (the paper's lattices), or D3Q19 + 4 x D3Q7 (a third
+// composition on the reduced lattice)
+constexpr int kMaxSlots = 19 + 3 * 19;
+// moments written by the moments mode: phi, cA, cB, muA, muB, p, ux, uy, uz, then cC, muC
+// of a third composition (N components)
+constexpr int kNumMom = 11;
 constexpr int kNumDiag = 8;
 
 enum Prec : int { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
@@ -59,6 +63,9 @@ struct KParams {
     double kap0[3], kap1[3];
     int general_k;
     double MA0, MA1, MB0, MB1;   // species mobilities per phase
+    // a third independent composition C (N components; the kernels instantiated with
+    // three compositions use it): equilibrium compositions and mobilities per phase
+    double c0C, c1C, MC0, MC1;
     double nu0, nu1, rho0, drho;
     double gx, gy, gz;           // gravity in the kernel frame
     double cap;                  // 3/2 sigma W of Eq. SurfaceTension_Force
@@ -67,7 +74,7 @@ struct KParams {
     // FP32 copies of the constants the FP32 collision uses (one SGPR each, no
     // conversion in the loop)
     struct {
-        float cap, inv_W2, drho, gx, gy, gz, inv_rho0, rho0, nu0, nu1, omega_g, MA0, MA1, MB0, MB1;
+        float cap, inv_W2, drho, gx, gy, gz, inv_rho0, rho0, nu0, nu1, omega_g, MA0, MA1, MB0, MB1, MC0, MC1;
         float trt_lf, trt_ls, omega_gp;
         float mrt_f[3], mrt_s[3];
     } f32;
@@ -76,19 +83,21 @@ struct KParams {
     const char* src_base;
     char* dst_base;
     unsigned long long stride_m, stride_r;
-    // 16-bit storage per field (0 f, 1 g, 2 hA, 3 hB): moving population k is
+    // 16-bit storage per field (0 f, 1 g, 2 hA, 3 hB, 4 hC): moving population k is
     // value = w_k fref + d * finv, d = (value - w_k fref) * fscale
-    float fref[4], fscale[4], finv[4];
+    float fref[5], fscale[5], finv[5];
     // device scalars
     const double* phi_ref;       // buoyancy reference <phi> (aux area)
     double* partials;            // per-work-group partial sums
-    // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame)
+    // moments output (MODE_MOMENTS): phi, cA, cB, muA, muB, p, ux, uy, uz (kernel frame),
+    // then cC, muC of a third composition
     void* mout[kNumMom];
     int mout_f32;
     // MODE_DIAG: 1 where phi >= 1/2, else 0, one byte per node (kernel frame)
     unsigned char* mask_out;
-    // initialisation: given compositions c^A, c^B ([node]) instead of the closure, or null
-    const double* init_c[2];
+    // initialisation: given compositions c^A, c^B (, c^C) ([node]) instead of the closure,
+    // or null
+    const double* init_c[3];
     // adjoint kernels.  The adjoint of the arriving
     // population X_s(x) is lambda_s(x) plus, for a scalar population of field F
     // (g, h^A, h^B), the field-wide term c_F(x) (row F - 1 of auxc).  lambda is FP32

@@ -60,6 +60,33 @@ __device__ __forceinline__ Scalars node_scalars(double phis, double cA, double c
     return s;
 }
 
+// Three independent compositions (N components, the conclusion's extension with the
+// quadratic free energies of Eq. Taylor): the same closure per composition, and
+// Delta omega = -sum_alpha mu_alpha (c_0 - c_1)_alpha over A, B, C.
+struct Scalars3 {
+    double phi, muA, muB, muC, S;
+};
+
+__device__ __forceinline__ void potentials_and_source3(double phi, double cA, double cB, double cC,
+                                                       const KParams& P, double& muA, double& muB,
+                                                       double& muC, double& S) {
+    const double pp = interp_p(phi);
+    muA = cA - P.c0A - pp * (P.c1A - P.c0A);
+    muB = cB - P.c0B - pp * (P.c1B - P.c0B);
+    muC = cC - P.c0C - pp * (P.c1C - P.c0C);
+    const double domega = -(muA * (P.c0A - P.c1A) + muB * (P.c0B - P.c1B) + muC * (P.c0C - P.c1C));
+    S = P.mphi_w2 * (P.lam * interp_dp(phi) * domega - dwell_d(phi));
+}
+
+__device__ __forceinline__ Scalars3 node_scalars3(double phis, double cA, double cB, double cC, const KParams& P) {
+    Scalars3 s;
+    double muA, muB, muC, S;
+    potentials_and_source3(phis, cA, cB, cC, P, muA, muB, muC, S);
+    s.phi = phis + 0.5 * S;
+    potentials_and_source3(s.phi, cA, cB, cC, P, s.muA, s.muB, s.muC, s.S);
+    return s;
+}
+
 // bulk free-energy density above the reference, in units of K: |mu|^2 / 2, or
 // 1/2 mu . kappa(phi) mu with general curvatures
 template <bool GK = false>

@@ -26,9 +26,12 @@ LBM_FP64, LBM_FP32, LBM_FP32_FP16STORE, LBM_FP32_BF16STORE = 0, 1, 2, 3
 LBM_OUT_F64, LBM_OUT_F32 = 0, 1
 LBM_BGK, LBM_TRT, LBM_MRT = 0, 1, 2
 _COLLISION = {"BGK": LBM_BGK, "TRT": LBM_TRT, "MRT": LBM_MRT}
-MOMENTS = ("phi", "cA", "cB", "muA", "muB", "p", "ux", "uy", "uz")
+# moments in the order of the LBM_M_* bits; cC, muC exist with a third composition
+MOMENTS = ("phi", "cA", "cB", "muA", "muB", "p", "ux", "uy", "uz", "cC", "muC")
+TERNARY_MOMENTS = MOMENTS[:9]
+# diagnostics in the order of the LBM_D_* indices; sum_cC exists with a third composition
 DIAGNOSTICS = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interface_measure",
-               "free_energy", "nan_count", "droplets", "mean_radius")
+               "free_energy", "nan_count", "droplets", "mean_radius", "sum_cC")
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP32_FP16STORE, "bf16": LBM_FP32_BF16STORE}
 _FLUID = {None: LBM_NONE, "none": LBM_NONE, "D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
 # D2Q5 / D3Q7: reduced scalar lattices; D2Q9 / D3Q19: the paper's
@@ -56,8 +59,10 @@ class _Config(ctypes.Structure):
         ("sigma", ctypes.c_double), ("nu", ctypes.c_double * 2),
         ("store_ref", ctypes.c_double * 4), ("store_shift", ctypes.c_int32 * 4),
         ("collision", ctypes.c_int32), ("variable_density", ctypes.c_int32), ("trt_magic", ctypes.c_double * 2),
-        ("general_kappa", ctypes.c_int32), ("reserved", ctypes.c_int32), ("kappa", (ctypes.c_double * 3) * 2),
+        ("general_kappa", ctypes.c_int32), ("ncomp", ctypes.c_int32), ("kappa", (ctypes.c_double * 3) * 2),
         ("mrt_rates", (ctypes.c_double * 3) * 2),
+        ("c_eq_C", ctypes.c_double * 2), ("M_C", ctypes.c_double * 2),
+        ("store_shift_C", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -73,6 +78,9 @@ _SIGS = {
     "lbm_init_composition": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "lbm_init_multi": (ctypes.c_int, [ctypes.POINTER(_Config), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "lbm_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "lbm_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                                    ctypes.c_int32, ctypes.c_void_p]),
@@ -145,7 +153,11 @@ class LBMConfig:
     M_phi: float = 0.1
     M_A: Tuple[float, float] = (0.1, 0.1)
     M_B: Tuple[float, float] = (0.1, 0.1)
-    c_eq: Tuple[Tuple[float, float], Tuple[float, float]] = ((0.2, 0.1), (0.6, 0.3))
+    # c_eq[phase] = (c^A, c^B) for the paper's ternary fluid, or (c^A, c^B, c^C) with a
+    # third independent composition C (N components; needs M_C)
+    c_eq: Tuple[Tuple[float, ...], Tuple[float, ...]] = ((0.2, 0.1), (0.6, 0.3))
+    M_C: Optional[Tuple[float, float]] = None
+    store_shift_C: int = 6
     rho0: float = 1.0
     drho: float = 0.0
     g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
@@ -170,6 +182,11 @@ class LBMConfig:
     @property
     def nodes(self):
         return self.nx * self.ny * self.nz
+
+    @property
+    def ncomp(self):
+        """Independent compositions: 2 (A, B) or 3 (A, B, C)."""
+        return len(self.c_eq[0])
 
     @property
     def shape(self):
@@ -198,6 +215,16 @@ class LBMConfig:
             c.M_A[i], c.M_B[i], c.nu[i] = self.M_A[i], self.M_B[i], self.nu[i]
             for a in range(2):
                 c.c_eq[i][a] = self.c_eq[i][a]
+        if len(self.c_eq[0]) != len(self.c_eq[1]) or self.ncomp not in (2, 3):
+            raise ValueError("c_eq needs 2 or 3 compositions per phase, the same for both phases")
+        if (self.M_C is not None) != (self.ncomp == 3):
+            raise ValueError("a third composition takes c_eq entries and M_C together")
+        c.ncomp = self.ncomp
+        if self.ncomp == 3:
+            for i in range(2):
+                c.c_eq_C[i] = self.c_eq[i][2]
+                c.M_C[i] = self.M_C[i]
+            c.store_shift_C = int(self.store_shift_C)
         c.rho0, c.drho, c.sigma = self.rho0, self.drho, self.sigma
         for a in range(3):
             c.g[a] = self.g[a]
@@ -267,9 +294,10 @@ def _dev_f64(a, n, device):
 class Simulation:
     """One domain on one GPU: state buffer (torch uint8 tensor) plus the library handle."""
 
-    def __init__(self, cfg: LBMConfig, phi0, muA0, muB0, device="cuda", stream=None, c0=None):
+    def __init__(self, cfg: LBMConfig, phi0, muA0, muB0, device="cuda", stream=None, c0=None, mu_x0=()):
         """c0 = (cA0, cB0) gives the compositions instead of the closure
-        (lbm_init_composition: the initial condition of Section 4.2.1)."""
+        (lbm_init_composition: the initial condition of Section 4.2.1).  With a third
+        composition, mu_x0 = (muC0,) and c0 = (cA0, cB0, cC0) (lbm_init_multi)."""
         if not torch.cuda.is_available():
             raise RuntimeError("liblbm needs a GPU; none is visible")
         L = lib()
@@ -279,10 +307,24 @@ class Simulation:
         nbytes = state_bytes(cfg)
         self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         n = cfg.nodes
-        self._inputs = [_dev_f64(a, n, self.device) for a in (phi0, muA0, muB0)]
+        if len(mu_x0) != cfg.ncomp - 2:
+            raise ValueError(f"{cfg.ncomp} compositions need {cfg.ncomp - 2} entries in mu_x0")
+        self._inputs = [_dev_f64(a, n, self.device) for a in (phi0, muA0, muB0) + tuple(mu_x0)]
         ptrs = [ctypes.c_void_p(t.data_ptr()) for t in self._inputs]
         h = ctypes.c_void_p()
-        if c0 is None:
+        if cfg.ncomp != 2:
+            mu = (ctypes.c_void_p * cfg.ncomp)(*[p.value for p in ptrs[1:]])
+            cp = None
+            self._c_inputs = []
+            if c0 is not None:
+                if len(c0) != cfg.ncomp:
+                    raise ValueError(f"c0 needs {cfg.ncomp} compositions")
+                self._c_inputs = [_dev_f64(a, n, self.device) for a in c0]
+                cp = (ctypes.c_void_p * cfg.ncomp)(*[t.data_ptr() for t in self._c_inputs])
+            _check(L.lbm_init_multi(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes, ptrs[0],
+                                    mu, cp, _on(stream, self.state, *self._inputs, *self._c_inputs),
+                                    ctypes.byref(h)))
+        elif c0 is None:
             _check(L.lbm_init(ctypes.byref(self._c), ctypes.c_void_p(self.state.data_ptr()), nbytes,
                               *ptrs, _on(stream, self.state, *self._inputs), ctypes.byref(h)))
         else:
@@ -306,7 +348,7 @@ class Simulation:
 
     @property
     def nslots(self):
-        return self.cfg.qf + 3 * self.cfg.qs
+        return self.cfg.qf + (1 + self.cfg.ncomp) * self.cfg.qs
 
     def step(self, n=1, stream=None):
         _check(lib().lbm_step(self._h, int(n), _stream_ptr(stream)))
@@ -315,7 +357,15 @@ class Simulation:
     def step_count(self):
         return lib().lbm_step_count(self._h)
 
-    def moments(self, names: Sequence[str] = MOMENTS, dtype=torch.float64, stream=None) -> Dict[str, torch.Tensor]:
+    @property
+    def moment_names(self):
+        return MOMENTS if self.cfg.ncomp == 3 else TERNARY_MOMENTS
+
+    def moments(self, names: Optional[Sequence[str]] = None, dtype=torch.float64,
+                stream=None) -> Dict[str, torch.Tensor]:
+        """Fields named in `names` (default: every moment of this run)."""
+        if names is None:
+            names = self.moment_names
         out_dtype = LBM_OUT_F64 if dtype == torch.float64 else LBM_OUT_F32
         outs = {}
         ptrs = (ctypes.c_void_p * len(MOMENTS))()
@@ -332,10 +382,14 @@ class Simulation:
     def diagnostics(self, stream=None) -> Dict[str, float]:
         out = (ctypes.c_double * len(DIAGNOSTICS))()
         _check(lib().lbm_diagnostics(self._h, out, _stream_ptr(stream)))
-        d = dict(zip(DIAGNOSTICS, list(out)))
+        d = dict(zip(self.diagnostic_names, list(out)))
         for k in ("nan_count", "droplets"):  # integer counts (exact in FP64)
             d[k] = int(d[k])
         return d
+
+    @property
+    def diagnostic_names(self):
+        return DIAGNOSTICS if self.cfg.ncomp == 3 else DIAGNOSTICS[:-1]
 
     def run_series(self, steps: int, every: int, stream=None) -> Dict[str, np.ndarray]:
         """Advance `steps` steps recording the diagnostics every `every` steps (and of
@@ -348,7 +402,7 @@ class Simulation:
         start = self.step_count
         _check(lib().lbm_run_series(self._h, int(steps), int(every), out, _stream_ptr(stream)))
         a = np.frombuffer(out, dtype=np.float64).reshape(rows, len(DIAGNOSTICS)).copy()
-        d = {k: a[:, i] for i, k in enumerate(DIAGNOSTICS)}
+        d = {k: a[:, i] for i, k in enumerate(self.diagnostic_names)}
         for k in ("nan_count", "droplets"):
             d[k] = d[k].astype(np.int64)
         d["step"] = start + every * np.arange(rows, dtype=np.int64)
@@ -490,8 +544,8 @@ class PhaseFieldRun(torch.autograd.Function):
     def forward(ctx, phi0, theta, cfg, steps, muA0, muB0, segment=None):
         if cfg.precision not in ("fp32", "fp64") or cfg.gravity_mean_subtract:
             raise ValueError("the adjoint runs on fp32 or fp64 storage without gravity_mean_subtract")
-        if cfg.collision != "BGK" or cfg.variable_density or cfg.kappa is not None:
-            raise ValueError("the adjoint covers the paper's BGK Boussinesq model")
+        if cfg.collision != "BGK" or cfg.variable_density or cfg.kappa is not None or cfg.ncomp != 2:
+            raise ValueError("the adjoint covers the paper's BGK Boussinesq model of the ternary fluid")
         steps = int(steps)
         seg = int(segment) if segment else max(1, math.isqrt(max(steps - 1, 0)) + 1)
         c = with_theta(cfg, theta.detach().double().cpu().tolist())

@@ -30,16 +30,33 @@ def test_binding_covers_header():
     assert set(_declared()) <= set(lbm._SIGS)
 
 
-def test_struct_layout_matches_header():
-    # 11 int32 fields (dim first), padding, then doubles; store_shift, the collision
-    # fields and the TRT magic parameters close the struct
-    assert lbm._Config.dim.offset == 0 and lbm._Config.nx.offset == 4
-    assert lbm._Config.W.offset == 48
-    assert lbm._Config.collision.offset == lbm._Config.store_shift.offset + 16
-    assert lbm._Config.trt_magic.offset == lbm._Config.collision.offset + 8
-    assert lbm._Config.general_kappa.offset == lbm._Config.trt_magic.offset + 16
-    assert lbm._Config.mrt_rates.offset == lbm._Config.kappa.offset + 48
-    assert ctypes.sizeof(lbm._Config) == lbm._Config.mrt_rates.offset + 48
+def test_struct_layout_matches_header(tmp_path):
+    """Every field of the ctypes mirror sits at the offset the C compiler gives the
+    header's lbm_config, and the sizes agree."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in lbm._Config._fields_]
+    cname = {"lambda_": "lambda"}
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "lbm.h"', "int main(void) {"]
+    src.append('    printf("%zu\\n", sizeof(lbm_config));')
+    for f in fields:
+        src.append(f'    printf("%zu\\n", offsetof(lbm_config, {cname.get(f, f)}));')
+    src.append("    return 0;\n}")
+    (tmp_path / "layout.c").write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(tmp_path / "layout.c"), "-o", str(exe)],
+                   check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(lbm._Config)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(lbm._Config, f).offset == off, f
+    assert lbm._Config.dim.offset == 0
+
+
+C_EQ3 = ((0.2, 0.1, 0.15), (0.6, 0.3, 0.05))
 
 
 def _cfg(**kw):
@@ -82,6 +99,13 @@ def test_state_bytes_layout():
     (dict(kappa=((0.6, 0.0, 1.0), (1.0, 0.0, 1.0))), lbm.LBM_EUNSTABLE),  # D2Q5: below 1 - w_0 = 2/3
     (dict(collision="MRT", mrt_rates=((1.2, 2.0, 1.2), (1.0, 1.0, 1.0))), lbm.LBM_EUNSTABLE),
     (dict(collision="MRT", fluid="D2Q9", variable_density=True), lbm.LBM_EUNSUPPORTED),
+    # a third composition: BGK Boussinesq on the reduced lattices, positive mobilities
+    (dict(c_eq=C_EQ3, M_C=(0.1, 0.1), collision="TRT"), lbm.LBM_EUNSUPPORTED),
+    (dict(c_eq=C_EQ3, M_C=(0.1, 0.1), fluid="D2Q9", variable_density=True), lbm.LBM_EUNSUPPORTED),
+    (dict(c_eq=C_EQ3, M_C=(0.1, 0.1), kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0))), lbm.LBM_EUNSUPPORTED),
+    (dict(c_eq=C_EQ3, M_C=(0.1, 0.1), scalar="D2Q9"), lbm.LBM_EUNSUPPORTED),
+    (dict(c_eq=C_EQ3, M_C=(0.1, 0.0)), lbm.LBM_EUNSTABLE),
+    (dict(c_eq=((0.2, 0.1, float("nan")), (0.6, 0.3, 0.05)), M_C=(0.1, 0.1)), lbm.LBM_EINVAL),
 ])
 def test_config_errors(kw, code):
     with pytest.raises(lbm.LBMError) as e:
@@ -104,13 +128,54 @@ def test_dim_field_checked():
     assert _raw_config_error(lambda c: setattr(c, "dim", 4)) == lbm.LBM_EINVAL
 
 
+def test_ncomp_field_checked():
+    assert _raw_config_error(lambda c: setattr(c, "ncomp", 2)) == lbm.LBM_OK
+    assert _raw_config_error(lambda c: setattr(c, "ncomp", 1)) == lbm.LBM_EUNSUPPORTED
+    assert _raw_config_error(lambda c: setattr(c, "ncomp", 4)) == lbm.LBM_EUNSUPPORTED
+
+
+def test_third_composition_layout():
+    """Q_f + 4 Q_s slots with a third composition, at every storage precision."""
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        for kw in (dict(), dict(fluid="D2Q9"), dict(scalar="D3Q7", nz=3), dict(scalar="D3Q7", nz=3, fluid="D3Q19")):
+            c3 = _cfg(precision=prec, c_eq=C_EQ3, M_C=(0.1, 0.2), **kw)
+            c2 = _cfg(precision=prec, **kw)
+            q = c3.qs
+            bytes_m = 8 if prec == "fp64" else (4 if prec == "fp32" else 2)
+            moving = (c3.nodes * bytes_m + 255) // 256 * 256
+            rest = (c3.nodes * (8 if prec == "fp64" else 4) + 255) // 256 * 256
+            assert lbm.checkpoint_bytes(c3) - lbm.checkpoint_bytes(c2) == (q - 1) * moving + rest
+
+
+def test_init_rejects_mismatched_composition_count():
+    """lbm_init on a configuration with three compositions, and lbm_init_multi without
+    potentials, fail before any device work."""
+    c = _cfg(c_eq=C_EQ3, M_C=(0.1, 0.1))
+    n = lbm.state_bytes(c)
+    h = ctypes.c_void_p()
+    cfg = c.to_c()
+    fake = ctypes.c_void_p(256)  # never dereferenced
+    assert lbm.lib().lbm_init(ctypes.byref(cfg), fake, n, fake, fake, fake, None, ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert "lbm_init_multi" in lbm.lib().lbm_last_error().decode()
+    assert lbm.lib().lbm_init_multi(ctypes.byref(cfg), fake, n, fake, None, None, None, ctypes.byref(h)) \
+        == lbm.LBM_EINVAL
+    mu = (ctypes.c_void_p * 3)(256, 256, None)
+    assert lbm.lib().lbm_init_multi(ctypes.byref(cfg), fake, n, fake, mu, None, None, ctypes.byref(h)) \
+        == lbm.LBM_EINVAL
+    assert not h.value
+    with pytest.raises(ValueError):
+        _cfg(c_eq=C_EQ3).to_c()                       # M_C missing
+    with pytest.raises(ValueError):
+        _cfg(M_C=(0.1, 0.1)).to_c()                   # c_eq of the ternary fluid
+
+
 def test_composition_references_must_vanish():
     def nonzero_h_ref(c):
         c.store_ref[2] = 0.3
     assert _raw_config_error(nonzero_h_ref) == lbm.LBM_EINVAL
 
 
-SURVEY_BOUNDARY = {
+BOUNDARY_CALLS = {
     # the calls a user of the method makes, with their parameter lists
     "lbm_state_bytes": "const lbm_config* cfg, size_t* bytes",
     "lbm_init": "const lbm_config* cfg, void* state, size_t state_bytes, const double* phi0, const double* muA0, "
@@ -130,7 +195,7 @@ def test_boundary_calls_declared_and_exported():
     text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "lbm.h")).read(), flags=re.S)
     text = re.sub(r"\s+", " ", text)
     L = lbm.lib()
-    for name, params in SURVEY_BOUNDARY.items():
+    for name, params in BOUNDARY_CALLS.items():
         m = re.search(r"\b" + name + r"\(([^)]*)\);", text)
         assert m, name
         assert m.group(1).strip() == params, (name, m.group(1))
@@ -164,7 +229,8 @@ def test_init_composition_rejects_null_compositions():
 
 @pytest.mark.parametrize("kw", [dict(collision="TRT"), dict(collision="MRT"),
                                 dict(fluid="D2Q9", variable_density=True),
-                                dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0))), dict(precision="bf16")])
+                                dict(kappa=((1.0, 0.0, 1.0), (1.0, 0.0, 1.0))), dict(precision="bf16"),
+                                dict(c_eq=C_EQ3, M_C=(0.1, 0.1))])
 def test_phase_field_run_rejects_configurations_without_adjoint(kw):
     """The differentiable run covers the paper's BGK Boussinesq model at FP32 / FP64;
     other configurations fail before any device work."""
