@@ -252,8 +252,9 @@ int lbm_get_populations(lbm_handle* h, double* dst, void* stream);
 int lbm_set_populations(lbm_handle* h, const double* src, void* stream);
 
 /* Checkpoint / resume: byte copy of the current population copy plus the
- * buffered <phi> of the gravity reference.  restore(save(s)) continues
- * bitwise identically. */
+ * buffered <phi> of the gravity reference (the remaining bytes of the last 256
+ * are zero, as is the padding after each slot, so equal states give equal
+ * checkpoints byte for byte).  restore(save(s)) continues bitwise identically. */
 int lbm_save(lbm_handle* h, void* dst, void* stream);
 int lbm_restore(lbm_handle* h, const void* src, void* stream);
 

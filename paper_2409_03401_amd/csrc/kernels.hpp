@@ -268,6 +268,28 @@ __device__ __forceinline__ float st_at_res(char* slot, unsigned idx, float wref,
     return d - back;
 }
 
+// store a moving 16-bit population and return the stored deviation in the encoded
+// domain, round(d): the slot now decodes to w_k ref + round(d) 2^-s (FP16) or
+// w_k ref + round(d) (BF16)
+template <int PREC>
+__device__ __forceinline__ float st_at_dev(char* slot, unsigned idx, float wref, float scale, float v) {
+    static_assert(PREC == P16 || PREC == PB16, "16-bit formats only");
+    const float d = enc_d<PREC>(v, wref, scale);
+    unsigned short bits;
+    float back;
+    if constexpr (PREC == P16) {
+        const __half hd = __float2half_rn(d);
+        bits = __half_as_ushort(hd);
+        back = __half2float(hd);
+    } else {
+        const __bf16 bd = __bf16(d);  // round to nearest even
+        bits = __builtin_bit_cast(unsigned short, bd);
+        back = float(bd);
+    }
+    __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short*>(slot + idx * 2u));
+    return back;
+}
+
 // runtime-slot variants (generic copy kernels)
 template <int PREC>
 __device__ __forceinline__ typename Stor<PREC>::C ld_pop(const void* base, int idx, bool rest,
@@ -512,6 +534,20 @@ k_lbm(const KParams P) {
         if constexpr (PREC == P16) return res * P.finv[decltype(f_)::value];
         else return res;
     };
+    // store a 16-bit moving population and add its stored deviation (encoded domain) to dev
+    auto store_d = [&](auto s_, auto k_, auto lat_, unsigned idx, C v, C& dev) __attribute__((always_inline)) {
+        constexpr int S = decltype(s_)::value;
+        static_assert(!SLOTS::rest(S), "rest populations are stored as they are");
+        dev += st_at_dev<PREC>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[SLOTS::field(S)], v);
+    };
+    // sum of the stored moving populations of field F on lattice L, from the sum of their
+    // stored deviations: sum_{k != 0} w_k ref_F + dev 2^-s
+    auto stored_sum = [&](auto f_, auto lat_, C dev) __attribute__((always_inline)) -> C {
+        using L = typename decltype(lat_)::type;
+        constexpr int F = decltype(f_)::value;
+        if constexpr (F >= 2) return fb(f_, dev);
+        else return fb(f_, dev) + C(1.0 - L::w(0)) * P.fref[F];
+    };
 
     // scalar populations arriving at node idx (pull from idx - e_k; the node's own
     // opposite population where that crosses a z wall: zlo / zhi, wave-uniform)
@@ -533,18 +569,40 @@ k_lbm(const KParams P) {
                 if constexpr (NC3) qq[k] = load(IC<HC0 + k>{}, kc, SLT{}, src_idx);
             }
         });
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // zeroth moments.  mu = c - c^eq(phi) cancels c ~ 0.3 down to ~1e-3, so FP32
+        // partial sums over all populations (several roundings of c and phi each) would
+        // enter mu with a relative error near 1e-4 per step: FP32 / FP64 storage sums in
+        // FP64.  16-bit storage sums its moving populations in FP32 and adds the FP32
+        // rest population in FP64: the moving h are ~w_k mu (their FP32 sum is near
+        // exact) and the moving g carry 16-bit storage noise far above FP32 rounding
+        if constexpr (PREC == P16 || PREC == PB16) {
+            C m0 = gg[1], m1 = aa[1], m2 = bb[1], m3 = C(0);
+            if constexpr (NC3) m3 = qq[1];
 #pragma unroll
-        for (int k = 0; k < QS; ++k) {
-            s0 += double(gg[k]);
-            s1 += double(aa[k]);
-            s2 += double(bb[k]);
-            if constexpr (NC3) s3 += double(qq[k]);
+            for (int k = 2; k < QS; ++k) {
+                m0 += gg[k];
+                m1 += aa[k];
+                m2 += bb[k];
+                if constexpr (NC3) m3 += qq[k];
+            }
+            phis = double(gg[0]) + double(m0);
+            cA = double(aa[0]) + double(m1);
+            cB = double(bb[0]) + double(m2);
+            cC = NC3 ? double(qq[0]) + double(m3) : 0.0;
+        } else {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int k = 0; k < QS; ++k) {
+                s0 += double(gg[k]);
+                s1 += double(aa[k]);
+                s2 += double(bb[k]);
+                if constexpr (NC3) s3 += double(qq[k]);
+            }
+            phis = s0;
+            cA = s1;
+            cB = s2;
+            cC = s3;
         }
-        phis = s0;
-        cA = s1;
-        cB = s2;
-        cC = s3;
     };
     // phi of a node from its population sums (Eqs. Moment0_Phi, PotChem)
     auto phi_from = [&](double ps, double sa, double sb, double sc) __attribute__((always_inline)) -> double {
@@ -826,6 +884,14 @@ k_lbm(const KParams P) {
                     if constexpr (FEEDBACK) store_r(s_, k_, lat_, idx, v, res);
                     else store(s_, k_, lat_, idx, v);
                 };
+                // BGK steps: a moving population; with 16-bit storage its stored deviation
+                // adds to dev, and the rest population is stored last as the field's
+                // post-collision zeroth moment (conserved by the collision) minus the
+                // stored moving populations (stored_sum)
+                auto push_d = [&](auto s_, auto k_, auto lat_, C v, C& dev) __attribute__((always_inline)) {
+                    if constexpr (FEEDBACK) store_d(s_, k_, lat_, idx, v, dev);
+                    else store(s_, k_, lat_, idx, v);
+                };
 
                 // ---- f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq ----
                 // f* = (1 - w) f + w w_k [p + rho0 (eu + 3/2 eu^2 - uu/2)] + (1 - w/2) F_k,
@@ -878,21 +944,37 @@ k_lbm(const KParams P) {
                             });
                         if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, restm + fb(IC<0>{}, resm));
                     } else if constexpr (!TRTC) {
-                    C res = C(0), rest = C(0);
-                    static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                    // f*_k = keep f_k + w_k [a_k + gam_k (e_k . Fh - u . Fh)] with
+                    // a_k = wf (e0 + rho0 (eu + 3/2 eu^2)), gam_k = 1 + 3 eu + 9/2 eu^2 - 3/2 uu
+                    // and Fh = (1 - wf/2) F (times 1 / (rho c_s^2) with variable density):
+                    // k and opp(k) share eu^2 and differ in the signs of eu, e_k . Fh
+                    const C A = wf * e0, B = wf * rho0;
+                    const C hs = half * fsc;
+                    const C Fh[3] = {hs * F[0], hs * F[1], hs * F[2]};
+                    const C uFh = hs * uF;
+                    C dev = C(0);
+                    static_for<1, QF>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
-                        constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
-                        const C wk = C(FL::w(k));
-                        const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
-                        const C eF = edot<ex, ey, ez>(F[0], F[1], F[2]);
-                        const C gam = wk * (g0 + eu * (C(3) + C(4.5) * eu));
-                        const C Fk = VD ? gam * (eF - uF) * fsc : gam * (eF - uF);
-                        const C feq = wk * (e0 + rho0 * eu * (C(1) + C(1.5) * eu));
-                        const C v = keep * fpop[k] + wf * feq + half * Fk;
-                        if constexpr (k == 0 && FEEDBACK) rest = v;
-                        else push_r(kc, kc, FLT{}, v, res);
+                        constexpr int o = FL::opp(k);
+                        if constexpr (k < o) {
+                            constexpr int ex = FL::ex(k), ey = FL::ey(k), ez = FL::ez(k);
+                            const C wk = C(FL::w(k));  // w_opp(k) = w_k
+                            const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
+                            const C eF = edot<ex, ey, ez>(Fh[0], Fh[1], Fh[2]);
+                            const C e2 = eu * eu;
+                            const C q = C(1.5) * e2;
+                            const C r = g0 + C(4.5) * e2;
+                            const C ak = A + B * (q + eu), ao = A + B * (q - eu);
+                            const C gk = r + C(3) * eu, go = r - C(3) * eu;
+                            const C vk = keep * fpop[k] + wk * (ak + gk * (eF - uFh));
+                            const C vo = keep * fpop[o] + wk * (ao - go * (eF + uFh));
+                            push_d(kc, kc, FLT{}, vk, dev);
+                            push_d(IC<o>{}, IC<o>{}, FLT{}, vo, dev);
+                        }
                     });
-                    if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, rest + fb(IC<0>{}, res));
+                    // rest: Sum_k f*_k = p_h (the equilibrium keeps p_h, the forcing sums to 0)
+                    if constexpr (FEEDBACK) push(IC<0>{}, IC<0>{}, FLT{}, p_h - stored_sum(IC<0>{}, FLT{}, dev));
+                    else push(IC<0>{}, IC<0>{}, FLT{}, keep * fpop[0] + C(FL::w(0)) * (A - g0 * uFh));
                     } else {
                         // TRT: the viscosity sets the symmetric rate w+ = wf; w- from the
                         // magic parameter, 1/w- - 1/2 = Lambda_f / (1/wf - 1/2) = Lambda_f / (3 nu)
@@ -968,19 +1050,29 @@ k_lbm(const KParams P) {
                             });
                         if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, restm + fb(IC<1>{}, resm));
                     } else if constexpr (!TRTC) {
-                    C res = C(0), rest = C(0);
-                    static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
+                    // g*_k = keep g_k + w_k (t + c eu), t = w phi + (1 - w/2) S, c = w phi / c_s^2
+                    const C t = wphi + srcS, cu = wphi * inv_cs2s;
+                    C dev = C(0);
+                    static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
-                        constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
-                        const C wk = C(SL::w(k));
-                        C eq = wphi;
-                        if constexpr (ex != 0 || ey != 0 || ez != 0)
-                            eq = wphi * (C(1) + edot<ex, ey, ez>(u[0], u[1], u[2]) * inv_cs2s);
-                        const C v = keep * g[k] + wk * (eq + srcS);
-                        if constexpr (k == 0 && FEEDBACK) rest = v;
-                        else push_r(IC<G0 + k>{}, kc, SLT{}, v, res);
+                        constexpr int o = SL::opp(k);
+                        if constexpr (k < o) {
+                            constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                            const C wk = C(SL::w(k));
+                            const C ceu = cu * edot<ex, ey, ez>(u[0], u[1], u[2]);
+                            push_d(IC<G0 + k>{}, kc, SLT{}, keep * g[k] + wk * (t + ceu), dev);
+                            push_d(IC<G0 + o>{}, IC<o>{}, SLT{}, keep * g[o] + wk * (t - ceu), dev);
+                        }
                     });
-                    if constexpr (FEEDBACK) push(IC<G0>{}, IC<0>{}, SLT{}, rest + fb(IC<1>{}, res));
+                    // rest: Sum_k g*_k = (1 - w) phi* + w phi + (1 - w/2) S with phi* = Sum_k g_k
+                    // (phi = phi* + S*/2 takes the predictor's S*, the source the corrected S)
+                    if constexpr (FEEDBACK) {
+                        const double wgd = double(wg);
+                        const double mg = c_ps + wgd * (m.phi - c_ps) + (1.0 - 0.5 * wgd) * m.S;
+                        push(IC<G0>{}, IC<0>{}, SLT{}, C(mg) - stored_sum(IC<1>{}, SLT{}, dev));
+                    }
+                    else
+                        push(IC<G0>{}, IC<0>{}, SLT{}, keep * g[0] + C(SL::w(0)) * t);
                     } else {
                         // TRT: M_phi sets the antisymmetric rate w- = wg; w+ (uniform) from
                         // the magic parameter on the host.  Shifted equilibrium
@@ -1089,45 +1181,53 @@ k_lbm(const KParams P) {
                         push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(fb(IC<2>{}, resA))));
                         push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(fb(IC<3>{}, resB))));
                     } else {
-                    // rest populations in double: they carry the conserved composition
-                    const double whA = double(wA), whB = double(wB);
-                    const double eqA = sA - (1.0 - SL::w(0)) * m.muA;
-                    const double eqB = sB - (1.0 - SL::w(0)) * m.muB;
-                    const double pa = double(a[0]) - whA * (double(a[0]) - eqA);
-                    const double pb = double(b[0]) - whB * (double(b[0]) - eqB);
-                    if constexpr (!FEEDBACK) {
-                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa));
-                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb));
-                    }
+                    // BGK: h*_k = keep h_k + w_k (w mu + w c eu / c_s^2); k and opp(k) share w mu.
+                    // Rest populations in double (they carry the conserved composition): from
+                    // the collision with FP32 / FP64 storage, as c minus the stored moving
+                    // populations with 16-bit storage
                     const C keepA = C(1) - wA, keepB = C(1) - wB;
                     const C wmuA = wA * C(m.muA), wmuB = wB * C(m.muB);
                     const C wcA = wA * C(sA) * inv_cs2s, wcB = wB * C(sB) * inv_cs2s;
-                    C resA = C(0), resB = C(0);
+                    C devA = C(0), devB = C(0);
                     // a third composition: the same BGK relaxation with its own mobility
-                    C keepC = C(0), wmuC = C(0), wcC = C(0), resC = C(0);
-                    double pq = 0.0;
+                    C wC = C(0), keepC = C(0), wmuC = C(0), wcC = C(0), devC = C(0);
                     if constexpr (NC3) {
                         const C MC = KC(P.MC0, P.f32.MC0) * (C(1) - phi) + KC(P.MC1, P.f32.MC1) * phi;
-                        const C wC = rcp<C>(MC * inv_cs2s + C(0.5));
-                        pq = double(cq[0]) - double(wC) * (double(cq[0]) - (sC - (1.0 - SL::w(0)) * muC));
-                        if constexpr (!FEEDBACK) push(IC<HC0>{}, IC<0>{}, SLT{}, C(pq));
+                        wC = rcp<C>(MC * inv_cs2s + C(0.5));
                         keepC = C(1) - wC;
                         wmuC = wC * C(muC);
                         wcC = wC * C(sC) * inv_cs2s;
                     }
                     static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
                         constexpr int k = decltype(kc)::value;
-                        constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
-                        const C wk = C(SL::w(k));
-                        const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
-                        push_r(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu), resA);
-                        push_r(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu), resB);
-                        if constexpr (NC3) push_r(IC<HC0 + k>{}, kc, SLT{}, keepC * cq[k] + wk * (wmuC + wcC * eu), resC);
+                        constexpr int o = SL::opp(k);
+                        if constexpr (k < o) {
+                            constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
+                            const C wk = C(SL::w(k));  // w_opp(k) = w_k
+                            const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
+                            push_d(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu), devA);
+                            push_d(IC<A0 + o>{}, IC<o>{}, SLT{}, keepA * a[o] + wk * (wmuA - wcA * eu), devA);
+                            push_d(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu), devB);
+                            push_d(IC<B0 + o>{}, IC<o>{}, SLT{}, keepB * b[o] + wk * (wmuB - wcB * eu), devB);
+                            if constexpr (NC3) {
+                                push_d(IC<HC0 + k>{}, kc, SLT{}, keepC * cq[k] + wk * (wmuC + wcC * eu), devC);
+                                push_d(IC<HC0 + o>{}, IC<o>{}, SLT{}, keepC * cq[o] + wk * (wmuC - wcC * eu), devC);
+                            }
+                        }
                     });
                     if constexpr (FEEDBACK) {
-                        push(IC<A0>{}, IC<0>{}, SLT{}, C(pa + double(fb(IC<2>{}, resA))));
-                        push(IC<B0>{}, IC<0>{}, SLT{}, C(pb + double(fb(IC<3>{}, resB))));
-                        if constexpr (NC3) push(IC<HC0>{}, IC<0>{}, SLT{}, C(pq + double(fb(IC<4>{}, resC))));
+                        push(IC<A0>{}, IC<0>{}, SLT{}, C(sA - double(stored_sum(IC<2>{}, SLT{}, devA))));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, C(sB - double(stored_sum(IC<3>{}, SLT{}, devB))));
+                        if constexpr (NC3)
+                            push(IC<HC0>{}, IC<0>{}, SLT{}, C(sC - double(stored_sum(IC<4>{}, SLT{}, devC))));
+                    } else {
+                        const double w1 = 1.0 - SL::w(0);
+                        auto rest = [&](C h0, C w, double sc, double mu) __attribute__((always_inline)) -> C {
+                            return C(double(h0) - double(w) * (double(h0) - (sc - w1 * mu)));
+                        };
+                        push(IC<A0>{}, IC<0>{}, SLT{}, rest(a[0], wA, sA, m.muA));
+                        push(IC<B0>{}, IC<0>{}, SLT{}, rest(b[0], wB, sB, m.muB));
+                        if constexpr (NC3) push(IC<HC0>{}, IC<0>{}, SLT{}, rest(cq[0], wC, sC, muC));
                     }
                     }
                 }

@@ -474,6 +474,9 @@ int init_impl(const lbm_config* cfg, void* state, size_t state_bytes, const doub
     }
     if (hipMemsetAsync(h->aux, 0, kAuxHead * sizeof(double), s) != hipSuccess)
         return bail(fail(LBM_EHIP, "hipMemsetAsync of the aux area failed"));
+    // both population copies start zeroed: the padding after each slot is then zero for
+    // good (no kernel writes it), and so are the padding bytes of every checkpoint
+    launch_zero(reinterpret_cast<double*>(h->copy[0]), (long long)(2 * L.copy_bytes / sizeof(double)), s);
     if (cfg->gravity_mean_subtract) {
         // <phi_0> for the buoyancy reference of the first step
         const int nb = int(std::min<long long>(1024, (L.nodes + 255) / 256));
@@ -668,6 +671,23 @@ int lbm_set_populations(lbm_handle* h, const double* src, void* stream) {
     return launched("set_populations kernel");
 }
 
+namespace {
+
+// the bytes of a checkpoint after the buffered <phi>: zero, so that a checkpoint is a
+// function of the state alone (a fill kernel, not a memset: callers may capture it)
+int zero_tail(const lbm_handle* h, void* ckpt, hipStream_t s) {
+    char* tail = static_cast<char*>(ckpt) + h->L.copy_bytes + sizeof(double);
+    constexpr long long n = (kAlign - sizeof(double)) / sizeof(double);
+    if (reinterpret_cast<uintptr_t>(tail) % alignof(double) == 0) {
+        launch_zero(reinterpret_cast<double*>(tail), n, s);
+        return launched("checkpoint tail");
+    }
+    LBM_HIP(hipMemsetAsync(tail, 0, kAlign - sizeof(double), s));
+    return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_save(lbm_handle* h, void* dst, void* stream) {
     if (int r = check_handle(h)) return r;
     if (!dst) return fail(LBM_EINVAL, "dst is NULL");
@@ -675,7 +695,7 @@ int lbm_save(lbm_handle* h, void* dst, void* stream) {
     LBM_HIP(hipMemcpyAsync(dst, h->copy[h->cur], h->L.copy_bytes, hipMemcpyDeviceToDevice, s));
     LBM_HIP(hipMemcpyAsync(static_cast<char*>(dst) + h->L.copy_bytes, h->aux, sizeof(double),
                            hipMemcpyDeviceToDevice, s));
-    return LBM_OK;
+    return zero_tail(h, dst, s);
 }
 
 int lbm_restore(lbm_handle* h, const void* src, void* stream) {
@@ -716,7 +736,8 @@ int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, 
         if (walls[a]) h->ks->walls(kp, a, s);
     if (h->cfg.gravity_mean_subtract)
         launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
-    return launched("step_external kernels");
+    if (int r = launched("step_external kernels")) return r;
+    return zero_tail(h, dst, s);
 }
 
 int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream) {
