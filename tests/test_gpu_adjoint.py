@@ -20,6 +20,7 @@ FP64 storage; the bars below are stated per check.
 """
 
 import functools
+import os
 
 import numpy as np
 import pytest
@@ -340,6 +341,63 @@ def test_phase_field_run_gradients(kind, prec):
         print(f"  FD h=1e-3: dL/ds {fd_s:.8e} dL/dW {fd_W:.8e} dL/dphi0.v {fd_v:.8e}")
         for g, fd in ((g_s, fd_s), (g_W, fd_W), (g_v, fd_v)):
             assert abs(g - fd) <= 1e-3 * abs(fd) + 1e-9 * L0
+
+
+GOLDEN_LONG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_crop4096_oracle.npz")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_phase_field_run_gradients_long(prec):
+    """T = 4096 on the 64 x 64 crop: dL/ds, dL/dW and dL/dphi_0 . v through
+    PhaseFieldRun against the oracle's complex-step derivatives through the whole run
+    (stored by tests/golden/make_adjoint_crop4096.py) and, in FP64, against central
+    differences of the GPU forward (h = 1e-3).  The adjoint populations are FP32, so
+    the bars are wider than at T = 256: 1e-4 relative in FP64 storage, 1e-2 in FP32
+    storage (whose forward trajectory itself departs from the oracle's)."""
+    _require_gpu()
+    from paper_2409_03401_amd.lbm import Simulation, phase_field_run, with_theta
+    g = np.load(GOLDEN_LONG)
+    steps = int(g["steps"])
+    w = inputs.single_drop_2d(n=64, R=12.0, centre=(32.0, 40.0, 0.0))
+    p = dict(w.params)
+    print(f"[adjoint long] {prec} T={steps}", flush=True)
+    cfg = gpu_config(p, prec)
+    dev = "cuda"
+    phi0_t = torch.tensor(w.phi0, dtype=torch.float64, device=dev, requires_grad=True)
+    W = torch.tensor(p["W"], dtype=torch.float64, requires_grad=True)
+    s = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    m0 = torch.tensor([p["M_phi"], *p["M_A"], *p["M_B"]], dtype=torch.float64)
+    theta = torch.cat([s * m0, W.reshape(1)])
+    tgt = torch.tensor(g["target"], dtype=torch.float64, device=dev)
+    phiT = phase_field_run(phi0_t, theta, cfg, steps, w.muA0, w.muB0)
+    loss = ((phiT - tgt) ** 2).sum()
+    loss.backward()
+    v = g["v"]
+    got = {"s": float(s.grad), "W": float(W.grad), "v": float(np.sum(phi0_t.grad.cpu().numpy() * v))}
+    ref = {"s": float(g["dL_ds"]), "W": float(g["dL_dW"]), "v": float(g["dL_dv"])}
+    L0 = float(g["loss"])
+    print(f"  loss gpu {float(loss.detach()):.8e} oracle {L0:.8e}", flush=True)
+    bar = 1e-4 if prec == "fp64" else 1e-2
+    for k in ("s", "W", "v"):
+        rel = abs(got[k] - ref[k]) / abs(ref[k])
+        print(f"  dL/d{k}: gpu {got[k]:.8e} oracle (complex step) {ref[k]:.8e} rel err {rel:.2e}", flush=True)
+        assert rel <= bar, (k, rel)
+    if prec == "fp64":
+        def gpu_loss(c, ph):
+            sim = Simulation(c, ph, w.muA0, w.muB0)
+            sim.step(steps)
+            return float(((sim.moments(["phi"])["phi"] - tgt) ** 2).sum())
+
+        h = 1e-3
+        fd = {"W": (gpu_loss(with_theta(cfg, [*m0.tolist(), p["W"] + h]), w.phi0) -
+                    gpu_loss(with_theta(cfg, [*m0.tolist(), p["W"] - h]), w.phi0)) / (2 * h),
+              "s": (gpu_loss(with_theta(cfg, [*(m0 * (1 + h)).tolist(), p["W"]]), w.phi0) -
+                    gpu_loss(with_theta(cfg, [*(m0 * (1 - h)).tolist(), p["W"]]), w.phi0)) / (2 * h),
+              "v": (gpu_loss(cfg, w.phi0 + h * v) - gpu_loss(cfg, w.phi0 - h * v)) / (2 * h)}
+        for k in ("s", "W", "v"):
+            rel = abs(got[k] - fd[k]) / abs(fd[k])
+            print(f"  dL/d{k}: central difference of the GPU forward {fd[k]:.8e} rel err {rel:.2e}", flush=True)
+            assert rel <= 1e-3, (k, rel)
 
 
 def test_boundary_calls_gradient():
