@@ -7,6 +7,8 @@
   Compos_Init have mean c_g exactly, whatever the droplet field.
 - The placement of Fig. initialization_flowchart: every accepted droplet keeps the
   clearances of the caption, and the accepted volume just reaches the target.
+- The stored oracle run from a supersaturated start (tests/golden/ripening64_oracle.npz):
+  its droplets survive and grow.
 """
 
 import math
@@ -84,3 +86,19 @@ def test_paper_ripening_workload_recipe():
     assert abs(w.c0[0].mean() - 0.31) < 1e-14 and abs(w.c0[1].mean() - 0.31) < 1e-14
     assert 0.07 < float((w.phi0 >= 0.5).mean()) < 0.09
     assert np.all(w.muA0 == 0) and np.all(w.muB0 == 0)
+
+
+def test_stored_supersaturated_run_grows_its_droplets():
+    """The oracle run stored for the long-horizon GPU test: droplets present at every
+    stored step, no non-finite node, and a mean radius that grows out of the
+    supersaturated matrix (later steps above the first)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ripening64_oracle.npz")
+    g = np.load(path)
+    names = ("sum_cA", "sum_cB", "sum_phi", "kinetic_energy", "max_u", "interface_measure", "free_energy",
+             "nan_count", "droplets", "mean_radius")
+    steps = [int(s) for s in g["steps"] if f"diag_{int(s)}" in g]
+    assert steps
+    d = [dict(zip(names, g[f"diag_{s}"])) for s in steps]
+    assert all(x["droplets"] > 0 and x["nan_count"] == 0 for x in d)
+    assert all(x["mean_radius"] > d[0]["mean_radius"] for x in d[1:])
