@@ -161,7 +161,8 @@ typedef struct lbm_config {
     double store_ref[4];       /* 16-bit storage: reference per field f, g, hA, hB:
                                   moving population k is stored as the deviation
                                   x - w_k store_ref[F], rounded to nearest even;
-                                  hA, hB must be 0 (w_k mu is near zero)            */
+                                  hA, hB must be 0 (w_k mu is near zero), and so
+                                  must f with BF16 storage                          */
     int32_t store_shift[4];    /* FP16 storage: the deviation is scaled by
                                   2^store_shift[F] before rounding (FP16's range);
                                   BF16 (FP32's exponent range) ignores it           */

@@ -8,6 +8,7 @@ paper_2409_03401_amd/liblbm.so.  Cross-compiles without a GPU.
 
 import os
 import subprocess
+import tempfile
 import sys
 import time
 
@@ -48,10 +49,14 @@ def build(verbose: bool = False, out: str = OUT, extra_flags=()) -> str:
     running = []
     failed = []
 
+    # each compiler writes its messages to a file of its own: a pipe read only after the
+    # compiler exits would block it once the messages fill the pipe buffer
     def reap(entry):
-        src, p = entry
-        raw, _ = p.communicate()
-        text = raw.decode(errors="replace")
+        src, p, log = entry
+        p.wait()
+        log.seek(0)
+        text = log.read().decode(errors="replace")
+        log.close()
         if p.returncode != 0:
             failed.append((src, text))
         elif verbose and text.strip():
@@ -66,7 +71,8 @@ def build(verbose: bool = False, out: str = OUT, extra_flags=()) -> str:
             cmd = [HIPCC, *CFLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            running.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+            log = tempfile.TemporaryFile()
+            running.append((src, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
         done = [e for e in running if e[1].poll() is not None]
         if not done:
             time.sleep(0.2)

@@ -268,25 +268,29 @@ __device__ __forceinline__ float st_at_res(char* slot, unsigned idx, float wref,
     return d - back;
 }
 
-// store a moving 16-bit population and return the stored deviation in the encoded
-// domain, round(d): the slot now decodes to w_k ref + round(d) 2^-s (FP16) or
-// w_k ref + round(d) (BF16)
+// store two moving 16-bit populations of one field (slots sa, sb at node idx, the same
+// reference w_k ref) with one packed conversion (round to nearest even); returns the sum
+// of their stored deviations in the encoded domain
 template <int PREC>
-__device__ __forceinline__ float st_at_dev(char* slot, unsigned idx, float wref, float scale, float v) {
+__device__ __forceinline__ float st2_at_dev(char* sa, char* sb, unsigned idx, float wref, float scale, float va,
+                                            float vb) {
     static_assert(PREC == P16 || PREC == PB16, "16-bit formats only");
-    const float d = enc_d<PREC>(v, wref, scale);
-    unsigned short bits;
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 d = {enc_d<PREC>(va, wref, scale), enc_d<PREC>(vb, wref, scale)};
+    unsigned bits;
     float back;
     if constexpr (PREC == P16) {
-        const __half hd = __float2half_rn(d);
-        bits = __half_as_ushort(hd);
-        back = __half2float(hd);
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        const h2 r = __builtin_convertvector(d, h2);
+        bits = __builtin_bit_cast(unsigned, r);
+        back = float(r.x) + float(r.y);
     } else {
-        const __bf16 bd = __bf16(d);  // round to nearest even
-        bits = __builtin_bit_cast(unsigned short, bd);
-        back = float(bd);
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+        bits = __builtin_bit_cast(unsigned, __builtin_convertvector(d, b2));
+        back = __builtin_bit_cast(float, bits << 16) + __builtin_bit_cast(float, bits & 0xffff0000u);
     }
-    __builtin_nontemporal_store(bits, reinterpret_cast<unsigned short*>(slot + idx * 2u));
+    __builtin_nontemporal_store((unsigned short)(bits & 0xffffu), reinterpret_cast<unsigned short*>(sa + idx * 2u));
+    __builtin_nontemporal_store((unsigned short)(bits >> 16), reinterpret_cast<unsigned short*>(sb + idx * 2u));
     return back;
 }
 
@@ -367,6 +371,9 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #endif
 #ifndef LBM_PHASES
 #define LBM_PHASES 0
+#endif
+#ifndef LBM_LATE_POPS
+#define LBM_LATE_POPS 0
 #endif
 // scheduling fence between phases of the collision (bounds register live ranges)
 #define LBM_FENCE()                                          \
@@ -498,12 +505,14 @@ k_lbm(const KParams P) {
         const unsigned long long b = reinterpret_cast<kslot*>(kargs + offsetof(KParams, dst_slot))[S];
         return (char*)(gmut*)b;
     };
-    // 16-bit reference w_k ref_field of slot S (direction k of lattice L)
-    // (zero for h^A, h^B, whose moving equilibria w_k mu are near zero)
+    // 16-bit reference w_k ref_field of slot S (direction k of lattice L): zero for the
+    // compositions (their moving equilibria w_k mu are near zero) and for f in BF16 (its
+    // deviations need no scale, and f ~ w_k p_h is centred on zero)
+    constexpr bool NOREF_F = PREC == PB16;
     auto wref = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {
         using L = typename decltype(lat_)::type;
         constexpr int F = SLOTS::field(decltype(s_)::value);
-        if constexpr (F >= 2) return 0.0f;
+        if constexpr (F >= 2 || (F == 0 && NOREF_F)) return 0.0f;
         else return float(L::w(decltype(k_)::value)) * P.fref[F];
     };
     auto load = [&](auto s_, auto k_, auto lat_, unsigned idx) __attribute__((always_inline)) -> C {
@@ -534,18 +543,12 @@ k_lbm(const KParams P) {
         if constexpr (PREC == P16) return res * P.finv[decltype(f_)::value];
         else return res;
     };
-    // store a 16-bit moving population and add its stored deviation (encoded domain) to dev
-    auto store_d = [&](auto s_, auto k_, auto lat_, unsigned idx, C v, C& dev) __attribute__((always_inline)) {
-        constexpr int S = decltype(s_)::value;
-        static_assert(!SLOTS::rest(S), "rest populations are stored as they are");
-        dev += st_at_dev<PREC>(dst(s_), idx, wref(s_, k_, lat_), P.fscale[SLOTS::field(S)], v);
-    };
     // sum of the stored moving populations of field F on lattice L, from the sum of their
     // stored deviations: sum_{k != 0} w_k ref_F + dev 2^-s
     auto stored_sum = [&](auto f_, auto lat_, C dev) __attribute__((always_inline)) -> C {
         using L = typename decltype(lat_)::type;
         constexpr int F = decltype(f_)::value;
-        if constexpr (F >= 2) return fb(f_, dev);
+        if constexpr (F >= 2 || (F == 0 && NOREF_F)) return fb(f_, dev);
         else return fb(f_, dev) + C(1.0 - L::w(0)) * P.fref[F];
     };
 
@@ -679,6 +682,24 @@ k_lbm(const KParams P) {
 
     // diagnostics: the kNumDiag reductions, then sum c^C with a third composition
     constexpr int NACC = (MODE == MODE_DIAG) ? (NC3 ? kNumDiag + 1 : kNumDiag) : 1;
+    // this node's scalar populations of plane z from the private LDS ring into registers.
+    // The step reads them only in the g and h collisions: with LATE_POPS they are read
+    // there, after the f collision, so they do not occupy registers across it
+    constexpr bool LATE_POPS = LBM_LATE_POPS && LDS_POPS && STENCIL && (MODE == MODE_STEP || MODE == MODE_STEP_PHI);
+    auto fetch_pops = [&](int zz) __attribute__((always_inline)) {
+        if constexpr (LDS_POPS && STENCIL) {
+            if (active) {
+                const int pb = (zz - z0) & 1;
+#pragma unroll
+                for (int k = 0; k < QS; ++k) {
+                    cg[k] = spop[pb][k][tid];
+                    ca[k] = spop[pb][QS + k][tid];
+                    cb[k] = spop[pb][2 * QS + k][tid];
+                    if constexpr (NC3) cq[k] = spop[pb][3 * QS + k][tid];
+                }
+            }
+        }
+    };
     double acc[NACC];
 #pragma unroll
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
@@ -744,18 +765,7 @@ k_lbm(const KParams P) {
             sp = (z - z0 + 2) % 3;
             fill_plane(z + 1, sp, (z - z0 + 1) & 1, n_ps, n_cA, n_cB, n_cC);
             __syncthreads();
-            if constexpr (LDS_POPS) {
-                if (active) {
-                    const int pb = (z - z0) & 1;
-#pragma unroll
-                    for (int k = 0; k < QS; ++k) {
-                        cg[k] = spop[pb][k][tid];
-                        ca[k] = spop[pb][QS + k][tid];
-                        cb[k] = spop[pb][2 * QS + k][tid];
-                        if constexpr (NC3) cq[k] = spop[pb][3 * QS + k][tid];
-                    }
-                }
-            }
+            if constexpr (LDS_POPS && !LATE_POPS) fetch_pops(z);
         } else {
             if (active) {
                 const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
@@ -884,13 +894,21 @@ k_lbm(const KParams P) {
                     if constexpr (FEEDBACK) store_r(s_, k_, lat_, idx, v, res);
                     else store(s_, k_, lat_, idx, v);
                 };
-                // BGK steps: a moving population; with 16-bit storage its stored deviation
-                // adds to dev, and the rest population is stored last as the field's
-                // post-collision zeroth moment (conserved by the collision) minus the
-                // stored moving populations (stored_sum)
-                auto push_d = [&](auto s_, auto k_, auto lat_, C v, C& dev) __attribute__((always_inline)) {
-                    if constexpr (FEEDBACK) store_d(s_, k_, lat_, idx, v, dev);
-                    else store(s_, k_, lat_, idx, v);
+                // BGK steps: the moving populations of directions k and opp(k) of one field
+                // (with 16-bit storage: one packed conversion; their stored deviations add to
+                // dev, and the rest population is stored last as the field's post-collision
+                // zeroth moment, conserved by the collision, minus the stored moving
+                // populations, stored_sum)
+                auto push_d2 = [&](auto sk_, auto so_, auto k_, auto o_, auto lat_, C vk, C vo, C& dev)
+                                   __attribute__((always_inline)) {
+                    if constexpr (FEEDBACK) {
+                        constexpr int F = SLOTS::field(decltype(sk_)::value);
+                        static_assert(F == SLOTS::field(decltype(so_)::value), "one field");
+                        dev += st2_at_dev<PREC>(dst(sk_), dst(so_), idx, wref(sk_, k_, lat_), P.fscale[F], vk, vo);
+                    } else {
+                        store(sk_, k_, lat_, idx, vk);
+                        store(so_, o_, lat_, idx, vo);
+                    }
                 };
 
                 // ---- f: Eqs. LBE_FluidFlow, ForcingTerm, GammaFunction, Feq ----
@@ -968,8 +986,7 @@ k_lbm(const KParams P) {
                             const C gk = r + C(3) * eu, go = r - C(3) * eu;
                             const C vk = keep * fpop[k] + wk * (ak + gk * (eF - uFh));
                             const C vo = keep * fpop[o] + wk * (ao - go * (eF + uFh));
-                            push_d(kc, kc, FLT{}, vk, dev);
-                            push_d(IC<o>{}, IC<o>{}, FLT{}, vo, dev);
+                            push_d2(kc, IC<o>{}, kc, IC<o>{}, FLT{}, vk, vo, dev);
                         }
                     });
                     // rest: Sum_k f*_k = p_h (the equilibrium keeps p_h, the forcing sums to 0)
@@ -1014,6 +1031,10 @@ k_lbm(const KParams P) {
                 }
 
                 LBM_FENCE();
+                if constexpr (LATE_POPS) {
+                    if constexpr (LBM_LATE_POPS > 1) __builtin_amdgcn_sched_barrier(0);
+                    fetch_pops(z);
+                }
                 // ---- g: Eqs. LBE_Phi, Geq, Source_LBE_Phi ----
                 // g* = (1 - w) g + w w_k phi (1 + eu / c_s^2) + (1 - w/2) w_k S
                 {
@@ -1060,8 +1081,8 @@ k_lbm(const KParams P) {
                             constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
                             const C wk = C(SL::w(k));
                             const C ceu = cu * edot<ex, ey, ez>(u[0], u[1], u[2]);
-                            push_d(IC<G0 + k>{}, kc, SLT{}, keep * g[k] + wk * (t + ceu), dev);
-                            push_d(IC<G0 + o>{}, IC<o>{}, SLT{}, keep * g[o] + wk * (t - ceu), dev);
+                            push_d2(IC<G0 + k>{}, IC<G0 + o>{}, kc, IC<o>{}, SLT{}, keep * g[k] + wk * (t + ceu),
+                                    keep * g[o] + wk * (t - ceu), dev);
                         }
                     });
                     // rest: Sum_k g*_k = (1 - w) phi* + w phi + (1 - w/2) S with phi* = Sum_k g_k
@@ -1205,14 +1226,14 @@ k_lbm(const KParams P) {
                             constexpr int ex = SL::ex(k), ey = SL::ey(k), ez = SL::ez(k);
                             const C wk = C(SL::w(k));  // w_opp(k) = w_k
                             const C eu = edot<ex, ey, ez>(u[0], u[1], u[2]);
-                            push_d(IC<A0 + k>{}, kc, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu), devA);
-                            push_d(IC<A0 + o>{}, IC<o>{}, SLT{}, keepA * a[o] + wk * (wmuA - wcA * eu), devA);
-                            push_d(IC<B0 + k>{}, kc, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu), devB);
-                            push_d(IC<B0 + o>{}, IC<o>{}, SLT{}, keepB * b[o] + wk * (wmuB - wcB * eu), devB);
-                            if constexpr (NC3) {
-                                push_d(IC<HC0 + k>{}, kc, SLT{}, keepC * cq[k] + wk * (wmuC + wcC * eu), devC);
-                                push_d(IC<HC0 + o>{}, IC<o>{}, SLT{}, keepC * cq[o] + wk * (wmuC - wcC * eu), devC);
-                            }
+                            push_d2(IC<A0 + k>{}, IC<A0 + o>{}, kc, IC<o>{}, SLT{}, keepA * a[k] + wk * (wmuA + wcA * eu),
+                                    keepA * a[o] + wk * (wmuA - wcA * eu), devA);
+                            push_d2(IC<B0 + k>{}, IC<B0 + o>{}, kc, IC<o>{}, SLT{}, keepB * b[k] + wk * (wmuB + wcB * eu),
+                                    keepB * b[o] + wk * (wmuB - wcB * eu), devB);
+                            if constexpr (NC3)
+                                push_d2(IC<HC0 + k>{}, IC<HC0 + o>{}, kc, IC<o>{}, SLT{},
+                                        keepC * cq[k] + wk * (wmuC + wcC * eu), keepC * cq[o] + wk * (wmuC - wcC * eu),
+                                        devC);
                         }
                     });
                     if constexpr (FEEDBACK) {

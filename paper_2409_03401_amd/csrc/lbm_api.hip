@@ -162,6 +162,8 @@ int check_config(const lbm_config* c, Layout* L) {
             if (!finite(c->store_ref[i])) return fail(LBM_EINVAL, "store_ref must be finite");
             if (i >= 2 && c->store_ref[i] != 0.0)
                 return fail(LBM_EINVAL, "store_ref of h^A, h^B must be 0 (their moving populations have no reference)");
+            if (i == 0 && c->precision == LBM_FP32_BF16STORE && c->store_ref[0] != 0.0)
+                return fail(LBM_EINVAL, "BF16 storage takes store_ref of f = 0 (f is stored as it is)");
             if (c->store_shift[i] < -30 || c->store_shift[i] > 30)
                 return fail(LBM_EINVAL, "store_shift out of [-30, 30]");
         }

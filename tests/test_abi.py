@@ -175,6 +175,18 @@ def test_composition_references_must_vanish():
     assert _raw_config_error(nonzero_h_ref) == lbm.LBM_EINVAL
 
 
+def test_bf16_f_reference_must_vanish():
+    """BF16 stores f as it is (the kernels take its reference as zero); FP16 keeps a
+    reference for f."""
+    def nonzero_f_ref(c):
+        c.store_ref[0] = 0.1
+    assert _raw_config_error(nonzero_f_ref) == lbm.LBM_EINVAL      # _raw_config_error uses BF16
+    c = _cfg(precision="fp16", fluid="D2Q9").to_c()
+    c.store_ref[0] = 0.1
+    n = ctypes.c_size_t()
+    assert lbm.lib().lbm_state_bytes(ctypes.byref(c), ctypes.byref(n)) == lbm.LBM_OK
+
+
 BOUNDARY_CALLS = {
     # the calls a user of the method makes, with their parameter lists
     "lbm_state_bytes": "const lbm_config* cfg, size_t* bytes",
