@@ -195,6 +195,19 @@ __device__ __forceinline__ typename Stor<PREC>::C ld_at(const char* slot, unsign
     }
 }
 
+// decode the low / high 16 bits of a word as a moving 16-bit population (the words of
+// the packed LDS ring); the same arithmetic as ld_at
+template <int PREC>
+__device__ __forceinline__ float dec_lo(unsigned w, float wref, float inv_scale) {
+    if constexpr (PREC == P16) return fmaf(__half2float(__ushort_as_half((unsigned short)(w & 0xffffu))), inv_scale, wref);
+    else return __builtin_bit_cast(float, w << 16) + wref;
+}
+template <int PREC>
+__device__ __forceinline__ float dec_hi(unsigned w, float wref, float inv_scale) {
+    if constexpr (PREC == P16) return fmaf(__half2float(__ushort_as_half((unsigned short)(w >> 16))), inv_scale, wref);
+    else return __builtin_bit_cast(float, w & 0xffff0000u) + wref;
+}
+
 // 16-bit encoding of one moving population: d = (v - w_k ref) 2^s in FP16, or v - w_k ref
 // in BF16 (its exponent range is FP32's, so it takes no scale), rounded to nearest even
 template <int PREC>
@@ -372,14 +385,21 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #ifndef LBM_PHASES
 #define LBM_PHASES 0
 #endif
-#ifndef LBM_LATE_POPS
-#define LBM_LATE_POPS 0
-#endif
+
 // scheduling fence between phases of the collision (bounds register live ranges)
 #define LBM_FENCE()                                          \
     do {                                                     \
         if constexpr (LBM_PHASES) __builtin_amdgcn_sched_barrier(0); \
     } while (0)
+
+// index of the pair (k, opp(k)), k < opp(k), among the moving directions of lattice L
+template <class L, int K>
+constexpr int pair_index() {
+    int n = 0;
+    for (int j = 1; j < K; ++j)
+        if (j < L::opp(j)) ++n;
+    return n;
+}
 
 // MRT relaxation of one field (the multiple-relaxation-time alternative to BGK):
 // n_k = X_k - eqs(k) to the moment basis, moment i times rate(i) / <M_i, M_i>, back
@@ -454,12 +474,21 @@ k_lbm(const KParams P) {
     // the private LDS ring of scalar populations, unless it would not leave room for
     // a second work-group per compute unit (the paper's D3Q19 scalar lattice)
     constexpr bool LDS_POPS = LBM_LDS_POPS && 2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024;
+    static_assert((QS - 1) % 2 == 0, "moving directions come in opposite pairs");
 
     __shared__ C sphi[NSLOT][LY][LX];
     // this thread's own scalar populations of the current and the next plane
-    // (thread-private ring of two planes, [plane][slot][thread], no barriers needed)
-    __shared__ C spop[(STENCIL && LDS_POPS) ? 2 : 1][(STENCIL && LDS_POPS) ? (1 + NC) * QS : 1]
-                     [(STENCIL && LDS_POPS) ? NT : 1];
+    // (thread-private ring of two planes, [plane][word][thread], no barriers needed).
+    // FP32 / FP64: one word per population.  16-bit storage (PACKED): per field, the
+    // FP32 rest population and the raw 16-bit moving populations of k and opp(k) packed
+    // in one 32-bit word: 12 LDS words per node and plane instead of 21 (29 KB per
+    // work-group instead of 48 KB; registers then bound the occupancy at three waves per
+    // SIMD)
+    constexpr bool PACKED = LDS_POPS && (PREC == P16 || PREC == PB16);
+    constexpr int NPAIR = (QS - 1) / 2;
+    constexpr int NWORD = PACKED ? (1 + NC) * (1 + NPAIR) : (1 + NC) * QS;
+    using W = typename std::conditional<PACKED, unsigned, C>::type;
+    __shared__ W spop[(STENCIL && LDS_POPS) ? 2 : 1][(STENCIL && LDS_POPS) ? NWORD : 1][(STENCIL && LDS_POPS) ? NT : 1];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
@@ -515,9 +544,16 @@ k_lbm(const KParams P) {
         if constexpr (F >= 2 || (F == 0 && NOREF_F)) return 0.0f;
         else return float(L::w(decltype(k_)::value)) * P.fref[F];
     };
+    // the reference a decode adds: a zero reference as -0.0, since x + (-0.0) = x folds away
+    // (x + 0.0 does not: it maps -0.0 to +0.0) and the encode's x - 0.0 folds as well
+    auto wref_dec = [&](auto s_, auto k_, auto lat_) __attribute__((always_inline)) -> float {
+        constexpr int F = SLOTS::field(decltype(s_)::value);
+        if constexpr (F >= 2 || (F == 0 && NOREF_F)) return -0.0f;
+        else return wref(s_, k_, lat_);
+    };
     auto load = [&](auto s_, auto k_, auto lat_, unsigned idx) __attribute__((always_inline)) -> C {
         constexpr int S = decltype(s_)::value;
-        return ld_at<PREC, SLOTS::rest(S)>(src(s_), idx, wref(s_, k_, lat_), P.finv[SLOTS::field(S)]);
+        return ld_at<PREC, SLOTS::rest(S)>(src(s_), idx, wref_dec(s_, k_, lat_), P.finv[SLOTS::field(S)]);
     };
     // fluid populations that arrive without an x shift are read by this work-group
     // only (no ring, no x neighbour shares their lines): streamed past the caches.
@@ -526,7 +562,7 @@ k_lbm(const KParams P) {
         constexpr int S = decltype(s_)::value;
         using L = typename decltype(lat_)::type;
         constexpr bool NT = LBM_NT_FLUID && SL::DIM == 3 && L::ex(decltype(k_)::value) == 0;
-        return ld_at<PREC, SLOTS::rest(S), NT>(src(s_), idx, wref(s_, k_, lat_), P.finv[SLOTS::field(S)]);
+        return ld_at<PREC, SLOTS::rest(S), NT>(src(s_), idx, wref_dec(s_, k_, lat_), P.finv[SLOTS::field(S)]);
     };
     auto store = [&](auto s_, auto k_, auto lat_, unsigned idx, C v) __attribute__((always_inline)) {
         constexpr int S = decltype(s_)::value;
@@ -550,6 +586,20 @@ k_lbm(const KParams P) {
         constexpr int F = decltype(f_)::value;
         if constexpr (F >= 2 || (F == 0 && NOREF_F)) return fb(f_, dev);
         else return fb(f_, dev) + C(1.0 - L::w(0)) * P.fref[F];
+    };
+
+    // FP32 sum of the moving populations of one field, in the order k1, opp(k1), k2,
+    // opp(k2), ... over k < opp(k) (16-bit storage; the packed LDS fill sums in this order)
+    auto moving_sum = [&](const auto& x) __attribute__((always_inline)) -> C {
+        C m = C(0);
+        static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value, o = SL::opp(k);
+            if constexpr (k < o) {
+                if constexpr (pair_index<SL, k>() == 0) m = x[k] + x[o];
+                else m = (m + x[k]) + x[o];
+            }
+        });
+        return m;
     };
 
     // scalar populations arriving at node idx (pull from idx - e_k; the node's own
@@ -579,19 +629,10 @@ k_lbm(const KParams P) {
         // rest population in FP64: the moving h are ~w_k mu (their FP32 sum is near
         // exact) and the moving g carry 16-bit storage noise far above FP32 rounding
         if constexpr (PREC == P16 || PREC == PB16) {
-            C m0 = gg[1], m1 = aa[1], m2 = bb[1], m3 = C(0);
-            if constexpr (NC3) m3 = qq[1];
-#pragma unroll
-            for (int k = 2; k < QS; ++k) {
-                m0 += gg[k];
-                m1 += aa[k];
-                m2 += bb[k];
-                if constexpr (NC3) m3 += qq[k];
-            }
-            phis = double(gg[0]) + double(m0);
-            cA = double(aa[0]) + double(m1);
-            cB = double(bb[0]) + double(m2);
-            cC = NC3 ? double(qq[0]) + double(m3) : 0.0;
+            phis = double(gg[0]) + double(moving_sum(gg));
+            cA = double(aa[0]) + double(moving_sum(aa));
+            cB = double(bb[0]) + double(moving_sum(bb));
+            cC = NC3 ? double(qq[0]) + double(moving_sum(qq)) : 0.0;
         } else {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
@@ -629,10 +670,56 @@ k_lbm(const KParams P) {
     // populations go to the private LDS ring entry `pbuf` when the node is inside.
     // A z wall plane takes the bounce-back pulls (a separate, uniform branch: the
     // interior planes keep the plain loads)
+    // PACKED: this node's own scalar populations into the LDS ring (per field: the FP32
+    // rest population, then the raw moving populations of k and opp(k) in one word) and
+    // their zeroth moments (the decoded moving populations summed as moving_sum does)
+    auto fill_packed = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, int pbuf, double& phis, double& cA,
+                           double& cB, double& cC) __attribute__((always_inline)) {
+        auto field = [&](auto b_, auto w0_, double& sum) __attribute__((always_inline)) {
+            constexpr int B = decltype(b_)::value;    // slot of the field's rest population
+            constexpr int W0 = decltype(w0_)::value;  // the field's first LDS word
+            constexpr int F = SLOTS::field(B);
+            const C r = load(IC<B>{}, IC<0>{}, SLT{}, idx);
+            spop[pbuf][W0][tid] = __builtin_bit_cast(unsigned, float(r));
+            auto bits = [&](auto k_) __attribute__((always_inline)) -> unsigned {
+                constexpr int kk = decltype(k_)::value, oo = SL::opp(kk);
+                const unsigned short* p;
+                if (zbounce<SL::ez(kk)>(zlo, zhi))
+                    p = reinterpret_cast<const unsigned short*>(src(IC<B + oo>{}) + idx * 2u);
+                else
+                    p = reinterpret_cast<const unsigned short*>(
+                        src(IC<B + kk>{}) + unsigned(int(idx) + pull_offset<SL::ex(kk), SL::ey(kk), SL::ez(kk)>(nb)) * 2u);
+                return *p;
+            };
+            C m = C(0);
+            static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
+                constexpr int k = decltype(kc)::value, o = SL::opp(k);
+                if constexpr (k < o) {
+                    constexpr int PI = pair_index<SL, k>();
+                    const unsigned w = bits(kc) | (bits(IC<o>{}) << 16);
+                    spop[pbuf][W0 + 1 + PI][tid] = w;
+                    const C dk = dec_lo<PREC>(w, wref_dec(IC<B + k>{}, kc, SLT{}), P.finv[F]);
+                    const C dd = dec_hi<PREC>(w, wref_dec(IC<B + o>{}, IC<o>{}, SLT{}), P.finv[F]);
+                    if constexpr (PI == 0) m = dk + dd;
+                    else m = (m + dk) + dd;
+                }
+            });
+            sum = double(r) + double(m);
+        };
+        field(IC<G0>{}, IC<0>{}, phis);
+        field(IC<A0>{}, IC<1 + NPAIR>{}, cA);
+        field(IC<B0>{}, IC<2 * (1 + NPAIR)>{}, cB);
+        if constexpr (NC3) field(IC<HC0>{}, IC<3 * (1 + NPAIR)>{}, cC);
+        else cC = 0.0;
+    };
+
     auto fill_body = [&](int zm, bool zlo, bool zhi, int slot, int pbuf, double& ps, double& cA, double& cB,
                          double& cC) __attribute__((always_inline)) {
         if (active) {
-            if constexpr (LDS_POPS) {
+            if constexpr (PACKED) {
+                fill_packed(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, pbuf, ps, cA, cB,
+                            cC);
+            } else if constexpr (LDS_POPS) {
                 C gg[QS], aa[QS], bb[QS], qq[QC];
                 load_scalars(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, gg, aa, bb,
                              qq, ps, cA, cB, cC);
@@ -682,12 +769,33 @@ k_lbm(const KParams P) {
 
     // diagnostics: the kNumDiag reductions, then sum c^C with a third composition
     constexpr int NACC = (MODE == MODE_DIAG) ? (NC3 ? kNumDiag + 1 : kNumDiag) : 1;
-    // this node's scalar populations of plane z from the private LDS ring into registers.
-    // The step reads them only in the g and h collisions: with LATE_POPS they are read
-    // there, after the f collision, so they do not occupy registers across it
-    constexpr bool LATE_POPS = LBM_LATE_POPS && LDS_POPS && STENCIL && (MODE == MODE_STEP || MODE == MODE_STEP_PHI);
+    // this node's scalar populations of plane z from the private LDS ring into registers
+    // (read right after the barrier: reading them only where the g and h collisions use
+    // them frees about 18 VGPRs but measured 17 % slower, the LDS latency exposed)
     auto fetch_pops = [&](int zz) __attribute__((always_inline)) {
-        if constexpr (LDS_POPS && STENCIL) {
+        if constexpr (PACKED && STENCIL) {
+            if (active) {
+                const int pb = (zz - z0) & 1;
+                auto field = [&](auto b_, auto w0_, C(&x)[QS]) __attribute__((always_inline)) {
+                    constexpr int B = decltype(b_)::value;
+                    constexpr int W0 = decltype(w0_)::value;
+                    constexpr int F = SLOTS::field(B);
+                    x[0] = __builtin_bit_cast(float, spop[pb][W0][tid]);
+                    static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
+                        constexpr int k = decltype(kc)::value, o = SL::opp(k);
+                        if constexpr (k < o) {
+                            const unsigned w = spop[pb][W0 + 1 + pair_index<SL, k>()][tid];
+                            x[k] = dec_lo<PREC>(w, wref_dec(IC<B + k>{}, kc, SLT{}), P.finv[F]);
+                            x[o] = dec_hi<PREC>(w, wref_dec(IC<B + o>{}, IC<o>{}, SLT{}), P.finv[F]);
+                        }
+                    });
+                };
+                field(IC<G0>{}, IC<0>{}, cg);
+                field(IC<A0>{}, IC<1 + NPAIR>{}, ca);
+                field(IC<B0>{}, IC<2 * (1 + NPAIR)>{}, cb);
+                if constexpr (NC3) field(IC<HC0>{}, IC<3 * (1 + NPAIR)>{}, cq);
+            }
+        } else if constexpr (LDS_POPS && STENCIL) {
             if (active) {
                 const int pb = (zz - z0) & 1;
 #pragma unroll
@@ -765,7 +873,7 @@ k_lbm(const KParams P) {
             sp = (z - z0 + 2) % 3;
             fill_plane(z + 1, sp, (z - z0 + 1) & 1, n_ps, n_cA, n_cB, n_cC);
             __syncthreads();
-            if constexpr (LDS_POPS && !LATE_POPS) fetch_pops(z);
+            if constexpr (LDS_POPS) fetch_pops(z);
         } else {
             if (active) {
                 const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
@@ -1031,10 +1139,6 @@ k_lbm(const KParams P) {
                 }
 
                 LBM_FENCE();
-                if constexpr (LATE_POPS) {
-                    if constexpr (LBM_LATE_POPS > 1) __builtin_amdgcn_sched_barrier(0);
-                    fetch_pops(z);
-                }
                 // ---- g: Eqs. LBE_Phi, Geq, Source_LBE_Phi ----
                 // g* = (1 - w) g + w w_k phi (1 + eu / c_s^2) + (1 - w/2) w_k S
                 {
