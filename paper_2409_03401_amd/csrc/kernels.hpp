@@ -385,6 +385,12 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], int maxslot, 
 #ifndef LBM_PHASES
 #define LBM_PHASES 0
 #endif
+#ifndef LBM_FLAT_FILL
+#define LBM_FLAT_FILL 1
+#endif
+#ifndef LBM_FRAW
+#define LBM_FRAW 1
+#endif
 
 // scheduling fence between phases of the collision (bounds register live ranges)
 #define LBM_FENCE()                                          \
@@ -604,24 +610,51 @@ k_lbm(const KParams P) {
 
     // scalar populations arriving at node idx (pull from idx - e_k; the node's own
     // opposite population where that crosses a z wall: zlo / zhi, wave-uniform)
-    auto load_scalars = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, C (&gg)[QS], C (&aa)[QS],
-                            C (&bb)[QS], C (&qq)[QC], double& phis, double& cA, double& cB, double& cC)
-                            __attribute__((always_inline)) {
+    // The scalar populations of a node in their stored form (RAW: 16-bit storage keeps
+    // the bits of the moving populations and of the FP32 rest population, decoded later;
+    // FP32 / FP64 the values), field-major: g, hA, hB (, hC), QS each
+    constexpr bool RAW16 = PREC == P16 || PREC == PB16;
+    constexpr int NSC = (1 + NC) * QS;
+    using RW = typename std::conditional<RAW16, unsigned, C>::type;
+    auto load_pops = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, RW (&raw)[NSC]) __attribute__((always_inline)) {
+        auto one = [&](auto s_, auto k_, unsigned t) __attribute__((always_inline)) -> RW {
+            constexpr int S = decltype(s_)::value;
+            if constexpr (!RAW16) return ld_at<PREC, SLOTS::rest(S)>(src(s_), t, 0.0f, 1.0f);
+            else if constexpr (SLOTS::rest(S)) return __builtin_bit_cast(unsigned, ld_at<PREC, true>(src(s_), t, 0.0f, 1.0f));
+            else return *reinterpret_cast<const unsigned short*>(src(s_) + t * 2u);
+        };
         static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value, o = SL::opp(k);
-            if (zbounce<SL::ez(k)>(zlo, zhi)) {
-                gg[k] = load(IC<G0 + o>{}, IC<o>{}, SLT{}, idx);
-                aa[k] = load(IC<A0 + o>{}, IC<o>{}, SLT{}, idx);
-                bb[k] = load(IC<B0 + o>{}, IC<o>{}, SLT{}, idx);
-                if constexpr (NC3) qq[k] = load(IC<HC0 + o>{}, IC<o>{}, SLT{}, idx);
-            } else {
-                const unsigned src_idx = unsigned(int(idx) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb));
-                gg[k] = load(IC<G0 + k>{}, kc, SLT{}, src_idx);
-                aa[k] = load(IC<A0 + k>{}, kc, SLT{}, src_idx);
-                bb[k] = load(IC<B0 + k>{}, kc, SLT{}, src_idx);
-                if constexpr (NC3) qq[k] = load(IC<HC0 + k>{}, kc, SLT{}, src_idx);
-            }
+            auto fields = [&](auto kk_, unsigned t) __attribute__((always_inline)) {
+                constexpr int kk = decltype(kk_)::value;
+                raw[k] = one(IC<G0 + kk>{}, kk_, t);
+                raw[QS + k] = one(IC<A0 + kk>{}, kk_, t);
+                raw[2 * QS + k] = one(IC<B0 + kk>{}, kk_, t);
+                if constexpr (NC3) raw[3 * QS + k] = one(IC<HC0 + kk>{}, kk_, t);
+            };
+            if (zbounce<SL::ez(k)>(zlo, zhi)) fields(IC<o>{}, idx);
+            else fields(kc, unsigned(int(idx) + pull_offset<SL::ex(k), SL::ey(k), SL::ez(k)>(nb)));
         });
+    };
+    // decoded values of one field (base slot B, first raw entry R0)
+    auto decode_field = [&](auto b_, const RW* raw, C (&x)[QS]) __attribute__((always_inline)) {
+        constexpr int B = decltype(b_)::value;
+        static_for<0, QS>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int k = decltype(kc)::value;
+            if constexpr (!RAW16) x[k] = raw[k];
+            else if constexpr (k == 0) x[0] = __builtin_bit_cast(float, raw[0]);
+            else x[k] = dec_lo<PREC>(raw[k], wref_dec(IC<B + k>{}, kc, SLT{}), P.finv[SLOTS::field(B)]);
+        });
+    };
+    auto decode_pops = [&](const RW (&raw)[NSC], C (&gg)[QS], C (&aa)[QS], C (&bb)[QS], C (&qq)[QC])
+                           __attribute__((always_inline)) {
+        decode_field(IC<G0>{}, raw, gg);
+        decode_field(IC<A0>{}, raw + QS, aa);
+        decode_field(IC<B0>{}, raw + 2 * QS, bb);
+        if constexpr (NC3) decode_field(IC<HC0>{}, raw + 3 * QS, qq);
+    };
+    auto pop_sums = [&](const C (&gg)[QS], const C (&aa)[QS], const C (&bb)[QS], const C (&qq)[QC], double& phis,
+                        double& cA, double& cB, double& cC) __attribute__((always_inline)) {
         // zeroth moments.  mu = c - c^eq(phi) cancels c ~ 0.3 down to ~1e-3, so FP32
         // partial sums over all populations (several roundings of c and phi each) would
         // enter mu with a relative error near 1e-4 per step: FP32 / FP64 storage sums in
@@ -648,6 +681,14 @@ k_lbm(const KParams P) {
             cC = s3;
         }
     };
+    auto load_scalars = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, C (&gg)[QS], C (&aa)[QS],
+                            C (&bb)[QS], C (&qq)[QC], double& phis, double& cA, double& cB, double& cC)
+                            __attribute__((always_inline)) {
+        RW raw[NSC];
+        load_pops(idx, nb, zlo, zhi, raw);
+        decode_pops(raw, gg, aa, bb, qq);
+        pop_sums(gg, aa, bb, qq, phis, cA, cB, cC);
+    };
     // phi of a node from its population sums (Eqs. Moment0_Phi, PotChem)
     auto phi_from = [&](double ps, double sa, double sb, double sc) __attribute__((always_inline)) -> double {
         if constexpr (NC3) return node_scalars3(ps, sa, sb, sc, P).phi;
@@ -670,33 +711,23 @@ k_lbm(const KParams P) {
     // populations go to the private LDS ring entry `pbuf` when the node is inside.
     // A z wall plane takes the bounce-back pulls (a separate, uniform branch: the
     // interior planes keep the plain loads)
-    // PACKED: this node's own scalar populations into the LDS ring (per field: the FP32
-    // rest population, then the raw moving populations of k and opp(k) in one word) and
-    // their zeroth moments (the decoded moving populations summed as moving_sum does)
-    auto fill_packed = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, int pbuf, double& phis, double& cA,
-                           double& cB, double& cC) __attribute__((always_inline)) {
-        auto field = [&](auto b_, auto w0_, double& sum) __attribute__((always_inline)) {
+    // PACKED: this node's own scalar populations (stored form) into the LDS ring (per
+    // field: the FP32 rest population, then the moving populations of k and opp(k) in one
+    // word) and their zeroth moments (the moving populations summed as moving_sum does)
+    auto finish_packed = [&](const RW (&raw)[NSC], int pbuf, double& phis, double& cA, double& cB, double& cC)
+                             __attribute__((always_inline)) {
+      if constexpr (PACKED) {
+        auto field = [&](auto b_, auto w0_, const RW* r, double& sum) __attribute__((always_inline)) {
             constexpr int B = decltype(b_)::value;    // slot of the field's rest population
             constexpr int W0 = decltype(w0_)::value;  // the field's first LDS word
             constexpr int F = SLOTS::field(B);
-            const C r = load(IC<B>{}, IC<0>{}, SLT{}, idx);
-            spop[pbuf][W0][tid] = __builtin_bit_cast(unsigned, float(r));
-            auto bits = [&](auto k_) __attribute__((always_inline)) -> unsigned {
-                constexpr int kk = decltype(k_)::value, oo = SL::opp(kk);
-                const unsigned short* p;
-                if (zbounce<SL::ez(kk)>(zlo, zhi))
-                    p = reinterpret_cast<const unsigned short*>(src(IC<B + oo>{}) + idx * 2u);
-                else
-                    p = reinterpret_cast<const unsigned short*>(
-                        src(IC<B + kk>{}) + unsigned(int(idx) + pull_offset<SL::ex(kk), SL::ey(kk), SL::ez(kk)>(nb)) * 2u);
-                return *p;
-            };
+            spop[pbuf][W0][tid] = r[0];
             C m = C(0);
             static_for<1, QS>([&](auto kc) __attribute__((always_inline)) {
                 constexpr int k = decltype(kc)::value, o = SL::opp(k);
                 if constexpr (k < o) {
                     constexpr int PI = pair_index<SL, k>();
-                    const unsigned w = bits(kc) | (bits(IC<o>{}) << 16);
+                    const unsigned w = r[k] | (r[o] << 16);
                     spop[pbuf][W0 + 1 + PI][tid] = w;
                     const C dk = dec_lo<PREC>(w, wref_dec(IC<B + k>{}, kc, SLT{}), P.finv[F]);
                     const C dd = dec_hi<PREC>(w, wref_dec(IC<B + o>{}, IC<o>{}, SLT{}), P.finv[F]);
@@ -704,17 +735,82 @@ k_lbm(const KParams P) {
                     else m = (m + dk) + dd;
                 }
             });
-            sum = double(r) + double(m);
+            sum = double(__builtin_bit_cast(float, r[0])) + double(m);
         };
-        field(IC<G0>{}, IC<0>{}, phis);
-        field(IC<A0>{}, IC<1 + NPAIR>{}, cA);
-        field(IC<B0>{}, IC<2 * (1 + NPAIR)>{}, cB);
-        if constexpr (NC3) field(IC<HC0>{}, IC<3 * (1 + NPAIR)>{}, cC);
+        field(IC<G0>{}, IC<0>{}, raw, phis);
+        field(IC<A0>{}, IC<1 + NPAIR>{}, raw + QS, cA);
+        field(IC<B0>{}, IC<2 * (1 + NPAIR)>{}, raw + 2 * QS, cB);
+        if constexpr (NC3) field(IC<HC0>{}, IC<3 * (1 + NPAIR)>{}, raw + 3 * QS, cC);
         else cC = 0.0;
+      }
+    };
+    auto fill_packed = [&](unsigned idx, const Nbr& nb, bool zlo, bool zhi, int pbuf, double& phis, double& cA,
+                           double& cB, double& cC) __attribute__((always_inline)) {
+        RW raw[NSC];
+        load_pops(idx, nb, zlo, zhi, raw);
+        finish_packed(raw, pbuf, phis, cA, cB, cC);
+    };
+
+    // 3D plane fill with one memory round trip: every lane loads its own node (lanes
+    // outside the domain an in-range stand-in) and one ring node (lanes beyond the ring
+    // repeat its last node) in one basic block, so that all loads go out together; only
+    // the waves that hold ring nodes decode them (a wave-uniform branch).  The stores
+    // need no conditions: a lane's private LDS ring entries and the phi cells of lanes
+    // outside the domain are never read, and a repeated ring node writes the same value
+    // to the same cell.
+    auto fill_body_flat = [&](int zm, bool zlo, bool zhi, int slot, int pbuf, double& ps, double& cA, double& cB,
+                              double& cC) __attribute__((always_inline)) {
+        constexpr int NH = 2 * LX + 2 * TY;
+        static_assert(NT % 64 == 0, "whole waves");
+        const int ox = map_coord(min(x, P.nx), P.nx, P.wall_x), oy = map_coord(min(y, P.ny), P.ny, P.wall_y);
+        const int i = min(tid, NH - 1);
+        int hx, hy;
+        if (i < LX) { hx = i; hy = 0; }
+        else if (i < 2 * LX) { hx = i - LX; hy = TY + 1; }
+        else if (i < 2 * LX + TY) { hx = 0; hy = i - 2 * LX + 1; }
+        else { hx = LX - 1; hy = i - 2 * LX - TY + 1; }
+        const int rx = map_coord(min(bx * TX + hx - 1, P.nx), P.nx, P.wall_x);
+        const int ry = map_coord(min(by * TY + hy - 1, P.ny), P.ny, P.wall_y);
+        RW own[NSC], ring[NSC];
+        load_pops(unsigned((zm * P.ny + oy) * P.nx + ox), neighbours(ox, oy, zm, P), zlo, zhi, own);
+        load_pops(unsigned((zm * P.ny + ry) * P.nx + rx), neighbours(rx, ry, zm, P), zlo, zhi, ring);
+        // keep the scheduler from moving the decode and sums of the own node between the
+        // loads (it would then wait for them before the ring loads go out)
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (PACKED) {
+            finish_packed(own, pbuf, ps, cA, cB, cC);
+        } else if constexpr (LDS_POPS) {
+            C gg[QS], aa[QS], bb[QS], qq[QC];
+            decode_pops(own, gg, aa, bb, qq);
+#pragma unroll
+            for (int k = 0; k < QS; ++k) {
+                spop[pbuf][k][tid] = gg[k];
+                spop[pbuf][QS + k][tid] = aa[k];
+                spop[pbuf][2 * QS + k][tid] = bb[k];
+                if constexpr (NC3) spop[pbuf][3 * QS + k][tid] = qq[k];
+            }
+            pop_sums(gg, aa, bb, qq, ps, cA, cB, cC);
+        } else {
+            decode_pops(own, ng, na, nb, nq);
+            pop_sums(ng, na, nb, nq, ps, cA, cB, cC);
+        }
+        sphi[slot][ty + OY][tx + 1] = C(phi_from(ps, cA, cB, cC));
+        // the first lane of this wave holds a ring node (wave-uniform)
+        if (__builtin_amdgcn_readfirstlane(tid) < NH) {
+            C tg[QS], ta[QS], tb[QS], tq[QC];
+            double rps, rsa, rsb, rsc;
+            decode_pops(ring, tg, ta, tb, tq);
+            pop_sums(tg, ta, tb, tq, rps, rsa, rsb, rsc);
+            sphi[slot][hy][hx] = C(phi_from(rps, rsa, rsb, rsc));
+        }
     };
 
     auto fill_body = [&](int zm, bool zlo, bool zhi, int slot, int pbuf, double& ps, double& cA, double& cB,
                          double& cC) __attribute__((always_inline)) {
+        if constexpr (HAS_Y && LBM_FLAT_FILL) {
+            fill_body_flat(zm, zlo, zhi, slot, pbuf, ps, cA, cB, cC);
+            return;
+        }
         if (active) {
             if constexpr (PACKED) {
                 fill_packed(unsigned((zm * P.ny + y) * P.nx + x), neighbours(x, y, zm, P), zlo, zhi, pbuf, ps, cA, cB,
@@ -844,10 +940,26 @@ k_lbm(const KParams P) {
         const unsigned idx = unsigned((z * P.ny + y) * P.nx + x);
         const Nbr nbr = neighbours(x, y, z, P);
         C fpop[QF > 0 ? QF : 1];
+        // 16-bit storage: the moving f arrive as raw bits and are decoded where the flow
+        // moments need them, so that no wait for them sits before the plane fill's loads
+        constexpr bool FRAW = LBM_FRAW && (PREC == P16 || PREC == PB16);
+        unsigned fraw[(QF > 0 && FRAW) ? QF : 1];
         auto load_f_body = [&](bool zlo, bool zhi) __attribute__((always_inline)) {
             static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
                 constexpr int k = decltype(kc)::value, o = FL::opp(k);
-                if (zbounce<FL::ez(k)>(zlo, zhi)) {
+                if constexpr (FRAW && k != 0) {
+                    constexpr bool NT = LBM_NT_FLUID && SL::DIM == 3 && FL::ex(k) == 0;
+                    const char* base;
+                    unsigned t;
+                    if (zbounce<FL::ez(k)>(zlo, zhi)) {
+                        base = src(IC<o>{});
+                        t = idx;
+                    } else {
+                        base = src(kc);
+                        t = unsigned(int(idx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(nbr));
+                    }
+                    fraw[k] = ld_raw<unsigned short, NT>(reinterpret_cast<const unsigned short*>(base + t * 2u));
+                } else if (zbounce<FL::ez(k)>(zlo, zhi)) {
                     fpop[k] = load_once(IC<o>{}, IC<o>{}, FLT{}, idx);
                 } else {
                     const unsigned src_idx = unsigned(int(idx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(nbr));
@@ -855,9 +967,37 @@ k_lbm(const KParams P) {
                 }
             });
         };
+        // 16-bit storage: z-wall bounce-back by selecting the source slot and node (no
+        // branch: the loads stay in one basic block with the plane fill's)
+        auto load_f_sel = [&]() __attribute__((always_inline)) {
+            const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
+            // lanes outside the domain load an in-range node (their values are not used)
+            const int fx = min(x, P.nx - 1), fy = min(y, P.ny - 1);
+            const unsigned fidx = unsigned((z * P.ny + fy) * P.nx + fx);
+            const Nbr fnb = neighbours(fx, fy, z, P);
+            static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
+                constexpr int k = decltype(kc)::value, o = FL::opp(k);
+                if constexpr (k != 0) {
+                    constexpr bool NT = LBM_NT_FLUID && SL::DIM == 3 && FL::ex(k) == 0;
+                    const unsigned pulled = unsigned(int(fidx) + pull_offset<FL::ex(k), FL::ey(k), FL::ez(k)>(fnb));
+                    const char* base = src(kc);
+                    unsigned t = pulled;
+                    if constexpr (FL::ez(k) != 0) {
+                        const bool b = zbounce<FL::ez(k)>(zlo, zhi);
+                        base = b ? src(IC<o>{}) : base;
+                        t = b ? fidx : pulled;
+                    }
+                    fraw[k] = ld_raw<unsigned short, NT>(reinterpret_cast<const unsigned short*>(base + t * 2u));
+                } else {
+                    fpop[0] = load_once(kc, kc, FLT{}, fidx);
+                }
+            });
+        };
         auto load_f = [&]() __attribute__((always_inline)) {
             if constexpr (FLOW) {
-                if (active) {
+                if constexpr (FRAW && HAS_Y && LBM_FLAT_FILL) {
+                    load_f_sel();  // every lane loads (lanes outside the domain: in-range stand-ins)
+                } else if (active) {
                     const bool zlo = P.wall_z && z == 0, zhi = P.wall_z && z == P.nz - 1;
                     if (zlo || zhi) load_f_body(zlo, zhi);
                     else load_f_body(false, false);
@@ -931,6 +1071,11 @@ k_lbm(const KParams P) {
                 F[0] = buoy * KC(P.gx, P.f32.gx) + bracket * grad[0];
                 F[1] = buoy * KC(P.gy, P.f32.gy) + bracket * grad[1];
                 F[2] = buoy * KC(P.gz, P.f32.gz) + bracket * grad[2];
+                if constexpr (FRAW) {
+                    static_for<1, QF>([&](auto kc) __attribute__((always_inline)) {
+                        fpop[decltype(kc)::value] = dec_lo<PREC>(fraw[decltype(kc)::value], wref_dec(kc, kc, FLT{}), P.finv[0]);
+                    });
+                }
                 // Eqs. HydroPressure and Velocity
                 C j0 = C(0), j1 = C(0), j2 = C(0);
                 static_for<0, QF>([&](auto kc) __attribute__((always_inline)) {
