@@ -266,7 +266,9 @@ int lbm_set_state(lbm_handle* h, const void* src, void* stream);
 
 /* One step from the checkpoint `src` into the checkpoint `dst` (both laid out
  * as lbm_save writes them; lbm_checkpoint_bytes each), without touching the
- * handle's own copies.  When phi_src is not NULL it receives phi of `src`
+ * handle's own copies.  It writes the populations and the buffered <phi> of
+ * `dst`; the padding bytes of `dst` keep what they held (zero for a buffer that
+ * lbm_save wrote).  When phi_src is not NULL it receives phi of `src`
  * (Eq. Moment0_Phi, [node], FP64 for LBM_FP64 storage, FP32 otherwise), the
  * field the step's stencil used.  Used to recompute states for the adjoint. */
 int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, void* stream);

@@ -738,8 +738,7 @@ int lbm_step_external(lbm_handle* h, const void* src, void* dst, void* phi_src, 
         if (walls[a]) h->ks->walls(kp, a, s);
     if (h->cfg.gravity_mean_subtract)
         launch_finalize(h->aux + kAuxHead, int(h->L.nparts), 1, -1, 1.0 / double(h->L.nodes), ref_out, s);
-    if (int r = launched("step_external kernels")) return r;
-    return zero_tail(h, dst, s);
+    return launched("step_external kernels");
 }
 
 int lbm_phase_field(lbm_handle* h, const void* state, void* phi, void* stream) {
