@@ -253,7 +253,7 @@ def cpu_baseline(name, budget_s=10.0, max_workers=16):
             "single_thread": {"value": round(single, 3), "unit": "MLUPS", "cores": 1, "steps": n},
             "sample": f"64^3 crop of the {crop} recipe, D3Q19 + 3xD3Q7, FP64 numpy oracle; "
                       f"1 thread: {n} steps in {el:.1f} s; all cores: {workers} processes, one crop each, "
-                      f"{total / 64 ** 3:.0f} node-steps in {wall:.1f} s; host {_cpu_model()}, "
+                      f"{total / 64 ** 3:.0f} crop-steps in {wall:.1f} s; host {_cpu_model()}, "
                       f"{cores} logical CPUs available"}
 
 
