@@ -382,6 +382,9 @@ def main():
     ap.add_argument("--series-every", type=int, default=500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale HBM counters")
+    ap.add_argument("--box", type=int, nargs=3, default=None, metavar=("NX", "NY", "NZ"),
+                    help="only time the sedimentation recipe (walls in z) on an NX x NY x NZ box")
+    ap.add_argument("--box-precision", default="fp32", choices=["fp64", "fp32", "bf16", "fp16"])
     args = ap.parse_args()
 
     if args.calibrate_copy:
@@ -403,7 +406,7 @@ def main():
 
     # the oracle's timing forks a process per core: it runs before the GPU is touched
     cpu = None
-    if not (args.no_cpu_baseline or args.series or args.adjoint_only):
+    if not (args.no_cpu_baseline or args.series or args.adjoint_only or args.box):
         print("[bench] timing the CPU oracle (one thread, then all cores)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.workload)
 
@@ -424,6 +427,19 @@ def main():
             print(f"[bench] adjoint timing at {n}^2", file=sys.stderr, flush=True)
             res[str(n)] = adjoint_timing(n=n, steps=args.adjoint_steps, kind=args.adjoint_kind)
         print(json.dumps({"adjoint": res}), flush=True)
+        return
+
+    if args.box:
+        from paper_2409_03401_amd import inputs
+        nx, ny, nz = args.box
+        print(f"[bench] sedimentation box {nx} x {ny} x {nz}, {args.box_precision}", file=sys.stderr, flush=True)
+        # droplet count scaled with the volume (64 in 256^3)
+        w = inputs.sediment_3d(n=nx, ny=ny, nz=nz, precision=args.box_precision,
+                               ndrops=max(4, nx * ny * nz // 262144))
+        cfg, wall, kernel_ms, diag, _ = time_gpu(w, args.steps, args.warmup)
+        print(json.dumps({"box": [nx, ny, nz], "precision": args.box_precision,
+                          "MLUPS": round(cfg.nodes / (kernel_ms * 1e-3) / 1e6, 1), "kernel_ms": round(kernel_ms, 4),
+                          "bytes_per_update": bytes_per_update(cfg), "nan_count": diag["nan_count"]}), flush=True)
         return
 
     print(f"[bench] building workload {args.workload}", file=sys.stderr, flush=True)
