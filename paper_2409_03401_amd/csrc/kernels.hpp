@@ -449,8 +449,18 @@ constexpr int basis_order() { return kBasis<L>.order[I]; }
 template <class L, int I>
 constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBasis<L>.order[I - 1] != 2); }
 
+// occupancy floor of the fused kernel: one wave per SIMD (the compiler may use every
+// register), except for the D3Q19 scalar lattices with 16-bit storage and BGK (the
+// paper's 3D discretisation): with the packed LDS ring they need 260 registers, and two
+// waves per SIMD (256, a few bytes of spill) run the 256^3 box 10 % (BF16) and 6 % (FP16)
+// faster than one; without the ring, or in FP32 / FP64, two waves gain nothing or spill
+template <class SL, int PREC, int COLL>
+constexpr int lbm_waves() {
+    return (PREC == P16 || PREC == PB16) && SL::Q == 19 && COLL == COLL_BGK ? 2 : LBM_WAVES_PER_EU;
+}
+
 template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK, int NC = 2>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(lbm_waves<SL, PREC, COLL>())))
 k_lbm(const KParams P) {
     using C = typename Stor<PREC>::C;
     using SLOTS = Slots<FL::Q, SL::Q, NC>;
@@ -477,9 +487,13 @@ k_lbm(const KParams P) {
     constexpr bool VD = FLOW && (COLL & COLL_VD) != 0;
     constexpr bool GK = (COLL & COLL_GK) != 0;
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
-    // the private LDS ring of scalar populations, unless it would not leave room for
-    // a second work-group per compute unit (the paper's D3Q19 scalar lattice)
-    constexpr bool LDS_POPS = LBM_LDS_POPS && 2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024;
+    // the private LDS ring of scalar populations, unless it would not leave room for a
+    // second work-group per compute unit (the paper's D3Q19 scalar lattice in FP32 / FP64,
+    // and with the TRT, MRT, variable-density and general-curvature collisions).  The
+    // D3Q19 BGK kernels with 16-bit storage take the packed ring (30 words per node and
+    // plane, 61 KB) and two waves per SIMD (see lbm_waves)
+    constexpr bool LDS_POPS = LBM_LDS_POPS && (lbm_waves<SL, PREC, COLL>() == 2 ||
+                                               2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024);
     static_assert((QS - 1) % 2 == 0, "moving directions come in opposite pairs");
 
     __shared__ C sphi[NSLOT][LY][LX];

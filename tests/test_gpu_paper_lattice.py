@@ -113,7 +113,7 @@ def test_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["2d_flow_walls", "3d_flow_walls", "2d_paper_initial_condition"])
+@pytest.mark.parametrize("name", ["2d_flow_walls", "3d_flow_walls", "3d_noflow_walls", "2d_paper_initial_condition"])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_parity_16bit(name, prec):
     """16-bit storage of the moving populations (FP32 rest populations and arithmetic)
