@@ -50,6 +50,9 @@ def case(name):
     if name == "3d_bgk_walls":
         p = inputs._base(21, 19, 20, W=4.0, bc=("periodic", "periodic", "walls"), **vd3)
         return (p, *_drops((20, 19, 21), 1, 4.0, 5.0, 4.0, 63, (2,)), 12)
+    if name == "3d_bgk_d3q19":
+        p = inputs._base(19, 18, 20, W=4.0, scalar="D3Q19", bc=("periodic", "walls", "walls"), **vd3)
+        return (p, *_drops((20, 18, 19), 1, 4.0, 5.0, 4.0, 65, (1, 2)), 10)
     if name == "3d_trt_d3q19":
         p = inputs._base(18, 20, 19, W=4.0, scalar="D3Q19", bc=("walls", "periodic", "walls"), collision="TRT",
                          trt_magic=(3.0 / 16.0, 0.25), **vd3)
@@ -57,7 +60,7 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["2d_bgk_walls", "2d_trt_d2q9", "3d_bgk_walls", "3d_trt_d3q19"]
+CASES = ["2d_bgk_walls", "2d_trt_d2q9", "3d_bgk_walls", "3d_bgk_d3q19", "3d_trt_d3q19"]
 
 
 @functools.lru_cache(maxsize=None)
@@ -105,7 +108,7 @@ def test_vd_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["2d_bgk_walls", "3d_bgk_walls", "3d_trt_d3q19"])
+@pytest.mark.parametrize("name", ["2d_bgk_walls", "3d_bgk_walls", "3d_bgk_d3q19", "3d_trt_d3q19"])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_vd_parity_16bit(name, prec):
     """16-bit storage (FP32 rest populations and arithmetic): c^A, c^B within 1e-3
