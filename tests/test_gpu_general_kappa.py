@@ -55,10 +55,14 @@ def case(name):
     if name == "3d_flow_walls":
         p = inputs._base(21, 18, 20, W=4.0, bc=("periodic", "periodic", "walls"), kappa=KAPPA, **flow3)
         return (p, *_drops((20, 18, 21), 1, 4.0, 5.0, 4.0, 74, (2,)), 12)
+    if name == "3d_d3q19_scalars":
+        p = inputs._base(19, 20, 18, W=4.0, scalar="D3Q19", bc=("walls", "periodic", "periodic"), kappa=KAPPA,
+                         **flow3)
+        return (p, *_drops((18, 20, 19), 1, 4.0, 5.0, 4.0, 75, (0,)), 10)
     raise KeyError(name)
 
 
-CASES = ["2d_noflow", "2d_flow_walls", "2d_d2q9_scalars", "3d_flow_walls"]
+CASES = ["2d_noflow", "2d_flow_walls", "2d_d2q9_scalars", "3d_flow_walls", "3d_d3q19_scalars"]
 
 
 @functools.lru_cache(maxsize=None)
@@ -104,7 +108,7 @@ def test_gk_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["2d_flow_walls", "3d_flow_walls"])
+@pytest.mark.parametrize("name", ["2d_flow_walls", "3d_flow_walls", "3d_d3q19_scalars"])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_gk_parity_16bit(name, prec):
     """16-bit storage (FP32 rest populations and arithmetic): c^A, c^B within 1e-3
