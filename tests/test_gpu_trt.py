@@ -58,10 +58,13 @@ def case(name):
         p = inputs._base(18, 17, 19, W=4.0, fluid="D3Q19", scalar="D3Q19", bc=("walls", "periodic", "periodic"),
                          **flow3, **mob, **TRT)
         return (p, *_drops((19, 17, 18), 1, 4.0, 5.0, 4.0, 54, (0,)), 10)
+    if name == "3d_d3q19_noflow":
+        p = inputs._base(20, 19, 17, W=3.0, scalar="D3Q19", bc=("periodic", "periodic", "walls"), **mob, **TRT)
+        return (p, *_drops((17, 19, 20), 2, 3.0, 5.0, 3.0, 55, (2,)), 12)
     raise KeyError(name)
 
 
-CASES = ["2d_d2q5_flow_walls", "2d_d2q9_noflow", "3d_d3q7_flow_walls", "3d_d3q19_flow"]
+CASES = ["2d_d2q5_flow_walls", "2d_d2q9_noflow", "3d_d3q7_flow_walls", "3d_d3q19_flow", "3d_d3q19_noflow"]
 
 
 @functools.lru_cache(maxsize=None)
@@ -104,7 +107,7 @@ def test_trt_parity_fp32(name):
     assert rel_l2(pops, ora_p) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["2d_d2q5_flow_walls", "3d_d3q7_flow_walls", "3d_d3q19_flow"])
+@pytest.mark.parametrize("name", ["2d_d2q5_flow_walls", "3d_d3q7_flow_walls", "3d_d3q19_flow", "3d_d3q19_noflow"])
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_trt_parity_16bit(name, prec):
     """16-bit storage (FP32 rest populations and arithmetic): c^A, c^B within 1e-3
