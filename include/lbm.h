@@ -189,8 +189,8 @@ typedef struct lbm_handle lbm_handle;
  * writes the other, because each work-group recomputes phi on a one-node ring
  * from populations its neighbours are updating in the same launch; in place,
  * those reads would race with the neighbours' writes unless phi took a pass of
- * its own.  The cost is memory: about 2 x the stored population bytes per node
- * (2 x 176 B with D3Q19 + 3 x D3Q7 and 16-bit storage, 23.8 GB for 512^3).
+ * its own.  The cost is memory: twice the stored population bytes per node
+ * (2 x 88 B with D3Q19 + 3 x D3Q7 and 16-bit storage, 23.8 GB for 512^3).
  * Tuning only: the environment variables LBM_TILE ("64x4" or "32x8" in 3D; "64x1",
  * "128x1" or "256x1" in 2D) and LBM_ZC (planes per work-group) override the launch
  * geometry the library chooses.  They are read whenever a configuration is checked,
