@@ -451,14 +451,16 @@ constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBas
 
 // occupancy floor of the fused kernel: one wave per SIMD (the compiler may use every
 // register), except for the D3Q19 scalar lattices with 16-bit storage (the paper's 3D
-// discretisation) and the BGK, TRT or variable-density collisions: with the packed LDS
-// ring they need about 260 registers, and two waves per SIMD (256, at most 28 bytes of
-// spill) run the 256^3 box 6-15 % faster than one.  Measured slower with two waves: the
-// MRT (FP16) and general-curvature kernels, and every kernel in FP32 / FP64
+// discretisation) and the BGK, TRT or variable-density collisions, or MRT with BF16: with
+// the packed LDS ring they need about 260 registers, and two waves per SIMD (256, at
+// most 64 bytes of spill) run the 256^3 box 6-15 % faster than one.  Measured slower
+// with two waves: MRT with FP16, the general-curvature kernels, and every kernel in
+// FP32 / FP64
 template <class SL, int PREC, int COLL>
 constexpr int lbm_waves() {
-    return (PREC == P16 || PREC == PB16) && SL::Q == 19 && (COLL & (COLL_MRT | COLL_GK)) == 0 ? 2
-                                                                                             : LBM_WAVES_PER_EU;
+    constexpr bool s16 = PREC == P16 || PREC == PB16;
+    constexpr bool coll = (COLL & COLL_GK) == 0 && ((COLL & COLL_MRT) == 0 || PREC == PB16);
+    return s16 && SL::Q == 19 && coll ? 2 : LBM_WAVES_PER_EU;
 }
 
 template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK, int NC = 2>
@@ -491,9 +493,9 @@ k_lbm(const KParams P) {
     static_assert(TY == 1 || HAS_Y, "2D problems use one row per work-group");
     // the private LDS ring of scalar populations, unless it would not leave room for a
     // second work-group per compute unit (the paper's D3Q19 scalar lattice in FP32 / FP64,
-    // and with the MRT and general-curvature collisions).  The other D3Q19 kernels with
-    // 16-bit storage take the packed ring (30 words per node and plane, 61 KB) and two
-    // waves per SIMD (lbm_waves)
+    // and with the general-curvature collision or MRT with FP16).  The other D3Q19
+    // kernels with 16-bit storage take the packed ring (30 words per node and plane,
+    // 61 KB) and two waves per SIMD (lbm_waves)
     constexpr bool LDS_POPS = LBM_LDS_POPS && (lbm_waves<SL, PREC, COLL>() == 2 ||
                                                2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024);
     static_assert((QS - 1) % 2 == 0, "moving directions come in opposite pairs");
