@@ -450,21 +450,26 @@ template <class L, int I>
 constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBasis<L>.order[I - 1] != 2); }
 
 // occupancy floor of the fused kernel: one wave per SIMD (the compiler may use every
-// register), except for the D3Q19 scalar lattices with 16-bit storage (the paper's 3D
-// discretisation) and the BGK, TRT or variable-density collisions, or MRT with BF16: with
-// the packed LDS ring they need about 260 registers, and two waves per SIMD (256, at
-// most 64 bytes of spill) run the 256^3 box 6-15 % faster than one.  Measured slower
-// with two waves: MRT with FP16, the general-curvature kernels, and every kernel in
-// FP32 / FP64
-template <class SL, int PREC, int COLL>
+// register), except where a higher floor measured faster at 256^3:
+// - the D3Q19 scalar lattices with 16-bit storage (the paper's 3D discretisation) and
+//   the BGK, TRT or variable-density collisions, or MRT with BF16: with the packed LDS
+//   ring they need about 260 registers; two waves per SIMD (256, at most 64 bytes of
+//   spill) are 6-15 % faster than one;
+// - a third composition on D3Q7 with BF16 storage: 175 registers; three waves (168,
+//   16 bytes of spill) are 8 % faster than two.
+// Measured slower with the higher floor: MRT and the third composition with FP16, the
+// general-curvature kernels, and every kernel in FP32 / FP64
+template <class SL, int PREC, int COLL, int NC = 2>
 constexpr int lbm_waves() {
     constexpr bool s16 = PREC == P16 || PREC == PB16;
     constexpr bool coll = (COLL & COLL_GK) == 0 && ((COLL & COLL_MRT) == 0 || PREC == PB16);
-    return s16 && SL::Q == 19 && coll ? 2 : LBM_WAVES_PER_EU;
+    if constexpr (s16 && SL::Q == 19 && coll) return 2;
+    if constexpr (PREC == PB16 && SL::Q == 7 && NC == 3) return 3;
+    return LBM_WAVES_PER_EU;
 }
 
 template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK, int NC = 2>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(lbm_waves<SL, PREC, COLL>())))
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(lbm_waves<SL, PREC, COLL, NC>())))
 k_lbm(const KParams P) {
     using C = typename Stor<PREC>::C;
     using SLOTS = Slots<FL::Q, SL::Q, NC>;
@@ -496,7 +501,7 @@ k_lbm(const KParams P) {
     // and with the general-curvature collision or MRT with FP16).  The other D3Q19
     // kernels with 16-bit storage take the packed ring (30 words per node and plane,
     // 61 KB) and two waves per SIMD (lbm_waves)
-    constexpr bool LDS_POPS = LBM_LDS_POPS && (lbm_waves<SL, PREC, COLL>() == 2 ||
+    constexpr bool LDS_POPS = LBM_LDS_POPS && (lbm_waves<SL, PREC, COLL, NC>() == 2 ||
                                                2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024);
     static_assert((QS - 1) % 2 == 0, "moving directions come in opposite pairs");
 
