@@ -455,15 +455,20 @@ constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBas
 //   the BGK, TRT or variable-density collisions, or MRT with BF16: with the packed LDS
 //   ring they need about 260 registers; two waves per SIMD (256, at most 64 bytes of
 //   spill) are 6-15 % faster than one;
-// - a third composition on D3Q7 with BF16 storage: 175 registers; three waves (168,
-//   16 bytes of spill) are 8 % faster than two.
-// Measured slower with the higher floor: MRT and the third composition with FP16, the
-// general-curvature kernels, and every kernel in FP32 / FP64
+// - D3Q7 with 16-bit storage, whose 3D launch puts three work-groups on a compute unit:
+//   where the kernel needs more than 168 registers only two fit, and the 768 work-groups
+//   of the 256^3 box run as one and a half rounds.  Three waves per SIMD (168 registers,
+//   8-20 bytes of spill): general curvatures +27 % (BF16) and +8 % (FP16); a third
+//   composition with BF16 (175 registers) +8 %.
+// Measured slower with the higher floor: MRT on D3Q7 (-16 %, 200 registers) and on D3Q19
+// with FP16, the third composition with FP16, the general-curvature D3Q19 kernels, and
+// every kernel in FP32 / FP64
 template <class SL, int PREC, int COLL, int NC = 2>
 constexpr int lbm_waves() {
     constexpr bool s16 = PREC == P16 || PREC == PB16;
     constexpr bool coll = (COLL & COLL_GK) == 0 && ((COLL & COLL_MRT) == 0 || PREC == PB16);
     if constexpr (s16 && SL::Q == 19 && coll) return 2;
+    if constexpr (s16 && SL::Q == 7 && (COLL & COLL_GK) != 0) return 3;
     if constexpr (PREC == PB16 && SL::Q == 7 && NC == 3) return 3;
     return LBM_WAVES_PER_EU;
 }
