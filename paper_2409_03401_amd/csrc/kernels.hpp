@@ -460,21 +460,32 @@ constexpr bool basis_trace() { return kBasis<L>.order[I] == 2 && (I == 0 || kBas
 //   of the 256^3 box run as one and a half rounds.  Three waves per SIMD (168 registers,
 //   8-20 bytes of spill): general curvatures +27 % (BF16) and +8 % (FP16); a third
 //   composition with BF16 (175 registers) +8 %.
+// - 2D with 16-bit storage and flow, kernels of 129-146 registers (three waves): four
+//   waves per SIMD measured at 2048^2 +9-13 % with a third composition, +13-14 % for the
+//   variable-density model on D2Q9 scalars, +14 % for the paper's D2Q9 lattices with
+//   FP16, +8 % for MRT on D2Q5 with BF16.
 // Measured slower with the higher floor: MRT on D3Q7 (-16 %, 200 registers) and on D3Q19
-// with FP16, the third composition with FP16, the general-curvature D3Q19 kernels, and
-// every kernel in FP32 / FP64
-template <class SL, int PREC, int COLL, int NC = 2>
+// with FP16, the third composition on D3Q7 with FP16, the general-curvature D3Q19 and
+// D2Q9 (FP16) kernels, the variable-density model on D2Q5 (BF16), and every kernel in
+// FP32 / FP64
+template <class SL, int PREC, int COLL, int NC = 2, int QF = 0>
 constexpr int lbm_waves() {
     constexpr bool s16 = PREC == P16 || PREC == PB16;
     constexpr bool coll = (COLL & COLL_GK) == 0 && ((COLL & COLL_MRT) == 0 || PREC == PB16);
     if constexpr (s16 && SL::Q == 19 && coll) return 2;
     if constexpr (s16 && SL::Q == 7 && (COLL & COLL_GK) != 0) return 3;
     if constexpr (PREC == PB16 && SL::Q == 7 && NC == 3) return 3;
+    if constexpr (s16 && SL::DIM == 2 && QF > 0) {
+        if constexpr (NC == 3) return 4;
+        if constexpr (SL::Q == 9 && COLL == COLL_VD) return 4;
+        if constexpr (SL::Q == 9 && COLL == COLL_BGK && PREC == P16) return 4;
+        if constexpr (SL::Q == 5 && COLL == COLL_MRT && PREC == PB16) return 4;
+    }
     return LBM_WAVES_PER_EU;
 }
 
 template <class SL, class FL, int MODE, int PREC, int TX, int TY, int COLL = COLL_BGK, int NC = 2>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(lbm_waves<SL, PREC, COLL, NC>())))
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(lbm_waves<SL, PREC, COLL, NC, FL::Q>())))
 k_lbm(const KParams P) {
     using C = typename Stor<PREC>::C;
     using SLOTS = Slots<FL::Q, SL::Q, NC>;
@@ -506,7 +517,7 @@ k_lbm(const KParams P) {
     // and with the general-curvature collision or MRT with FP16).  The other D3Q19
     // kernels with 16-bit storage take the packed ring (30 words per node and plane,
     // 61 KB) and two waves per SIMD (lbm_waves)
-    constexpr bool LDS_POPS = LBM_LDS_POPS && (lbm_waves<SL, PREC, COLL, NC>() == 2 ||
+    constexpr bool LDS_POPS = LBM_LDS_POPS && (lbm_waves<SL, PREC, COLL, NC, FL::Q>() == 2 ||
                                                2 * (1 + NC) * QS * NT * sizeof(C) <= 96 * 1024);
     static_assert((QS - 1) % 2 == 0, "moving directions come in opposite pairs");
 
